@@ -1,0 +1,169 @@
+"""FP64 CPU oracle for non-gridding MEM imaging (Carcamo et al.).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library.  The heavy sums
+live in uvmem_oracle.c (plain direct sums, FP64, compensated); this module
+marshals numpy arrays and composes the objective of Eq. phi2/phi3:
+
+    Phi(I) = chi^2(I) + lambda * S(I),
+    chi^2  = 1/2 sum_k w_k |V^m_k(I) - V^o_k|^2,          (Eq. phi2)
+    S      = sum_p I_p ln(I_p / M),                        (regulariser; its
+             gradient ln(I/M) + 1 is Eq. Sgradient)
+    grad Phi = A o Re F^H (w o R) + lambda (ln(I/M) + 1)   (Eq. chi2gradient,
+             with the beam factor of the exact derivative).
+
+Readings where the paper is ambiguous are listed in the design doc; the ones this
+file depends on: the 1/2 in chi^2 (Eq. phi2), S written with M in place of G
+and without the 1/G prefactor (so that Eq. Sgradient is its exact gradient),
+the sign Phi = chi^2 + lambda S (the paper's S carries the opposite sign), and
+the beam factor A_ij kept in the chi^2 gradient.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "uvmem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (-O2, IEEE semantics, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_beam.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        L.or_forward.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp, dp, dp]
+        L.or_forward_sel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, i64p,
+                                     dp, dp, dp, dp, dp]
+        L.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp, dp,
+                                 ctypes.c_int64, i64p, dp]
+        L.or_chi2.argtypes = [ctypes.c_int64, dp, dp, dp, dp]
+        L.or_chi2.restype = ctypes.c_double
+        L.or_entropy.argtypes = [ctypes.c_int64, dp, ctypes.c_double, dp]
+        L.or_entropy.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cplx(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def beam(n: int, cell: float, fwhm: float) -> np.ndarray:
+    """A_ij = exp(-4 ln 2 (x_j^2 + y_i^2) / FWHM^2) (Sec. 2.4, item 1)."""
+    A = np.empty((n, n))
+    lib().or_beam(n, cell, fwhm, _d(A))
+    return A
+
+
+def forward(n: int, cell: float, u, v, A: Optional[np.ndarray], I) -> np.ndarray:
+    """V^m_k = sum_ij A_ij I_ij exp(-2 pi i (u_k x_j + v_k y_i)) (Eq. fft)."""
+    u, v, I = _f64(u), _f64(v), _f64(I)
+    assert I.shape == (n, n)
+    Ak = None if A is None else _f64(A)
+    V = np.empty(u.shape[0], dtype=np.complex128)
+    lib().or_forward(n, cell, u.shape[0], _d(u), _d(v), _d(Ak) if Ak is not None else None,
+                     _d(I), _d(V.view(np.float64)))
+    return V
+
+
+def forward_sel(n: int, cell: float, idx, u, v, A, I) -> np.ndarray:
+    """Forward model at the listed visibility indices only."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    u, v, I = _f64(u), _f64(v), _f64(I)
+    Ak = None if A is None else _f64(A)
+    V = np.empty(idx.shape[0], dtype=np.complex128)
+    lib().or_forward_sel(n, cell, idx.shape[0], idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         _d(u), _d(v), _d(Ak) if Ak is not None else None, _d(I),
+                         _d(V.view(np.float64)))
+    return V
+
+
+def adjoint(n: int, cell: float, u, v, A: Optional[np.ndarray], c, pix=None) -> np.ndarray:
+    """G_ij = A_ij sum_k Re(c_k exp(+2 pi i (u_k x_j + v_k y_i))).
+
+    With c = w * R this is the chi^2 gradient (Eq. chi2gradient, Alg. 3).
+    `pix` (optional) lists linear pixel indices N*i + j to evaluate."""
+    u, v = _f64(u), _f64(v)
+    c = _cplx(c)
+    Ak = None if A is None else _f64(A)
+    if pix is None:
+        G = np.empty((n, n))
+        lib().or_adjoint(n, cell, u.shape[0], _d(u), _d(v), _d(Ak) if Ak is not None else None,
+                         _d(c.view(np.float64)), -1, None, _d(G))
+        return G
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    G = np.empty(pix.shape[0])
+    lib().or_adjoint(n, cell, u.shape[0], _d(u), _d(v), _d(Ak) if Ak is not None else None,
+                     _d(c.view(np.float64)), pix.shape[0],
+                     pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(G))
+    return G
+
+
+def chi2(V, Vo, w):
+    """chi^2 = 1/2 sum_k w_k |V_k - Vo_k|^2 (Eq. phi2); returns (chi2, R)."""
+    V, Vo = _cplx(V), _cplx(Vo)
+    w = _f64(w)
+    R = np.empty_like(V)
+    x = lib().or_chi2(V.shape[0], _d(V.view(np.float64)), _d(Vo.view(np.float64)), _d(w),
+                      _d(R.view(np.float64)))
+    return float(x), R
+
+
+def entropy(I, M: float):
+    """S = sum I ln(I/M), grad = ln(I/M) + 1 (Eq. Sgradient).  S is NaN if
+    any pixel is <= 0."""
+    I = _f64(I)
+    g = np.empty_like(I)
+    s = lib().or_entropy(I.size, _d(I), M, _d(g))
+    return float(s), g
+
+
+def phi_grad(n, cell, u, v, A, I, Vo, w, M, lam):
+    """Phi = chi^2 + lambda S and its gradient for one channel (Eq. phi2/phi3,
+    Eq. Sgradient, Eq. chi2gradient)."""
+    V = forward(n, cell, u, v, A, I)
+    x2, R = chi2(V, Vo, w)
+    S, gS = entropy(I, M)
+    gchi = adjoint(n, cell, u, v, A, _f64(w) * R)
+    grad = gchi + lam * gS
+    return dict(phi=x2 + lam * S, chi2=x2, S=S, grad=grad, gchi2=gchi, V=V, R=R)

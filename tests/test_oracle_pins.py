@@ -1,0 +1,336 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed forms,
+a library FFT, invariants of the Fourier transform, brute-force finite
+differences, a textbook linear CG, and a library bound-constrained minimiser.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import oracle
+from oracle import cg as ocg
+from paper_1703_02920_amd import synth
+
+N = 32
+CELL = 1.0e-6
+
+
+def _uv(nvis, seed, fill=0.45):
+    u, v, _, _ = synth.random_problem(N, nvis, seed, cell=CELL, fill=fill)
+    return u, v
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+# ---------------------------------------------------------------- forward model
+
+def test_point_source_at_phase_centre_is_constant():
+    """A point of flux F at pixel (N/2, N/2) sits at (0,0) where A = 1, so every
+    visibility equals F exactly (Eq. fft with x = y = 0)."""
+    u, v = _uv(500, 1)
+    A = oracle.beam(N, CELL, 10 * CELL)
+    img = np.zeros((N, N))
+    img[N // 2, N // 2] = 2.5
+    V = oracle.forward(N, CELL, u, v, A, img)
+    assert A[N // 2, N // 2] == 1.0
+    assert np.max(np.abs(V - 2.5)) < 1e-13
+
+
+def test_point_source_off_centre_phase_and_orientation():
+    """Point at row i0 (y) and column j0 (x): V = F A e^{-2 pi i (u x + v y)}.
+    Checks the sign of the exponent and that rows are y and columns x."""
+    u, v = _uv(300, 2)
+    A = oracle.beam(N, CELL, 12 * CELL)
+    i0, j0 = 5, 23
+    img = np.zeros((N, N))
+    img[i0, j0] = 1.7
+    V = oracle.forward(N, CELL, u, v, A, img)
+    x, y = (j0 - N // 2) * CELL, (i0 - N // 2) * CELL
+    expect = 1.7 * A[i0, j0] * np.exp(-2j * np.pi * (u * x + v * y))
+    assert np.max(np.abs(V - expect)) < 1e-12
+
+
+def test_grid_aligned_uv_matches_numpy_fft2():
+    """On grid-aligned uv, u = p/(N dx), v = q/(N dx), the direct sum is a DFT:
+    V = (-1)^{p+q} fft2(A o I)[q mod N, p mod N]."""
+    rng = np.random.default_rng(3)
+    p = rng.integers(-N // 2, N // 2, size=400)
+    q = rng.integers(-N // 2, N // 2, size=400)
+    u = p / (N * CELL)
+    v = q / (N * CELL)
+    A = oracle.beam(N, CELL, 20 * CELL)
+    img = rng.uniform(0, 1, size=(N, N))
+    V = oracle.forward(N, CELL, u, v, A, img)
+    Fk = np.fft.fft2(A * img)
+    expect = ((-1.0) ** (p + q)) * Fk[q % N, p % N]
+    assert rel(V, expect) < 1e-13
+
+
+def test_gaussian_blob_closed_form():
+    """Centred Gaussian I = F dx^2/(2 pi s^2) e^{-r^2/2s^2} through a Gaussian
+    beam: V(u, v) = F (s_e^2/s^2) e^{-2 pi^2 s_e^2 |u|^2}, 1/s_e^2 = 1/s^2 + 1/s_A^2.
+    Alias error <= F e^{-2 pi^2 s_e^2 (1/dx - |u|)^2} (~1e-17 here)."""
+    n = 64
+    s = 3.0 * CELL
+    fwhm = 20.0 * CELL
+    sA = fwhm / math.sqrt(8 * math.log(2))
+    F = 3.0
+    c = (np.arange(n) - n // 2) * CELL
+    r2 = c[None, :] ** 2 + c[:, None] ** 2
+    img = F * CELL ** 2 / (2 * math.pi * s * s) * np.exp(-r2 / (2 * s * s))
+    A = oracle.beam(n, CELL, fwhm)
+    u, v, _, _ = synth.random_problem(n, 400, 4, cell=CELL, fill=0.5)
+    V = oracle.forward(n, CELL, u, v, A, img)
+    se2 = 1.0 / (1.0 / s ** 2 + 1.0 / sA ** 2)
+    expect = F * se2 / s ** 2 * np.exp(-2 * math.pi ** 2 * se2 * (u * u + v * v))
+    assert np.max(np.abs(V - expect)) < 1e-12 * F
+
+
+def test_hermitian_symmetry_and_linearity():
+    u, v = _uv(200, 5)
+    A = oracle.beam(N, CELL, 15 * CELL)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 1, (N, N))
+    y = rng.uniform(-1, 1, (N, N))
+    Vp = oracle.forward(N, CELL, u, v, A, x)
+    Vm = oracle.forward(N, CELL, -u, -v, A, x)
+    assert np.max(np.abs(Vm - np.conj(Vp))) < 1e-12 * np.max(np.abs(Vp))
+    Vy = oracle.forward(N, CELL, u, v, A, y)
+    Vs = oracle.forward(N, CELL, u, v, A, 2.0 * x - 0.5 * y)
+    assert rel(Vs, 2.0 * Vp - 0.5 * Vy) < 1e-13
+
+
+def test_shift_theorem():
+    """Moving the image one pixel along +x multiplies V by e^{-2 pi i u dx}
+    (no beam, so the forward model is shift-covariant)."""
+    u, v = _uv(200, 6)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(0, 1, (N, N))
+    x[:, -1] = 0.0
+    xs = np.zeros_like(x)
+    xs[:, 1:] = x[:, :-1]
+    V = oracle.forward(N, CELL, u, v, None, x)
+    Vs = oracle.forward(N, CELL, u, v, None, xs)
+    assert rel(Vs, V * np.exp(-2j * np.pi * u * CELL)) < 1e-13
+
+
+def test_forward_sel_matches_full():
+    u, v = _uv(300, 7)
+    A = oracle.beam(N, CELL, 15 * CELL)
+    x = np.random.default_rng(7).uniform(0, 1, (N, N))
+    V = oracle.forward(N, CELL, u, v, A, x)
+    idx = np.array([0, 5, 17, 299, 123])
+    assert np.array_equal(oracle.forward_sel(N, CELL, idx, u, v, A, x), V[idx])
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_adjoint_dot_test():
+    """sum_k Re(conj(c_k) F(x)_k) = sum_p x_p [F^H c]_p for real x, complex c."""
+    u, v = _uv(500, 8)
+    A = oracle.beam(N, CELL, 15 * CELL)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((N, N))
+    c = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    lhs = float(np.sum((np.conj(c) * oracle.forward(N, CELL, u, v, A, x)).real))
+    rhs = float(np.sum(x * oracle.adjoint(N, CELL, u, v, A, c)))
+    assert abs(lhs - rhs) < 1e-11 * (abs(lhs) + 1.0)
+
+
+def test_adjoint_grid_aligned_matches_numpy_ifft2():
+    """Grid-aligned uv: F^H c = A o Re(N^2 ifft2(C)) with C[q, p] += (-1)^{p+q} c."""
+    rng = np.random.default_rng(9)
+    p = rng.integers(-N // 2, N // 2, size=300)
+    q = rng.integers(-N // 2, N // 2, size=300)
+    u, v = p / (N * CELL), q / (N * CELL)
+    A = oracle.beam(N, CELL, 20 * CELL)
+    c = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    G = oracle.adjoint(N, CELL, u, v, A, c)
+    C = np.zeros((N, N), complex)
+    np.add.at(C, (q % N, p % N), ((-1.0) ** (p + q)) * c)
+    expect = A * (N * N * np.fft.ifft2(C)).real
+    assert rel(G, expect) < 1e-12
+
+
+def test_adjoint_pixel_subset():
+    u, v = _uv(100, 10)
+    A = oracle.beam(N, CELL, 15 * CELL)
+    c = np.random.default_rng(10).standard_normal(100) + 0j
+    G = oracle.adjoint(N, CELL, u, v, A, c)
+    pix = np.array([0, 33, 1023, 512])
+    assert np.array_equal(oracle.adjoint(N, CELL, u, v, A, c, pix=pix), G.ravel()[pix])
+
+
+# ---------------------------------------------------------------- objective pieces
+
+def test_entropy_closed_forms():
+    M = 1e-3
+    S, g = oracle.entropy(np.full((8, 8), M), M)
+    assert S == 0.0 and np.all(g == 1.0)
+    S, g = oracle.entropy(np.full((8, 8), math.e * M), M)
+    assert abs(S - 64 * math.e * M) < 1e-15 and np.allclose(g, 2.0, rtol=0, atol=1e-15)
+    bad = np.full((4, 4), M)
+    bad[1, 2] = 0.0
+    assert math.isnan(oracle.entropy(bad, M)[0])
+
+
+def test_chi2_point_source_data_at_zero_image():
+    """Data of a unit-flux point at the phase centre (V^o = F for all k) and
+    the empty image give chi^2 = F^2 sum(w) / 2 exactly."""
+    w = np.random.default_rng(11).uniform(0.5, 2, 300)
+    F = 1.5
+    x2, R = oracle.chi2(np.zeros(300, complex), np.full(300, F + 0j), w)
+    assert abs(x2 - 0.5 * F * F * np.sum(w)) < 1e-12 * x2
+
+
+def test_dirty_image_is_minus_gradient_at_zero():
+    """grad chi^2 at I = 0 equals minus the (unnormalised) natural-weight dirty
+    image A o sum_k w_k Re(V^o_k e^{+2 pi i U.X}) (App. A, Eq. dirty); for
+    point-source data it is -F A o PSF with PSF = sum_k w_k cos(2 pi U.X)."""
+    u, v = _uv(400, 12)
+    A = oracle.beam(N, CELL, 15 * CELL)
+    w = np.random.default_rng(12).uniform(0.5, 2, 400)
+    F = 0.8
+    out = oracle.phi_grad(N, CELL, u, v, A, np.full((N, N), 1e-300), np.full(400, F + 0j), w,
+                          M=1.0, lam=0.0)
+    c = (np.arange(N) - N // 2) * CELL
+    psf = np.zeros((N, N))
+    for k in range(400):
+        psf += w[k] * np.cos(2 * np.pi * (u[k] * c[None, :] + v[k] * c[:, None]))
+    assert rel(out["gchi2"], -F * A * psf) < 1e-9
+
+
+def _phi(n, cell, u, v, A, img, Vo, w, M, lam):
+    return oracle.phi_grad(n, cell, u, v, A, img, Vo, w, M, lam)["phi"]
+
+
+def test_gradient_matches_central_differences_8x8():
+    """Brute-force central differences of Phi at every pixel of an 8x8 image
+    (relative step 1e-4) reproduce the analytic gradient, including the beam
+    factor of the chi^2 term and the entropy gradient."""
+    n, cell = 8, 4.0e-6
+    u, v, vis, w = synth.random_problem(n, 60, 13, cell=cell)
+    A = oracle.beam(n, cell, 5 * cell)
+    img = synth.random_image(n, 13, lo=0.05, hi=1.0)[0]
+    M, lam = 1e-2, 0.3
+    out = oracle.phi_grad(n, cell, u, v, A, img, vis, w, M, lam)
+    fd = np.zeros((n, n))
+    for p in range(n * n):
+        i, j = divmod(p, n)
+        h = 1e-4 * img[i, j]
+        a = img.copy(); a[i, j] += h
+        b = img.copy(); b[i, j] -= h
+        fd[i, j] = (_phi(n, cell, u, v, A, a, vis, w, M, lam) - _phi(n, cell, u, v, A, b, vis, w, M, lam)) / (2 * h)
+    assert rel(out["grad"], fd) < 1e-7
+
+
+def test_gradient_without_beam_factor_would_fail_fd():
+    """The A_ij factor is required: dropping it (App. C's approximation) is
+    detectably wrong against finite differences on a narrow beam."""
+    n, cell = 8, 4.0e-6
+    u, v, vis, w = synth.random_problem(n, 60, 14, cell=cell)
+    A = oracle.beam(n, cell, 3 * cell)
+    img = synth.random_image(n, 14, lo=0.05, hi=1.0)[0]
+    out = oracle.phi_grad(n, cell, u, v, A, img, vis, w, 1e-2, 0.0)
+    g_noA = oracle.adjoint(n, cell, u, v, None, w * out["R"])
+    i, j = 1, 6
+    h = 1e-4
+    a = img.copy(); a[i, j] += h
+    b = img.copy(); b[i, j] -= h
+    fd = (_phi(n, cell, u, v, A, a, vis, w, 1e-2, 0.0) - _phi(n, cell, u, v, A, b, vis, w, 1e-2, 0.0)) / (2 * h)
+    assert abs(out["grad"][i, j] - fd) < 1e-6 * abs(fd)
+    assert abs(g_noA[i, j] - fd) > 1e-2 * abs(fd)
+
+
+# ---------------------------------------------------------------- CG
+
+def _small_problem(seed, n=8, nvis=80, M=1e-2, lam=0.1, noiseless_from=None):
+    cell = 4.0e-6
+    u, v, vis, w = synth.random_problem(n, nvis, seed, cell=cell)
+    A = oracle.beam(n, cell, 6 * cell)
+    if noiseless_from is not None:
+        vis = oracle.forward(n, cell, u, v, A, noiseless_from)
+    return ocg.Problem(n, cell, u, v, vis, w, A, M, lam)
+
+
+def test_line_search_is_exact_minimiser():
+    """Step 7 returns the minimiser of phi on [0, alpha_max]: compare with a
+    library bounded scalar minimiser on the same phi."""
+    rng = np.random.default_rng(15)
+    I = rng.uniform(0.01, 1.0, 64)
+    d = rng.standard_normal(64)
+    M, lam, a, b = 1e-3, 0.2, 3.0, -2.0
+    neg = d < 0
+    amax = float(np.min((I[neg] - M) / (-d[neg])))
+
+    def phi(al):
+        x = I + al * d
+        return b * al + 0.5 * a * al * al + lam * float(np.sum(x * np.log(x / M)))
+
+    al, _ = ocg.line_search(a, b, I, d, M, lam, amax)
+    ref = scipy.optimize.minimize_scalar(phi, bounds=(0.0, amax), method="bounded",
+                                         options=dict(xatol=1e-12))
+    assert abs(al - ref.x) < 1e-7 * amax
+    assert phi(al) <= ref.fun + 1e-12
+
+
+def test_cg_lambda0_unconstrained_equals_textbook_linear_cg():
+    """lambda = 0, iterates strictly inside the bound: projected PR CG with an
+    exact line search is linear CG (Hestenes-Stiefel) on the normal equations
+    Re(F^H W F) I = Re(F^H W V^o), started from the same point."""
+    n = 8
+    truth = 0.5 + 0.5 * synth.random_image(n, 16, lo=0.0, hi=1.0)[0]
+    prob = _small_problem(16, n=n, nvis=120, M=1e-9, lam=0.0, noiseless_from=truth)
+    I0 = np.full((n, n), 0.7)
+    # explicit normal matrix, one column per unit image
+    H = np.zeros((n * n, n * n))
+    for p in range(n * n):
+        e = np.zeros((n, n)); e.flat[p] = 1.0
+        H[:, p] = prob.FH(prob.w * prob.F(e)).ravel()
+    rhs = prob.FH(prob.w * prob.vis).ravel()
+    x = I0.ravel().copy()
+    r = rhs - H @ x
+    dd = r.copy()
+    iters = 6
+    xs = []
+    for _ in range(iters):
+        Hd = H @ dd
+        al = (r @ r) / (dd @ Hd)
+        x = x + al * dd
+        rn = r - al * Hd
+        dd = rn + (rn @ rn) / (r @ r) * dd
+        r = rn
+        xs.append(x.copy())
+    I, traj = ocg.projected_cg(prob, iters, I0=I0)
+    assert len(traj) == iters
+    assert all(t["alpha"] < t["alpha_max"] for t in traj)
+    assert rel(I.ravel(), xs[-1]) < 1e-8
+
+
+def test_cg_invariants_and_convergence_to_bound_constrained_minimum():
+    """Phi non-increasing, I >= M, beta >= 0; after many iterations the
+    objective equals the minimum found by L-BFGS-B with the bound I >= M."""
+    n = 8
+    prob = _small_problem(17, n=n, nvis=100, M=1e-2, lam=0.05)
+    I, traj = ocg.projected_cg(prob, 300)
+    phis = [t["phi"] for t in traj]
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(phis, phis[1:]))
+    assert np.all(I >= prob.M)
+    assert all(t["beta"] >= 0 for t in traj)
+
+    def fun(x):
+        ev = prob.evaluate(x.reshape(n, n))
+        return ev["phi"], ev["g"].ravel()
+
+    ref = scipy.optimize.minimize(fun, np.full(n * n, 0.1), jac=True, method="L-BFGS-B",
+                                  bounds=[(prob.M, None)] * (n * n),
+                                  options=dict(maxiter=5000, ftol=1e-15, gtol=1e-12))
+    phi_cg = prob.evaluate(I)["phi"]
+    assert phi_cg <= ref.fun + 1e-8 * abs(ref.fun)
+    assert abs(phi_cg - ref.fun) < 1e-7 * abs(ref.fun)
+    assert np.max(np.abs(I - ref.x.reshape(n, n))) < 1e-3 * np.max(I)
