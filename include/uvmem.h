@@ -1,0 +1,174 @@
+/*
+ * uvmem.h -- C ABI of the MI355X (gfx950) non-gridding maximum-entropy
+ * imaging hot path (Carcamo et al., "Multi-GPU maximum entropy image
+ * synthesis for radio astronomy").
+ *
+ * What it computes (paper Sec. 2.2-2.5):
+ *   V^m_k   = sum_{i,j} A_ij I_ij exp(-2 pi i (u_k x_j + v_k y_i))  (Eq. fft,
+ *             discretised exactly at the measured, ungridded (u_k, v_k))
+ *   R_k     = V^m_k - V^o_k                                       (Alg. 2)
+ *   chi^2   = 1/2 sum_k w_k |R_k|^2, w_k = 1/sigma_k^2             (Eq. phi2)
+ *   S       = sum_p I_p ln(I_p / M)        (regulariser; Eq. Sgradient is its
+ *                                           gradient ln(I/M) + 1)
+ *   Phi     = chi^2 + lambda S                                     (Eq. phi3)
+ *   grad chi^2_ij = A_ij sum_k Re(w_k R_k exp(+2 pi i (u_k x_j + v_k y_i)))
+ *                                            (Eq. chi2gradient, Alg. 3; the
+ *                                            A_ij factor is the exact derivative)
+ *   grad Phi = grad chi^2 + lambda (ln(I/M) + 1)
+ * and a positively-constrained projected conjugate-gradient step minimising
+ * Phi over I >= M (Eq. minproblem; M plays the role of the paper's G).
+ *
+ * Geometry: image side N (even), pixel (i, j) at x_j = (j - N/2) cell,
+ * y_i = (i - N/2) cell (Alg. 3 with the phase centre at pixel (N/2, N/2));
+ * linear pixel index N*i + j (row i <-> y).  u, v in wavelengths, cell in
+ * radians.  Channels are independent problems (cube mode): each has its own
+ * image, visibilities, weights and primary beam; Eq. chi2-multi is the sum
+ * of the per-channel chi^2 reported alongside.
+ *
+ * Conventions for every entry point:
+ *  - Return value: UVMEM_OK (0) or a negative uvmem_status.  On error the
+ *    context keeps a message readable with uvmem_last_error(); no C++
+ *    exception crosses the ABI.  A context is used by one host thread at a
+ *    time.
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller owns them.  set_* calls accept host or device pointers and copy
+ *    the data into buffers the context owns (the caller may free its copy).
+ *  - Image-like arrays are [n_chan][N][N] row-major, element type double for
+ *    UVMEM_FP64 and float for every other precision.  Visibility arrays are
+ *    the concatenation of the channels in channel order.
+ *  - Hot entry points (phi_and_grad, forward, adjoint, cg_step, cg_run) only
+ *    enqueue work on the context's stream and never synchronise; the
+ *    results are valid once that stream has reached them.  They allocate
+ *    nothing: uvmem_finalize allocates every buffer.
+ */
+#ifndef UVMEM_H
+#define UVMEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct uvmem_ctx uvmem_ctx;
+
+typedef enum uvmem_status {
+    UVMEM_OK = 0,
+    UVMEM_EINVAL = -1,   /* bad argument (null pointer, size, index)          */
+    UVMEM_ENOMEM = -2,   /* device or host allocation failed                  */
+    UVMEM_EDEVICE = -3,  /* a HIP runtime call failed                         */
+    UVMEM_EDOMAIN = -4,  /* an image pixel was <= 0 or NaN (from uvmem_check) */
+    UVMEM_ESTATE = -5    /* call out of order (e.g. set_* after finalize)     */
+} uvmem_status;
+
+/* Precision of the DFT contractions (the chi^2, entropy and line-search sums
+ * are FP64 in every mode, and so are the model visibilities and residuals). */
+typedef enum uvmem_precision {
+    UVMEM_FP64 = 0,      /* FP64 operands, FP64 matrix cores                  */
+    UVMEM_FP32 = 1,      /* FP32 operands on FP32 matrix cores                */
+    UVMEM_BF16X3 = 2,    /* bf16 hi+lo split, three products, FP32 accumulate */
+    UVMEM_FP16X3 = 3     /* fp16 hi+lo split (power-of-two scaled), three products */
+} uvmem_precision;
+
+typedef enum uvmem_mode {
+    UVMEM_CUBE = 0       /* one image per channel, channels independent       */
+} uvmem_mode;
+
+/* Per-channel scalar slots, FP64, layout [n_chan][UVMEM_NSCAL]. */
+enum {
+    UVMEM_S_PHI = 0,     /* Phi = chi^2 + lambda S                            */
+    UVMEM_S_CHI2 = 1,    /* chi^2                                             */
+    UVMEM_S_S = 2,       /* S                                                 */
+    UVMEM_S_ALPHA = 3,   /* CG step length of the last step                   */
+    UVMEM_S_BETA = 4,    /* Polak-Ribiere beta of the last step               */
+    UVMEM_S_GNORM2 = 5,  /* squared norm of the projected gradient            */
+    UVMEM_S_ALPHA_MAX = 6, /* largest feasible step of the last line search   */
+    UVMEM_S_ITER = 7,    /* CG iterations taken so far (stops count)          */
+    UVMEM_NSCAL = 8
+};
+
+/* Create a context for images of side n (even, 2..8192) and n_chan >= 1
+ * channels.  hip_stream is a hipStream_t (NULL = the null stream) on the
+ * current device; all work is enqueued there. */
+int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, void *hip_stream);
+int uvmem_destroy(uvmem_ctx *ctx);
+
+/* Visibility coordinates of channel `chan` (Sec. 2.1): nvis >= 0 points,
+ * u, v in wavelengths (double[nvis]).  cell_rad is the pixel size Delta x in
+ * radians and must be the same for every channel (one pixel grid).  nvis = 0
+ * is legal: the channel then contributes chi^2 = 0 and grad chi^2 = 0. */
+int uvmem_set_uv(uvmem_ctx *ctx, int chan, int64_t nvis, const double *u, const double *v,
+                 double cell_rad);
+/* Observed visibilities V^o of the channel: float[nvis][2] (re, im). */
+int uvmem_set_vis(uvmem_ctx *ctx, int chan, const float *vis);
+/* Weights w_k = 1/sigma_k^2 >= 0 of the channel: float[nvis]; 0 = flagged. */
+int uvmem_set_weights(uvmem_ctx *ctx, int chan, const float *w);
+/* Gaussian primary beam of the given FWHM (radians), centred on the phase
+ * centre (Sec. 2.4 item 1): A_ij = exp(-4 ln2 (x_j^2 + y_i^2) / fwhm^2). */
+int uvmem_set_beam(uvmem_ctx *ctx, int chan, double fwhm_rad);
+/* General attenuation image A for the channel: float[N][N]. */
+int uvmem_set_beam_image(uvmem_ctx *ctx, int chan, const float *A);
+/* Image floor M > 0 (the paper's G, Eq. minproblem) and entropy weight
+ * lambda >= 0 (Eq. phi2). */
+int uvmem_set_prior(uvmem_ctx *ctx, double M, double lambda);
+/* Validate, upload, build the work tables and allocate every buffer.  After
+ * it, set_* return UVMEM_ESTATE and the hot entry points allocate nothing. */
+int uvmem_finalize(uvmem_ctx *ctx);
+
+/* One evaluation of Phi and grad Phi at I_dev ([n_chan][N][N]).  grad_dev
+ * receives grad Phi ([n_chan][N][N]); scal_dev (may be NULL) receives Phi,
+ * chi^2 and S per channel in slots UVMEM_S_PHI..UVMEM_S_S of
+ * double[n_chan][UVMEM_NSCAL].  The residuals R are kept in the context. */
+int uvmem_phi_and_grad(uvmem_ctx *ctx, const void *I_dev, void *grad_dev, double *scal_dev);
+/* Model visibilities V^m = F(I) (Eq. fft): vis_dev is double[sum Z][2]. */
+int uvmem_forward(uvmem_ctx *ctx, const void *I_dev, void *vis_dev);
+/* Adjoint A o Re F^H c of complex coefficients c (double[sum Z][2], e.g. the
+ * weighted residual w R): img_dev is [n_chan][N][N]. */
+int uvmem_adjoint(uvmem_ctx *ctx, const void *coef_dev, void *img_dev);
+/* Copy the current residuals R = V^m - V^o (double[sum Z][2]) to res_dev. */
+int uvmem_get_residual(uvmem_ctx *ctx, void *res_dev);
+
+/* Projected CG (positively constrained, Sec. 2.6).  cg_init evaluates Phi at
+ * I_dev (first setting I_dev to M everywhere if init_to_floor) and sets the
+ * first direction.  cg_step performs one iteration in place on I_dev (which
+ * must be the same buffer as in cg_init) and writes the per-channel scalars
+ * (all UVMEM_NSCAL slots) to scal_dev (may be NULL).  A channel whose line
+ * search stalls (no descent, or zero projected gradient) stops: later steps
+ * leave it unchanged.  cg_run performs `iters` steps, writing scalars to
+ * scal_hist_dev (double[iters][n_chan][UVMEM_NSCAL], may be NULL); with
+ * use_graph != 0 it replays one step captured as a HIP graph. */
+int uvmem_cg_init(uvmem_ctx *ctx, void *I_dev, int init_to_floor);
+int uvmem_cg_step(uvmem_ctx *ctx, void *I_dev, double *scal_dev);
+int uvmem_cg_run(uvmem_ctx *ctx, void *I_dev, int iters, double *scal_hist_dev, int use_graph);
+/* Checkpoint of the CG state (direction, projected gradients, residuals,
+ * scalars, iteration count) to/from host memory.  With host_blob == NULL,
+ * get_state only reports the size in *bytes.  Both synchronise the stream. */
+int uvmem_cg_get_state(uvmem_ctx *ctx, void *host_blob, size_t *bytes);
+int uvmem_cg_set_state(uvmem_ctx *ctx, const void *host_blob, size_t bytes);
+
+/* Synchronise the stream; return UVMEM_EDOMAIN if any evaluated image had a
+ * pixel <= 0 or NaN since the last check (and clear the flag), else the
+ * first asynchronous HIP error, else UVMEM_OK. */
+int uvmem_check(uvmem_ctx *ctx);
+
+/* Kernel timing (benchmarking): when enabled, the forward and adjoint
+ * launches of every hot call are bracketed by HIP events on the context's
+ * stream.  which = 0 forward, 1 adjoint; total_ms and count accumulate over
+ * completed launches (reading synchronises the stream); reset clears them. */
+int uvmem_timing_enable(uvmem_ctx *ctx, int enable);
+int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *count, int reset);
+
+/* Introspection: padded side, channel offsets into the visibility arrays,
+ * split-K depth chosen for the adjoint. */
+int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);
+int uvmem_chan_range(const uvmem_ctx *ctx, int chan, int64_t *offset, int64_t *nvis);
+
+const char *uvmem_last_error(const uvmem_ctx *ctx);
+const char *uvmem_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UVMEM_H */

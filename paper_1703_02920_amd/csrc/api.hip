@@ -1,0 +1,675 @@
+// Host side of the uvmem C ABI: argument checking, staging of the inputs,
+// layout and work tables, device allocation, and the hot entry points, which
+// only enqueue kernels on the context's stream.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace uvm;
+
+namespace {
+
+int fail(uvmem_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(uvmem_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((c), UVMEM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+size_t real_size(const uvmem_ctx *c) { return c->prec == UVMEM_FP64 ? sizeof(double) : sizeof(float); }
+
+bool valid_chan(uvmem_ctx *c, int chan) { return chan >= 0 && chan < c->nchan; }
+
+// Copy n bytes from a host or device pointer into host memory.
+hipError_t fetch(void *dst, const void *src, size_t n) {
+    if (n == 0) return hipSuccess;
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, src);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        std::memcpy(dst, src, n);
+        return hipSuccess;
+    }
+    if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged)
+        return hipMemcpy(dst, src, n, hipMemcpyDeviceToHost);
+    std::memcpy(dst, src, n);
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e == hipSuccess) {
+        c->bytes_device += bytes;
+        e = hipMemset(*p, 0, bytes);
+    }
+    return e;
+}
+
+void free_all(uvmem_ctx *c) {
+    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwd, c->d_adj, c->d_vis,
+                    c->d_slot_base, c->d_vis_base, c->d_R, c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
+                    c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
+                    c->d_flag, c->d_hist_ptr, c->d_iter_ctr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto &pr : c->pend[0]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    for (auto &pr : c->pend[1]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ev_pool.clear();
+}
+
+// ---------------------------------------------------------------- timing
+void harvest(uvmem_ctx *c) {
+    for (int w = 0; w < 2; ++w) {
+        for (auto &pr : c->pend[w]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                c->t_ms[w] += ms;
+                c->t_cnt[w] += 1;
+            }
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        c->pend[w].clear();
+    }
+}
+
+// Launch the forward (which = 0) or adjoint (which = 1) DFT, bracketed by
+// events when timing is on.
+hipError_t timed_dft(uvmem_ctx *c, int which, const void *bop, const double2 *coef, const float *w) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_pool.size() < 2) {
+            (void)hipStreamSynchronize(c->stream);
+            harvest(c);
+        }
+        if (c->ev_pool.size() >= 2) {
+            e0 = c->ev_pool.back(); c->ev_pool.pop_back();
+            e1 = c->ev_pool.back(); c->ev_pool.pop_back();
+            (void)hipEventRecord(e0, c->stream);
+        }
+    }
+    hipError_t e = which == 0 ? launch_forward(c, bop, c->stream) : launch_adjoint(c, coef, w, c->stream);
+    if (e0) {
+        (void)hipEventRecord(e1, c->stream);
+        c->pend[which].push_back({e0, e1});
+    }
+    return e;
+}
+
+int check_ready(uvmem_ctx *c) {
+    if (!c) return UVMEM_EINVAL;
+    if (!c->finalized) return fail(c, UVMEM_ESTATE, "context is not finalized");
+    return UVMEM_OK;
+}
+
+int build_layout(uvmem_ctx *c) {
+    const int C = c->nchan;
+    c->np = ((c->n + 63) / 64) * 64;
+    c->ib_rows = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    c->n_ib = c->np / c->ib_rows;
+    c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    c->adj_nt = c->np / c->adj_tt;
+    c->n_pb = (int)(((int64_t)c->n * c->n + PIX_BLK - 1) / PIX_BLK);
+    c->off.assign(C + 1, 0);
+    for (int ch = 0; ch < C; ++ch) c->off[ch + 1] = c->off[ch] + c->nvis[ch];
+    c->ztot = c->off[C];
+    return UVMEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *uvmem_strerror(int code) {
+    switch (code) {
+    case UVMEM_OK: return "ok";
+    case UVMEM_EINVAL: return "invalid argument";
+    case UVMEM_ENOMEM: return "out of memory";
+    case UVMEM_EDEVICE: return "HIP runtime error";
+    case UVMEM_EDOMAIN: return "image pixel <= 0 or NaN";
+    case UVMEM_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char *uvmem_last_error(const uvmem_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, void *hip_stream) {
+    if (!out) return UVMEM_EINVAL;
+    *out = nullptr;
+    if (n < 2 || n > 8192 || (n % 2) != 0) return UVMEM_EINVAL;
+    if (n_chan < 1 || n_chan > 65536) return UVMEM_EINVAL;
+    if (mode != UVMEM_CUBE) return UVMEM_EINVAL;
+    if (precision != UVMEM_FP64 && precision != UVMEM_FP32) return UVMEM_EINVAL;
+    uvmem_ctx *c = new (std::nothrow) uvmem_ctx();
+    if (!c) return UVMEM_ENOMEM;
+    c->n = n;
+    c->nchan = n_chan;
+    c->mode = mode;
+    c->prec = precision;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return UVMEM_EDEVICE;
+    }
+    c->nvis.assign(n_chan, 0);
+    c->hu.resize(n_chan);
+    c->hv.resize(n_chan);
+    c->hvis.resize(n_chan);
+    c->hw.resize(n_chan);
+    c->hbeam.resize(n_chan);
+    c->fwhm.assign(n_chan, 0.0);
+    c->has_uv.assign(n_chan, 0);
+    c->has_vis.assign(n_chan, 0);
+    c->has_w.assign(n_chan, 0);
+    c->has_beam.assign(n_chan, 0);
+    *out = c;
+    return UVMEM_OK;
+}
+
+int uvmem_destroy(uvmem_ctx *ctx) {
+    if (!ctx) return UVMEM_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->finalized) (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return UVMEM_OK;
+}
+
+int uvmem_set_uv(uvmem_ctx *c, int chan, int64_t nvis, const double *u, const double *v, double cell_rad) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_uv after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
+    if (nvis < 0 || nvis > (int64_t)1 << 40) return fail(c, UVMEM_EINVAL, "bad nvis");
+    if (nvis > 0 && (!u || !v)) return fail(c, UVMEM_EINVAL, "null u/v");
+    if (!(cell_rad > 0.0) || !std::isfinite(cell_rad)) return fail(c, UVMEM_EINVAL, "bad cell");
+    if (c->cell_set && cell_rad != c->cell)
+        return fail(c, UVMEM_EINVAL, "cell differs between channels (one pixel grid)");
+    c->cell = cell_rad;
+    c->cell_set = true;
+    c->nvis[chan] = nvis;
+    try {
+        c->hu[chan].resize(nvis);
+        c->hv[chan].resize(nvis);
+    } catch (...) {
+        return fail(c, UVMEM_ENOMEM, "host staging");
+    }
+    HIPCHK(c, fetch(c->hu[chan].data(), u, nvis * sizeof(double)));
+    HIPCHK(c, fetch(c->hv[chan].data(), v, nvis * sizeof(double)));
+    for (int64_t k = 0; k < nvis; ++k)
+        if (!std::isfinite(c->hu[chan][k]) || !std::isfinite(c->hv[chan][k]))
+            return fail(c, UVMEM_EINVAL, "non-finite u/v at %lld", (long long)k);
+    c->has_uv[chan] = 1;
+    c->has_vis[chan] = nvis == 0;
+    c->has_w[chan] = nvis == 0;
+    return UVMEM_OK;
+}
+
+int uvmem_set_vis(uvmem_ctx *c, int chan, const float *vis) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_vis after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
+    if (!c->has_uv[chan]) return fail(c, UVMEM_ESTATE, "set_vis before set_uv");
+    const int64_t nv = c->nvis[chan];
+    if (nv > 0 && !vis) return fail(c, UVMEM_EINVAL, "null vis");
+    try { c->hvis[chan].resize(2 * nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(c->hvis[chan].data(), vis, 2 * nv * sizeof(float)));
+    c->has_vis[chan] = 1;
+    return UVMEM_OK;
+}
+
+int uvmem_set_weights(uvmem_ctx *c, int chan, const float *w) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_weights after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
+    if (!c->has_uv[chan]) return fail(c, UVMEM_ESTATE, "set_weights before set_uv");
+    const int64_t nv = c->nvis[chan];
+    if (nv > 0 && !w) return fail(c, UVMEM_EINVAL, "null weights");
+    try { c->hw[chan].resize(nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(c->hw[chan].data(), w, nv * sizeof(float)));
+    for (int64_t k = 0; k < nv; ++k)
+        if (!(c->hw[chan][k] >= 0.0f) || !std::isfinite(c->hw[chan][k]))
+            return fail(c, UVMEM_EINVAL, "weight %lld is negative or not finite", (long long)k);
+    c->has_w[chan] = 1;
+    return UVMEM_OK;
+}
+
+int uvmem_set_beam(uvmem_ctx *c, int chan, double fwhm_rad) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_beam after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
+    if (!(fwhm_rad > 0.0) || !std::isfinite(fwhm_rad)) return fail(c, UVMEM_EINVAL, "bad fwhm");
+    c->fwhm[chan] = fwhm_rad;
+    c->hbeam[chan].clear();
+    c->has_beam[chan] = 1;
+    return UVMEM_OK;
+}
+
+int uvmem_set_beam_image(uvmem_ctx *c, int chan, const float *A) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_beam_image after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
+    if (!A) return fail(c, UVMEM_EINVAL, "null beam image");
+    const size_t npix = (size_t)c->n * c->n;
+    try { c->hbeam[chan].resize(npix); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(c->hbeam[chan].data(), A, npix * sizeof(float)));
+    for (size_t p = 0; p < npix; ++p)
+        if (!std::isfinite(c->hbeam[chan][p])) return fail(c, UVMEM_EINVAL, "non-finite beam value");
+    c->fwhm[chan] = 0.0;
+    c->has_beam[chan] = 1;
+    return UVMEM_OK;
+}
+
+int uvmem_set_prior(uvmem_ctx *c, double M, double lambda) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_prior after finalize");
+    if (!(M > 0.0) || !std::isfinite(M)) return fail(c, UVMEM_EINVAL, "M must be > 0");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(c, UVMEM_EINVAL, "lambda must be >= 0");
+    c->M = M;
+    c->lam = lambda;
+    c->prior_set = true;
+    return UVMEM_OK;
+}
+
+int uvmem_finalize(uvmem_ctx *c) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "finalize called twice");
+    const int C = c->nchan;
+    for (int ch = 0; ch < C; ++ch) {
+        if (!c->has_uv[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no uv", ch);
+        if (!c->has_vis[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no visibilities", ch);
+        if (!c->has_w[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no weights", ch);
+        if (!c->has_beam[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no beam", ch);
+    }
+    if (!c->prior_set) return fail(c, UVMEM_ESTATE, "prior not set");
+    HIPCHK(c, hipSetDevice(c->device));
+    build_layout(c);
+    const int n = c->n, np = c->np;
+    const size_t npix = (size_t)n * n;
+    const size_t rs = real_size(c);
+
+    // ---- work tables
+    std::vector<FwdItem> fwd;
+    std::vector<VisItem> vis;
+    std::vector<AdjItem> adj;
+    c->h_slot_base.assign(C + 1, 0);
+    c->h_vis_base.assign(C + 1, 0);
+    const int tiles = c->adj_nt * c->adj_nt;
+    // split-K chunk length: enough workgroups to fill the GPU several times
+    // over, chunks of equal length across channels (uneven channels balance)
+    const int64_t target = 2048;
+    int64_t klen = (c->ztot * tiles + target - 1) / target;
+    klen = std::max<int64_t>(klen, ADJ_KMIN);
+    klen = ((klen + 15) / 16) * 16;
+    int slot = 0;
+    for (int ch = 0; ch < C; ++ch) {
+        const int64_t b = c->off[ch], e = c->off[ch + 1];
+        for (int64_t k = b; k < e; k += FWD_KV)
+            fwd.push_back(FwdItem{ch, (int)std::min<int64_t>(FWD_KV, e - k), (long long)k});
+        c->h_vis_base[ch] = (int)vis.size();
+        for (int64_t k = b; k < e; k += VIS_BLK)
+            vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + VIS_BLK, e)});
+        c->h_slot_base[ch] = slot;
+        for (int64_t k = b; k < e; k += klen, ++slot)
+            for (int ti = 0; ti < c->adj_nt; ++ti)
+                for (int tj = 0; tj < c->adj_nt; ++tj)
+                    adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k, (long long)std::min<int64_t>(k + klen, e)});
+    }
+    c->h_slot_base[C] = slot;
+    c->h_vis_base[C] = (int)vis.size();
+    c->n_slots = slot;
+    c->n_fwd = (int)fwd.size();
+    c->n_adj = (int)adj.size();
+    c->n_visit = (int)vis.size();
+
+    // ---- host-side conversions
+    std::vector<double> a(c->ztot), bb(c->ztot);
+    std::vector<float> vo(2 * c->ztot), w(c->ztot);
+    for (int ch = 0; ch < C; ++ch) {
+        const int64_t o = c->off[ch];
+        for (int64_t k = 0; k < c->nvis[ch]; ++k) {
+            a[o + k] = c->hu[ch][k] * c->cell;
+            bb[o + k] = c->hv[ch][k] * c->cell;
+            vo[2 * (o + k)] = c->hvis[ch][2 * k];
+            vo[2 * (o + k) + 1] = c->hvis[ch][2 * k + 1];
+            w[o + k] = c->hw[ch][k];
+        }
+    }
+    std::vector<char> beam(C * npix * rs);
+    for (int ch = 0; ch < C; ++ch) {
+        for (size_t p = 0; p < npix; ++p) {
+            double A;
+            if (!c->hbeam[ch].empty()) {
+                A = c->hbeam[ch][p];
+            } else {
+                const double x = (double)((int)(p % n) - n / 2) * c->cell;
+                const double y = (double)((int)(p / n) - n / 2) * c->cell;
+                A = std::exp(-4.0 * std::log(2.0) * (x * x + y * y) / (c->fwhm[ch] * c->fwhm[ch]));
+            }
+            if (rs == 8) reinterpret_cast<double *>(beam.data())[ch * npix + p] = A;
+            else reinterpret_cast<float *>(beam.data())[ch * npix + p] = (float)A;
+        }
+    }
+
+    // ---- device allocation
+    hipError_t e = hipSuccess;
+    auto ok = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    ok(dalloc(c, &c->d_a, c->ztot));
+    ok(dalloc(c, &c->d_b, c->ztot));
+    ok(dalloc(c, &c->d_vo, c->ztot));
+    ok(dalloc(c, &c->d_w, c->ztot));
+    ok(dalloc(c, (char **)&c->d_beam, C * npix * rs));
+    ok(dalloc(c, &c->d_fwd, fwd.size()));
+    ok(dalloc(c, &c->d_adj, adj.size()));
+    ok(dalloc(c, &c->d_vis, vis.size()));
+    ok(dalloc(c, &c->d_slot_base, C + 1));
+    ok(dalloc(c, &c->d_vis_base, C + 1));
+    ok(dalloc(c, &c->d_R, c->ztot));
+    ok(dalloc(c, &c->d_Vd, c->ztot));
+    ok(dalloc(c, &c->d_vpart, (size_t)c->n_ib * c->ztot));
+    ok(dalloc(c, &c->d_gpart, (size_t)c->n_slots * np * np));
+    ok(dalloc(c, (char **)&c->d_bop, (size_t)C * np * np * rs));
+    ok(dalloc(c, (char **)&c->d_g, C * npix * rs));
+    ok(dalloc(c, (char **)&c->d_gt, C * npix * rs));
+    ok(dalloc(c, (char **)&c->d_dir, C * npix * rs));
+    ok(dalloc(c, &c->d_scal, (size_t)C * UVMEM_NSCAL));
+    ok(dalloc(c, &c->d_chan, (size_t)C * CH_N));
+    ok(dalloc(c, &c->d_ls, (size_t)2 * C * LSS_N));
+    ok(dalloc(c, &c->d_ppart, (size_t)2 * C * c->n_pb * NPART));
+    ok(dalloc(c, &c->d_vispart, (size_t)std::max(c->n_visit, 1) * NPART));
+    ok(dalloc(c, &c->d_flag, 4));
+    ok(dalloc(c, &c->d_hist_ptr, 1));
+    ok(dalloc(c, &c->d_iter_ctr, 1));
+    if (e != hipSuccess) {
+        free_all(c);
+        c->d_a = nullptr;
+        (void)hipGetLastError();
+        return fail(c, e == hipErrorOutOfMemory ? UVMEM_ENOMEM : UVMEM_EDEVICE, "device allocation: %s",
+                    hipGetErrorString(e));
+    }
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes && e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up(c->d_a, a.data(), a.size() * 8);
+    up(c->d_b, bb.data(), bb.size() * 8);
+    up(c->d_vo, vo.data(), vo.size() * 4);
+    up(c->d_w, w.data(), w.size() * 4);
+    up(c->d_beam, beam.data(), beam.size());
+    up(c->d_fwd, fwd.data(), fwd.size() * sizeof(FwdItem));
+    up(c->d_adj, adj.data(), adj.size() * sizeof(AdjItem));
+    up(c->d_vis, vis.data(), vis.size() * sizeof(VisItem));
+    up(c->d_slot_base, c->h_slot_base.data(), (C + 1) * sizeof(int));
+    up(c->d_vis_base, c->h_vis_base.data(), (C + 1) * sizeof(int));
+    if (e != hipSuccess) return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
+    HIPCHK(c, hipDeviceSynchronize());
+    // release host staging
+    for (int ch = 0; ch < C; ++ch) {
+        std::vector<double>().swap(c->hu[ch]);
+        std::vector<double>().swap(c->hv[ch]);
+        std::vector<float>().swap(c->hvis[ch]);
+        std::vector<float>().swap(c->hw[ch]);
+        std::vector<float>().swap(c->hbeam[ch]);
+    }
+    c->finalized = true;
+    return UVMEM_OK;
+}
+
+int uvmem_phi_and_grad(uvmem_ctx *c, const void *I, void *grad, double *scal) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!I || !grad) return fail(c, UVMEM_EINVAL, "null image or gradient");
+    HIPCHK(c, launch_prologue(c, I, 1, c->stream));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, launch_vis_sum(c, 1, nullptr, c->stream));
+    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w));
+    HIPCHK(c, launch_grad(c, I, grad, 1, c->stream));
+    HIPCHK(c, launch_chan_phi(c, scal, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_forward(uvmem_ctx *c, const void *I, void *vis) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!I || (!vis && c->ztot)) return fail(c, UVMEM_EINVAL, "null image or output");
+    HIPCHK(c, launch_prologue(c, I, 0, c->stream));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, launch_vis_sum(c, 0, (double2 *)vis, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_adjoint(uvmem_ctx *c, const void *coef, void *img) {
+    int s = check_ready(c);
+    if (s) return s;
+    if ((!coef && c->ztot) || !img) return fail(c, UVMEM_EINVAL, "null coefficients or output");
+    HIPCHK(c, timed_dft(c, 1, nullptr, (const double2 *)coef, nullptr));
+    HIPCHK(c, launch_grad(c, nullptr, img, 0, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_get_residual(uvmem_ctx *c, void *res) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!res && c->ztot) return fail(c, UVMEM_EINVAL, "null output");
+    if (c->ztot)
+        HIPCHK(c, hipMemcpyAsync(res, c->d_R, c->ztot * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_cg_init(uvmem_ctx *c, void *I, int init_to_floor) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!I) return fail(c, UVMEM_EINVAL, "null image");
+    if (init_to_floor) HIPCHK(c, launch_fill(c, I, c->M, c->stream));
+    s = uvmem_phi_and_grad(c, I, c->d_g, nullptr);
+    if (s) return s;
+    HIPCHK(c, launch_cg_init_dir(c, I, c->stream));
+    c->cg_I = I;
+    c->cg_ready = true;
+    return UVMEM_OK;
+}
+
+int uvmem_cg_step(uvmem_ctx *c, void *I, double *scal) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_step before cg_init");
+    if (I != c->cg_I) return fail(c, UVMEM_EINVAL, "cg_step image differs from cg_init's");
+    HIPCHK(c, launch_cg_phase(c, I, scal, 0, c->stream));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, launch_cg_phase(c, I, scal, 1, c->stream));
+    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w));
+    HIPCHK(c, launch_cg_phase(c, I, scal, 2, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_run before cg_init");
+    if (I != c->cg_I) return fail(c, UVMEM_EINVAL, "cg_run image differs from cg_init's");
+    if (iters < 0) return fail(c, UVMEM_EINVAL, "negative iteration count");
+    const size_t stride = (size_t)c->nchan * UVMEM_NSCAL;
+    if (!use_graph) {
+        for (int t = 0; t < iters; ++t) {
+            s = uvmem_cg_step(c, I, hist ? hist + t * stride : nullptr);
+            if (s) return s;
+        }
+        return UVMEM_OK;
+    }
+    if (!c->graph_exec || c->graph_I != I) {
+        if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+        hipStream_t cap;
+        HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        // the capture stream must not start before work already queued on the
+        // context's stream: graph launches go to that stream, so ordering holds.
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = launch_cg_step(c, I, nullptr, cap);
+        if (e == hipSuccess) e = launch_copy_scal(c, nullptr, c->d_iter_ctr, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            c->graph_exec = nullptr;
+            return fail(c, UVMEM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+        c->graph = g;
+        c->graph_I = I;
+    }
+    // point the history copy at the caller's buffer and reset the counter
+    long long hp[2] = {(long long)(uintptr_t)hist, 0};
+    HIPCHK(c, hipMemcpyAsync(c->d_hist_ptr, &hp[0], sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_iter_ctr, &hp[1], sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    // the two copies read host stack memory: let them finish before returning
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int t = 0; t < iters; ++t) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    return UVMEM_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int32_t n, nchan, prec, pad;
+    int64_t ztot;
+};
+const uint64_t STATE_MAGIC = 0x31534d454d5655ull;  // "UVMEMS1"
+}  // namespace
+
+int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!bytes) return fail(c, UVMEM_EINVAL, "null size");
+    const size_t img = (size_t)c->nchan * c->n * c->n * real_size(c);
+    const size_t need = sizeof(StateHeader) + 3 * img + c->ztot * sizeof(double2) +
+                        (size_t)c->nchan * (UVMEM_NSCAL + CH_N) * sizeof(double);
+    if (!blob) { *bytes = need; return UVMEM_OK; }
+    if (*bytes < need) return fail(c, UVMEM_EINVAL, "state buffer too small (%zu < %zu)", *bytes, need);
+    if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "no CG state");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    char *p = (char *)blob;
+    StateHeader h{STATE_MAGIC, c->n, c->nchan, c->prec, 0, c->ztot};
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    HIPCHK(c, hipMemcpy(p, c->d_dir, img, hipMemcpyDeviceToHost)); p += img;
+    HIPCHK(c, hipMemcpy(p, c->d_gt, img, hipMemcpyDeviceToHost)); p += img;
+    HIPCHK(c, hipMemcpy(p, c->d_g, img, hipMemcpyDeviceToHost)); p += img;
+    if (c->ztot) HIPCHK(c, hipMemcpy(p, c->d_R, c->ztot * sizeof(double2), hipMemcpyDeviceToHost));
+    p += c->ztot * sizeof(double2);
+    HIPCHK(c, hipMemcpy(p, c->d_scal, c->nchan * UVMEM_NSCAL * sizeof(double), hipMemcpyDeviceToHost));
+    p += c->nchan * UVMEM_NSCAL * sizeof(double);
+    HIPCHK(c, hipMemcpy(p, c->d_chan, c->nchan * CH_N * sizeof(double), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return UVMEM_OK;
+}
+
+int uvmem_cg_set_state(uvmem_ctx *c, const void *blob, size_t bytes) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!blob) return fail(c, UVMEM_EINVAL, "null state");
+    if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_set_state before cg_init");
+    const size_t img = (size_t)c->nchan * c->n * c->n * real_size(c);
+    const size_t need = sizeof(StateHeader) + 3 * img + c->ztot * sizeof(double2) +
+                        (size_t)c->nchan * (UVMEM_NSCAL + CH_N) * sizeof(double);
+    if (bytes < need) return fail(c, UVMEM_EINVAL, "state blob too small");
+    StateHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    if (h.magic != STATE_MAGIC || h.n != c->n || h.nchan != c->nchan || h.prec != c->prec || h.ztot != c->ztot)
+        return fail(c, UVMEM_EINVAL, "state blob does not match this context");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const char *p = (const char *)blob + sizeof h;
+    HIPCHK(c, hipMemcpy(c->d_dir, p, img, hipMemcpyHostToDevice)); p += img;
+    HIPCHK(c, hipMemcpy(c->d_gt, p, img, hipMemcpyHostToDevice)); p += img;
+    HIPCHK(c, hipMemcpy(c->d_g, p, img, hipMemcpyHostToDevice)); p += img;
+    if (c->ztot) HIPCHK(c, hipMemcpy(c->d_R, p, c->ztot * sizeof(double2), hipMemcpyHostToDevice));
+    p += c->ztot * sizeof(double2);
+    HIPCHK(c, hipMemcpy(c->d_scal, p, c->nchan * UVMEM_NSCAL * sizeof(double), hipMemcpyHostToDevice));
+    p += c->nchan * UVMEM_NSCAL * sizeof(double);
+    HIPCHK(c, hipMemcpy(c->d_chan, p, c->nchan * CH_N * sizeof(double), hipMemcpyHostToDevice));
+    return UVMEM_OK;
+}
+
+int uvmem_check(uvmem_ctx *c) {
+    int s = check_ready(c);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int flag[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpy(flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag[0]) {
+        int zero[4] = {0, 0, 0, 0};
+        HIPCHK(c, hipMemcpy(c->d_flag, zero, sizeof zero, hipMemcpyHostToDevice));
+        return fail(c, UVMEM_EDOMAIN, "an image pixel was <= 0 or NaN");
+    }
+    HIPCHK(c, hipGetLastError());
+    return UVMEM_OK;
+}
+
+int uvmem_timing_enable(uvmem_ctx *c, int enable) {
+    if (!c) return UVMEM_EINVAL;
+    if (enable && c->ev_pool.empty()) {
+        for (int i = 0; i < 512; ++i) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+    }
+    c->timing = enable != 0;
+    return UVMEM_OK;
+}
+
+int uvmem_timing_read(uvmem_ctx *c, int which, double *total_ms, int64_t *count, int reset) {
+    if (!c || which < 0 || which > 1) return UVMEM_EINVAL;
+    if (c->finalized) HIPCHK(c, hipStreamSynchronize(c->stream));
+    harvest(c);
+    if (total_ms) *total_ms = c->t_ms[which];
+    if (count) *count = c->t_cnt[which];
+    if (reset) {
+        c->t_ms[which] = 0.0;
+        c->t_cnt[which] = 0;
+    }
+    return UVMEM_OK;
+}
+
+int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
+    if (!c || !out) return UVMEM_EINVAL;
+    const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_ib, c->adj_tt, c->n_slots,
+                            c->n_fwd, c->n_adj, c->n_visit, (int64_t)c->bytes_device};
+    const int nv = (int)(sizeof vals / sizeof vals[0]);
+    for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
+    return UVMEM_OK;
+}
+
+int uvmem_chan_range(const uvmem_ctx *c, int chan, int64_t *offset, int64_t *nvis) {
+    if (!c || chan < 0 || chan >= c->nchan) return UVMEM_EINVAL;
+    int64_t o = 0;
+    for (int ch = 0; ch < chan; ++ch) o += c->nvis[ch];
+    if (offset) *offset = o;
+    if (nvis) *nvis = c->nvis[chan];
+    return UVMEM_OK;
+}
+
+}  // extern "C"

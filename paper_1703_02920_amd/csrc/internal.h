@@ -1,0 +1,171 @@
+// Internal declarations of the uvmem library: context layout, work-item
+// tables, kernel launchers.  Not part of the public ABI (include/uvmem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/uvmem.h"
+
+namespace uvm {
+
+// Visibilities per forward workgroup (4 waves x 16 MFMA rows).
+constexpr int FWD_KV = 64;
+// Visibilities per visibility-reduction workgroup item.
+constexpr int VIS_BLK = 2048;
+// Pixels per pixel-kernel workgroup (256 threads x 4).
+constexpr int PIX_BLK = 1024;
+// Minimum visibilities per adjoint split-K chunk (multiple of 16).
+constexpr int ADJ_KMIN = 256;
+// Partial-sum slots per pixel / visibility item.
+constexpr int NPART = 4;
+// Relative tolerance that decides "pixel at the bound I <= M (1 + tol)".
+constexpr double BOUND_TOL = 1e-12;
+// Fixed number of line-search launches per CG step (Newton / bisection).
+constexpr int LS_STEPS = 12;
+
+// One forward workgroup: FWD_KV visibilities [k0, k0 + nvalid) of a channel.
+struct FwdItem {
+    int chan;
+    int nvalid;
+    long long k0;
+};
+
+// One adjoint workgroup: a square pixel tile (ti, tj) of a channel and a
+// chunk [kbeg, kend) of its visibilities; `slot` indexes the partial image.
+struct AdjItem {
+    int chan;
+    int ti;
+    int tj;
+    int slot;
+    long long kbeg;
+    long long kend;
+};
+
+// One visibility-reduction workgroup: [kbeg, kend) inside one channel.
+struct VisItem {
+    int chan;
+    int pad;
+    long long kbeg;
+    long long kend;
+};
+
+// Device-side line-search state of one channel (double[LSS_N]).
+enum {
+    LSS_PHASE = 0,   // 0 = check alpha_max, 1 = grow bracket, 2 = Newton, 3 = done
+    LSS_LO,
+    LSS_HI,          // < 0 means +infinity
+    LSS_TRY,         // trial step evaluated by the next pixel pass
+    LSS_ALPHA,       // accepted step once done
+    LSS_A,           // sum w |Vd|^2
+    LSS_B,           // sum w Re(conj(R) Vd)
+    LSS_AMAX,        // alpha_max (< 0 means +infinity)
+    LSS_STOP,        // 1 if the channel has stopped (no descent / zero gradient)
+    LSS_N = 12
+};
+
+// Per-channel flags / CG bookkeeping kept on the device (double).
+enum {
+    CH_GTD = 0,      // gt . d after projection
+    CH_RESTART,      // 1 if the direction was reset to -gt this step
+    CH_GG_OLD,       // |gt_old|^2
+    CH_STOP,         // 1 once the channel has stopped (zero gradient or zero step)
+    CH_N = 4
+};
+
+}  // namespace uvm
+
+struct uvmem_ctx {
+    int n = 0, np = 0, nchan = 0, mode = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double cell = 0.0;
+    bool cell_set = false;
+    double M = 0.0, lam = 0.0;
+    bool prior_set = false;
+    bool finalized = false;
+    std::string err;
+
+    // host staging (until finalize)
+    std::vector<int64_t> nvis;
+    std::vector<std::vector<double>> hu, hv;
+    std::vector<std::vector<float>> hvis, hw, hbeam;
+    std::vector<double> fwhm;
+    std::vector<char> has_uv, has_vis, has_w, has_beam;
+
+    // layout
+    std::vector<int64_t> off;          // channel offsets, size nchan+1
+    int64_t ztot = 0;
+    int ib_rows = 0, n_ib = 0;         // forward i-blocks
+    int adj_tt = 0, adj_nt = 0;        // adjoint tile side, tiles per side
+    int n_slots = 0;
+    int n_pb = 0;                      // pixel blocks per channel
+    std::vector<int> h_slot_base;      // nchan+1
+    std::vector<int> h_vis_base;       // nchan+1
+    int n_fwd = 0, n_adj = 0, n_visit = 0;
+
+    // device buffers
+    double *d_a = nullptr, *d_b = nullptr;      // u cell, v cell
+    float2 *d_vo = nullptr;
+    float *d_w = nullptr;
+    void *d_beam = nullptr;                     // real [C][n][n]
+    uvm::FwdItem *d_fwd = nullptr;
+    uvm::AdjItem *d_adj = nullptr;
+    uvm::VisItem *d_vis = nullptr;
+    int *d_slot_base = nullptr, *d_vis_base = nullptr;
+    double2 *d_R = nullptr, *d_Vd = nullptr, *d_vpart = nullptr;
+    double *d_gpart = nullptr;
+    void *d_bop = nullptr;                      // operand image [C][np][np]
+    void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [C][n][n]
+    double *d_scal = nullptr;                   // [C][NSCAL]
+    double *d_chan = nullptr;                   // [C][CH_N]
+    double *d_ls = nullptr;                     // [2][C][LSS_N] (ping-pong)
+    double *d_ppart = nullptr;                  // [2][C][n_pb][NPART] (ping-pong)
+    double *d_vispart = nullptr;                // [n_visit][NPART]
+    int *d_flag = nullptr;                      // [4]: domain flag, ...
+    size_t bytes_device = 0;
+
+    // CG
+    void *cg_I = nullptr;
+    bool cg_ready = false;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void *graph_I = nullptr;
+    long long *d_hist_ptr = nullptr;            // device copy of the cg_run history pointer
+    long long *d_iter_ctr = nullptr;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend[2];
+    double t_ms[2] = {0, 0};
+    int64_t t_cnt[2] = {0, 0};
+};
+
+namespace uvm {
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error; every launch goes to `st`.
+
+// Forward DFT: vpart[ib][k] = sum over the i-block ib of E_v T (see k_dft.hip).
+hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st);
+// Adjoint: gpart[slot] tiles of Re F^H (w coef) without the beam factor.
+hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st);
+
+// Auxiliary kernels (k_aux.hip).
+hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st);
+hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st);
+hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st);
+hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st);
+hipError_t launch_chan_phi(const uvmem_ctx *c, double *user_scal, hipStream_t st);
+hipError_t launch_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st);
+hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user_scal, hipStream_t st);
+// The CG step in three phases around the DFT launches (0: before the forward
+// model, 1: between forward and adjoint, 2: after the adjoint).
+hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user_scal, int phase, hipStream_t st);
+hipError_t launch_copy_scal(const uvmem_ctx *c, double *dst, long long *ctr, hipStream_t st);
+
+}  // namespace uvm

@@ -1,0 +1,350 @@
+// Separable direct-DFT contractions on CDNA4 matrix cores (gfx950).
+//
+// Forward model (Eq. fft discretised at the measured (u, v)):
+//   V_k = sum_i E_v[k,i] T[k,i],   T[k,i] = sum_j E_u[k,j] B[i,j],
+//   E_u[k,j] = exp(-2 pi i a_k (j - N/2)),  E_v[k,i] = exp(-2 pi i b_k (i - N/2)),
+//   a_k = u_k cell, b_k = v_k cell, B = A o I.
+// The exponent of Eq. fft factorises over the two image axes, so the N^2-term
+// sum per visibility becomes one complex-by-real matrix product over j (on
+// MFMA) followed by a length-N row dot over i.
+//
+// Adjoint (Eq. chi2gradient / Alg. 3 without the beam factor, applied later):
+//   G[i,j] = sum_k Re( P[k,i] conj(E_u[k,j]) ),  P[k,i] = c_k conj(E_v[k,i]),
+//          = sum_k P_re[k,i] cos(2 pi a_k m_j) - P_im[k,i] sin(2 pi a_k m_j)
+// a real matrix product with the visibilities as the contraction dimension,
+// split over visibility chunks (split-K); chunk partials are summed in a fixed
+// order by the gradient kernel, so results are bitwise reproducible.
+//
+// Phases are formed and reduced modulo one cycle in FP64 (f = t - rint(t) with
+// t = a_k m), then the twiddle is sincospi(2 f) in the operand precision.
+#include "internal.h"
+
+namespace uvm {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+
+// v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// it holds D[4 (l/16) + r][l%16] in accumulator register r.
+template <> struct Mfma<float> {
+    typedef floatx4 acc;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int g, int r) { return 4 * g + r; }
+    static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+};
+
+// v_mfma_f64_16x16x4_f64: same A/B lane layout as FP32, but lane l holds
+// D[4 r + l/16][l%16] in accumulator register r (checked on gfx950).
+template <> struct Mfma<double> {
+    typedef doublex4 acc;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int g, int r) { return 4 * r + g; }
+    static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+};
+
+__device__ __forceinline__ void cis2pi(double f, double &c, double &s) { sincospi(2.0 * f, &s, &c); }
+__device__ __forceinline__ void cis2pi(float f, float &c, float &s) { sincospif(2.0f * f, &s, &c); }
+
+// Reduced phase frac(a * m) in [-1/2, 1/2], formed in FP64.
+__device__ __forceinline__ double phase(double a, int m) {
+    double t = a * (double)m;
+    return t - rint(t);
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
+// ----------------------------------------------------------------------------
+// Forward.  Workgroup = 4 waves; wave w owns the 16 visibilities
+// k0 + 16 w + (0..15) as MFMA rows and all IB image rows of i-block blockIdx.y
+// as MFMA columns; the image block is staged through LDS in JC-column chunks.
+// Within a 16-column super-step, MFMA #s (s = 0..3) of lane group g = l/16
+// contracts column j = jbase + 4 g + s, so each lane reads 4 consecutive
+// image values with one vector load.
+// ----------------------------------------------------------------------------
+constexpr int JC = 32;
+constexpr int JPAD = 4;
+
+template <typename T, int IB>
+__global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ items,
+                                                 const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 const T *__restrict__ bop, double2 *__restrict__ vpart,
+                                                 int n, int np, long long ztot) {
+    typedef typename Mfma<T>::acc acc_t;
+    typedef typename Vec4<T>::type T4;
+    constexpr int NT = IB / 16;
+    __shared__ __attribute__((aligned(16))) T sB[IB][JC + JPAD];
+
+    const FwdItem it = items[blockIdx.x];
+    const int ib = blockIdx.y;
+    const int i0 = ib * IB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const T *B = bop + (size_t)it.chan * np * np;
+    const int half = n / 2;
+
+    const int krow = wave * 16 + q;
+    const double ak = krow < it.nvalid ? a[it.k0 + krow] : 0.0;
+
+    acc_t accR[NT], accI[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accR[t] = Mfma<T>::zero();
+        accI[t] = Mfma<T>::zero();
+    }
+
+    constexpr int V_PER_ROW = JC / 4;                 // 4-wide vectors per staged row
+    constexpr int NLOAD = IB * V_PER_ROW / 256;       // vectors per thread
+    for (int jc = 0; jc < np; jc += JC) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NLOAD; ++r) {
+            int idx = tid + 256 * r;
+            int row = idx / V_PER_ROW, c4 = idx % V_PER_ROW;
+            T4 v = *reinterpret_cast<const T4 *>(B + (size_t)(i0 + row) * np + jc + 4 * c4);
+            *reinterpret_cast<T4 *>(&sB[row][4 * c4]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int js = 0; js < JC; js += 16) {
+            T cr[4], ci[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                int m = jc + js + 4 * g + s - half;
+                T c, sn;
+                cis2pi((T)phase(ak, m), c, sn);
+                cr[s] = c;
+                ci[s] = -sn;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                T4 bv = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
+                accR[t] = Mfma<T>::mma(cr[0], bv.x, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[0], bv.x, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[1], bv.y, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[1], bv.y, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[2], bv.z, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[2], bv.z, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[3], bv.w, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[3], bv.w, accI[t]);
+            }
+        }
+    }
+
+    // Row dot with E_v, accumulated in FP64: lane holds T[k][i] for
+    // k = 16 w + drow(g, r), i = i0 + 16 t + q.
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kk = wave * 16 + Mfma<T>::drow(g, r);
+        const bool ok = kk < it.nvalid;
+        const double bk = ok ? b[it.k0 + kk] : 0.0;
+        double vr = 0.0, vi = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            int m = i0 + 16 * t + q - half;
+            T c, sn;
+            cis2pi((T)phase(bk, m), c, sn);
+            double tr = (double)accR[t][r], ti = (double)accI[t][r];
+            double cd = (double)c, sd = (double)sn;
+            vr += cd * tr + sd * ti;
+            vi += cd * ti - sd * tr;
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            vr += __shfl_xor(vr, o, 64);
+            vi += __shfl_xor(vi, o, 64);
+        }
+        if (q == 0 && ok) vpart[(size_t)ib * ztot + it.k0 + kk] = make_double2(vr, vi);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint.  Workgroup tile TT x TT pixels (TT = 2 WT), 2 x 2 waves of WT x WT.
+// Per 16-visibility super-step the workgroup writes to LDS, for k in the step,
+//   Hv[k][q] = c_k w_k exp(+2 pi i b_k (i0 + q - N/2)),  Gv[k][t] = exp(+2 pi i b_k 16 t)
+//   Fu[k][q] = exp(+2 pi i a_k (j0 + q - N/2)),          Gu[k][t] = exp(+2 pi i a_k 16 t)
+// so that P[k][i0 + 16 t + q] = Hv[k][q] Gv[k][t] and the cos/sin operand at
+// column j0 + 16 t + q is Fu[k][q] Gu[k][t] (one product per operand, two
+// correctly rounded factors).  MFMA #s of lane group g contracts visibility
+// 4 g + s of the step.  FP32 accumulators are folded into FP64 ones every
+// FLUSH super-steps.
+// ----------------------------------------------------------------------------
+template <typename T> struct C2T;
+template <> struct C2T<float> { typedef float2 type; };
+template <> struct C2T<double> { typedef double2 type; };
+
+template <typename T, int WT>
+__global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ items,
+                                                 const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 const double2 *__restrict__ coef,
+                                                 const float *__restrict__ w,
+                                                 double *__restrict__ gpart, int n, int np) {
+    typedef typename Mfma<T>::acc acc_t;
+    typedef typename C2T<T>::type C2;
+    constexpr int TT = 2 * WT;
+    constexpr int NT = WT / 16;
+    constexpr int NC = TT / 16;
+    constexpr int FLUSH = 16;
+    __shared__ C2 sHv[16][16], sFu[16][16], sGv[16][NC], sGu[16][NC];
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int ci0 = (wave >> 1) * NT;   // wave's first coarse i-tile
+    const int cj0 = (wave & 1) * NT;    // wave's first coarse j-tile
+    const int half = n / 2;
+
+    acc_t acc[NT][NT];
+    double dacc[NT][NT][4];
+#pragma unroll
+    for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y) {
+            acc[x][y] = Mfma<T>::zero();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dacc[x][y][r] = 0.0;
+        }
+
+    int step = 0;
+    for (long long kb = it.kbeg; kb < it.kend; kb += 16, ++step) {
+        // ---- generate the step's twiddle tables
+        {
+            const int kk = tid >> 4, qq = tid & 15;
+            const long long k = kb + kk;
+            const bool ok = k < it.kend;
+            C2 hv = {0, 0}, fu = {0, 0};
+            if (ok) {
+                const double bk = b[k], ak = a[k];
+                double2 cc = coef[k];
+                double ww = w ? (double)w[k] : 1.0;
+                T c, s;
+                cis2pi((T)phase(bk, i0 + qq - half), c, s);
+                double cr = ww * cc.x, cim = ww * cc.y;
+                hv.x = (T)(cr * (double)c - cim * (double)s);
+                hv.y = (T)(cr * (double)s + cim * (double)c);
+                cis2pi((T)phase(ak, j0 + qq - half), c, s);
+                fu.x = c;
+                fu.y = s;
+            }
+            sHv[kk][qq] = hv;
+            sFu[kk][qq] = fu;
+            if (tid < 32 * NC) {
+                const int which = tid / (16 * NC);
+                const int r2 = tid % (16 * NC);
+                const int k2 = r2 / NC, t2 = r2 % NC;
+                const long long kg = kb + k2;
+                C2 gval = {1, 0};
+                if (kg < it.kend) {
+                    const double ab = which ? a[kg] : b[kg];
+                    T c, s;
+                    cis2pi((T)phase(ab, 16 * t2), c, s);
+                    gval.x = c;
+                    gval.y = s;
+                }
+                if (which) sGu[k2][t2] = gval; else sGv[k2][t2] = gval;
+            }
+        }
+        __syncthreads();
+        // ---- contract the step on matrix cores
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * g + s;
+            const C2 h = sHv[kk][q];
+            const C2 f = sFu[kk][q];
+            T pr[NT], pn[NT], ec[NT], es[NT];
+#pragma unroll
+            for (int x = 0; x < NT; ++x) {
+                const C2 gv = sGv[kk][ci0 + x];
+                pr[x] = h.x * gv.x - h.y * gv.y;
+                pn[x] = -(h.x * gv.y + h.y * gv.x);
+            }
+#pragma unroll
+            for (int y = 0; y < NT; ++y) {
+                const C2 gu = sGu[kk][cj0 + y];
+                ec[y] = f.x * gu.x - f.y * gu.y;
+                es[y] = f.x * gu.y + f.y * gu.x;
+            }
+#pragma unroll
+            for (int x = 0; x < NT; ++x)
+#pragma unroll
+                for (int y = 0; y < NT; ++y) {
+                    acc[x][y] = Mfma<T>::mma(pr[x], ec[y], acc[x][y]);
+                    acc[x][y] = Mfma<T>::mma(pn[x], es[y], acc[x][y]);
+                }
+        }
+        __syncthreads();
+        if (sizeof(T) == 4 && (step % FLUSH) == FLUSH - 1) {
+#pragma unroll
+            for (int x = 0; x < NT; ++x)
+#pragma unroll
+                for (int y = 0; y < NT; ++y) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dacc[x][y][r] += (double)acc[x][y][r];
+                    acc[x][y] = Mfma<T>::zero();
+                }
+        }
+    }
+    double *out = gpart + (size_t)it.slot * np * np;
+#pragma unroll
+    for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 16 * (ci0 + x) + Mfma<T>::drow(g, r);
+                const int j = j0 + 16 * (cj0 + y) + q;
+                out[(size_t)i * np + j] = dacc[x][y][r] + (double)acc[x][y][r];
+            }
+}
+
+template <typename T>
+hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->n_fwd == 0) return hipSuccess;
+    dim3 grid(c->n_fwd, c->n_ib);
+    if (c->ib_rows == 128)
+        hipLaunchKernelGGL((k_forward<T, 128>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
+                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+    else
+        hipLaunchKernelGGL((k_forward<T, 64>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
+                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+    if (c->n_adj == 0) return hipSuccess;
+    if (c->adj_tt == 128)
+        hipLaunchKernelGGL((k_adjoint<T, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
+                           c->d_b, coef, w, c->d_gpart, c->n, c->np);
+    else
+        hipLaunchKernelGGL((k_adjoint<T, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
+                           c->d_b, coef, w, c->d_gpart, c->n, c->np);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st);
+    return fwd_dispatch<float>(c, bop, st);
+}
+
+hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+    if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st);
+    return adj_dispatch<float>(c, coef, w, st);
+}
+
+}  // namespace uvm

@@ -1,0 +1,295 @@
+"""Python binding of the uvmem C ABI (include/uvmem.h).
+
+Argument marshalling only: every step of the imaging hot path runs in the HIP
+kernels of libuvmem.so.  PyTorch supplies device memory and the stream.  If
+the HIP library is missing the binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuvmem.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ESTATE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+NSCAL = 8
+S_PHI, S_CHI2, S_S, S_ALPHA, S_BETA, S_GNORM2, S_ALPHA_MAX, S_ITER = range(8)
+
+SYMBOLS = [
+    "uvmem_create", "uvmem_destroy", "uvmem_set_uv", "uvmem_set_vis", "uvmem_set_weights",
+    "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_prior", "uvmem_finalize",
+    "uvmem_phi_and_grad", "uvmem_forward", "uvmem_adjoint", "uvmem_get_residual",
+    "uvmem_cg_init", "uvmem_cg_step", "uvmem_cg_run", "uvmem_cg_get_state", "uvmem_cg_set_state",
+    "uvmem_check", "uvmem_timing_enable", "uvmem_timing_read", "uvmem_info", "uvmem_chan_range",
+    "uvmem_last_error", "uvmem_strerror",
+]
+
+_lib = None
+
+
+class UvmemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"uvmem error {code}: {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    """Load libuvmem.so (built by paper_1703_02920_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run python -m paper_1703_02920_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "uvmem_create": [ctypes.POINTER(vp), ci, ci, ci, ci, vp],
+        "uvmem_destroy": [vp],
+        "uvmem_set_uv": [vp, ci, i64, vp, vp, dbl],
+        "uvmem_set_vis": [vp, ci, vp],
+        "uvmem_set_weights": [vp, ci, vp],
+        "uvmem_set_beam": [vp, ci, dbl],
+        "uvmem_set_beam_image": [vp, ci, vp],
+        "uvmem_set_prior": [vp, dbl, dbl],
+        "uvmem_finalize": [vp],
+        "uvmem_phi_and_grad": [vp, vp, vp, vp],
+        "uvmem_forward": [vp, vp, vp],
+        "uvmem_adjoint": [vp, vp, vp],
+        "uvmem_get_residual": [vp, vp],
+        "uvmem_cg_init": [vp, vp, ci],
+        "uvmem_cg_step": [vp, vp, vp],
+        "uvmem_cg_run": [vp, vp, ci, vp, ci],
+        "uvmem_cg_get_state": [vp, vp, ctypes.POINTER(ctypes.c_size_t)],
+        "uvmem_cg_set_state": [vp, vp, ctypes.c_size_t],
+        "uvmem_check": [vp],
+        "uvmem_timing_enable": [vp, ci],
+        "uvmem_timing_read": [vp, ci, ctypes.POINTER(dbl), ctypes.POINTER(i64), ci],
+        "uvmem_info": [vp, ctypes.POINTER(i64), ci],
+        "uvmem_chan_range": [vp, ci, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "uvmem_last_error": [vp],
+        "uvmem_strerror": [ci],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name in ("uvmem_last_error", "uvmem_strerror") else ci
+    _lib = L
+    return L
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+class Context:
+    """One imaging problem: image side n, n_chan independent channels."""
+
+    def __init__(self, n: int, n_chan: int = 1, precision: str = "fp32",
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        self._lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("uvmem needs a GPU")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n, self.n_chan, self.precision = int(n), int(n_chan), precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        h = ctypes.c_void_p()
+        code = self._lib.uvmem_create(ctypes.byref(h), self.n, self.n_chan, 0, PRECISIONS[precision],
+                                      ctypes.c_void_p(self.stream.cuda_stream))
+        if code != OK:
+            raise UvmemError(code, self._lib.uvmem_strerror(code).decode())
+        self._h = h
+        self._nvis = [0] * self.n_chan
+        self._keep = []
+
+    # ------------------------------------------------------------ plumbing
+    def _call(self, name, *args):
+        code = getattr(self._lib, name)(self._h, *args)
+        if code != OK:
+            raise UvmemError(code, self._lib.uvmem_last_error(self._h).decode())
+        return code
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.uvmem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------ setup
+    def set_uv(self, chan: int, u, v, cell: float):
+        u = np.ascontiguousarray(u, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        self._nvis[chan] = int(u.shape[0])
+        self._call("uvmem_set_uv", chan, u.shape[0], _ptr(u), _ptr(v), float(cell))
+
+    def set_vis(self, chan: int, vis):
+        vis = np.ascontiguousarray(vis, np.complex64)
+        self._call("uvmem_set_vis", chan, _ptr(vis))
+
+    def set_weights(self, chan: int, w):
+        w = np.ascontiguousarray(w, np.float32)
+        self._call("uvmem_set_weights", chan, _ptr(w))
+
+    def set_beam(self, chan: int, fwhm: float):
+        self._call("uvmem_set_beam", chan, float(fwhm))
+
+    def set_beam_image(self, chan: int, A):
+        A = np.ascontiguousarray(A, np.float32)
+        self._call("uvmem_set_beam_image", chan, _ptr(A))
+
+    def set_prior(self, M: float, lam: float):
+        self._call("uvmem_set_prior", float(M), float(lam))
+
+    def finalize(self):
+        self._call("uvmem_finalize")
+        info = self.info()
+        self.np, self.ztot = info["np"], info["ztot"]
+        return self
+
+    @classmethod
+    def from_dataset(cls, ds, precision: str = "fp32", **kw) -> "Context":
+        """Context for a synthetic data set (paper_1703_02920_amd.synth)."""
+        ctx = cls(ds.n, ds.n_chan, precision, **kw)
+        for c, ch in enumerate(ds.channels):
+            ctx.set_uv(c, ch.u, ch.v, ds.cell)
+            ctx.set_vis(c, ch.vis)
+            ctx.set_weights(c, ch.w)
+            ctx.set_beam(c, ch.fwhm)
+        ctx.set_prior(ds.prior_m, ds.lam)
+        return ctx.finalize()
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 12)()
+        self._call("uvmem_info", out, 12)
+        keys = ["n", "np", "n_chan", "prec", "ztot", "n_ib", "adj_tile", "n_slots", "n_fwd_items",
+                "n_adj_items", "n_vis_items", "device_bytes"]
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def chan_range(self, chan: int):
+        o, nv = ctypes.c_int64(), ctypes.c_int64()
+        self._call("uvmem_chan_range", chan, ctypes.byref(o), ctypes.byref(nv))
+        return int(o.value), int(nv.value)
+
+    # ------------------------------------------------------------ tensors
+    def image(self, fill: Optional[float] = None) -> torch.Tensor:
+        t = torch.empty((self.n_chan, self.n, self.n), dtype=self.dtype, device=self.device)
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    def _img(self, I: torch.Tensor) -> torch.Tensor:
+        if I.dtype != self.dtype or I.device != self.device or not I.is_contiguous():
+            raise ValueError("image must be a contiguous %s tensor on %s" % (self.dtype, self.device))
+        if I.numel() != self.n_chan * self.n * self.n:
+            raise ValueError("image must have n_chan * n * n elements")
+        return I
+
+    def scalars(self) -> torch.Tensor:
+        return torch.zeros((self.n_chan, NSCAL), dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------ hot path
+    def phi_and_grad(self, I: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                     scal: Optional[torch.Tensor] = None):
+        I = self._img(I)
+        grad = torch.empty_like(I) if grad is None else self._img(grad)
+        scal = self.scalars() if scal is None else scal
+        self._call("uvmem_phi_and_grad", _ptr(I), _ptr(grad), _ptr(scal))
+        return scal, grad
+
+    def forward(self, I: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        I = self._img(I)
+        if out is None:
+            out = torch.empty(max(self.ztot, 1), dtype=torch.complex128, device=self.device)[: self.ztot]
+        self._call("uvmem_forward", _ptr(I), _ptr(out))
+        return out
+
+    def adjoint(self, coef: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if coef.dtype != torch.complex128 or not coef.is_contiguous() or coef.numel() != self.ztot:
+            raise ValueError("coefficients must be a contiguous complex128 tensor of sum Z elements")
+        out = self.image() if out is None else self._img(out)
+        self._call("uvmem_adjoint", _ptr(coef) if self.ztot else None, _ptr(out))
+        return out
+
+    def residual(self) -> torch.Tensor:
+        out = torch.empty(max(self.ztot, 1), dtype=torch.complex128, device=self.device)[: self.ztot]
+        self._call("uvmem_get_residual", _ptr(out) if self.ztot else None)
+        return out
+
+    def cg_init(self, I: torch.Tensor, init_to_floor: bool = True):
+        self._cg_I = self._img(I)
+        self._call("uvmem_cg_init", _ptr(I), 1 if init_to_floor else 0)
+
+    def cg_step(self, I: torch.Tensor, scal: Optional[torch.Tensor] = None) -> torch.Tensor:
+        scal = self.scalars() if scal is None else scal
+        self._call("uvmem_cg_step", _ptr(self._img(I)), _ptr(scal))
+        return scal
+
+    def cg_run(self, I: torch.Tensor, iters: int, graph: bool = True,
+               hist: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if hist is None:
+            hist = torch.zeros((max(iters, 1), self.n_chan, NSCAL), dtype=torch.float64, device=self.device)
+        self._call("uvmem_cg_run", _ptr(self._img(I)), int(iters), _ptr(hist), 1 if graph else 0)
+        return hist[:iters]
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self._call("uvmem_cg_get_state", None, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        self._call("uvmem_cg_get_state", buf, ctypes.byref(n))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._call("uvmem_cg_set_state", buf, len(blob))
+
+    def check(self):
+        self._call("uvmem_check")
+
+    # ------------------------------------------------------------ timing
+    def timing(self, enable: bool = True):
+        self._call("uvmem_timing_enable", 1 if enable else 0)
+
+    def timing_read(self, which: int, reset: bool = False):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        self._call("uvmem_timing_read", int(which), ctypes.byref(ms), ctypes.byref(cnt), 1 if reset else 0)
+        return float(ms.value), int(cnt.value)
+
+
+class PhiFunction(torch.autograd.Function):
+    """Phi(I) summed over channels as a differentiable torch function; the
+    backward pass returns g * grad Phi computed by the same HIP evaluation."""
+
+    @staticmethod
+    def forward(ctx, I: torch.Tensor, uctx: Context):
+        scal, grad = uctx.phi_and_grad(I.detach().contiguous())
+        ctx.save_for_backward(grad)
+        return scal[:, S_PHI].sum()
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout.to(grad.dtype) * grad, None

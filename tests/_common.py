@@ -1,0 +1,87 @@
+"""Shared helpers of the GPU tests: build the same problem for the HIP path
+and for the oracle, and error metrics."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1703_02920_amd import synth  # noqa: E402
+
+# Parity bars (relative l2): the stated targets for the FP32 matrix-core path
+# and the split-precision path; FP64 is held to a bar set by the FP64 sums.
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-4, "fp16x3": 1e-4}
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def flush(msg: str) -> None:
+    print(msg, flush=True)
+
+
+class Problem:
+    """A set of channels sharing one pixel grid, as plain numpy arrays."""
+
+    def __init__(self, n, cell, chans, M=1e-3, lam=0.01):
+        self.n, self.cell, self.chans, self.M, self.lam = n, cell, chans, M, lam
+
+    @property
+    def n_chan(self):
+        return len(self.chans)
+
+    @staticmethod
+    def from_dataset(ds, channels=None):
+        idx = range(ds.n_chan) if channels is None else channels
+        chans = [dict(u=ds.channels[c].u, v=ds.channels[c].v, vis=ds.channels[c].vis, w=ds.channels[c].w,
+                      fwhm=ds.channels[c].fwhm) for c in idx]
+        return Problem(ds.n, ds.cell, chans, ds.prior_m, ds.lam)
+
+    @staticmethod
+    def random(n, nvis_list, seed, fwhm_px=None, M=1e-3, lam=0.01, cell=1.0e-6):
+        chans = []
+        for c, nv in enumerate(nvis_list):
+            u, v, vis, w = synth.random_problem(n, nv, seed * 101 + c, cell=cell)
+            chans.append(dict(u=u, v=v, vis=vis, w=w, fwhm=(fwhm_px or 0.8 * n) * cell))
+        return Problem(n, cell, chans, M, lam)
+
+    def context(self, precision):
+        from paper_1703_02920_amd.uvmem import Context
+        ctx = Context(self.n, self.n_chan, precision)
+        for c, ch in enumerate(self.chans):
+            ctx.set_uv(c, ch["u"], ch["v"], self.cell)
+            ctx.set_vis(c, ch["vis"])
+            ctx.set_weights(c, ch["w"])
+            ctx.set_beam(c, ch["fwhm"])
+        ctx.set_prior(self.M, self.lam)
+        return ctx.finalize()
+
+    def beam(self, c):
+        return oracle.beam(self.n, self.cell, self.chans[c]["fwhm"])
+
+    def oracle_forward(self, c, img):
+        ch = self.chans[c]
+        return oracle.forward(self.n, self.cell, ch["u"], ch["v"], self.beam(c), img)
+
+    def oracle_adjoint(self, c, coef, pix=None):
+        ch = self.chans[c]
+        return oracle.adjoint(self.n, self.cell, ch["u"], ch["v"], self.beam(c), coef, pix=pix)
+
+    def oracle_phi_grad(self, c, img):
+        ch = self.chans[c]
+        return oracle.phi_grad(self.n, self.cell, ch["u"], ch["v"], self.beam(c), img,
+                               ch["vis"].astype(np.complex128), ch["w"].astype(np.float64), self.M, self.lam)
+
+    def offsets(self):
+        o = [0]
+        for ch in self.chans:
+            o.append(o[-1] + len(ch["u"]))
+        return o
