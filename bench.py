@@ -1,0 +1,194 @@
+"""Benchmark of the MEM imaging hot path on one MI355X.
+
+One step = one projected-CG iteration over the whole hot path: direction
+update and projection, forward model of the direction (separable DFT on
+matrix cores), chi^2 line-search scalars, the FP64 line search, image and
+residual update, adjoint gradient (separable DFT), entropy term and the
+Polak-Ribiere update.  Each step does one forward and one adjoint pass over
+every (visibility, pixel) pair, so the headline value is
+    vis.pixel evaluations / s = sum_c Z_c N^2 * steps / time.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (see the keys below).  The CPU baseline is the FP64
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "vis·pixel evals/sec (fwd+adjoint ∇Φ); CG iters/sec, mixed vs FP32 at stated err"
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "fp16x3": 2500.0}   # TFLOP/s, dense MFMA
+KERNEL_SRC = ["paper_1703_02920_amd/csrc/k_dft.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters for the current
+    kernel source (null when the kernel changed since the counters)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("kernel_hash") != kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(ds, target_s: float = 12.0):
+    """FP64 oracle on a bounded sample: the forward model at a subset of the
+    visibilities (all pixels) and the adjoint at a subset of the pixels (all
+    visibilities).  One vis.pixel evaluation = one forward term + one adjoint
+    term, so the rate is (forward pairs + adjoint pairs) / 2 / time."""
+    import numpy as np
+
+    import oracle
+    ch = ds.channels[0]
+    n = ds.n
+    A = oracle.beam(n, ds.cell, ch.fwhm)
+    img = np.full((n, n), ds.prior_m)
+    coef = (ch.w.astype(np.float64) * ch.vis.astype(np.complex128))
+    rng = np.random.default_rng(0)
+
+    def run(n_vis, n_pix):
+        vi = np.sort(rng.choice(ch.nvis, size=n_vis, replace=False))
+        px = np.sort(rng.choice(n * n, size=n_pix, replace=False))
+        t0 = time.perf_counter()
+        oracle.forward_sel(n, ds.cell, vi, ch.u, ch.v, A, img)
+        oracle.adjoint(n, ds.cell, ch.u, ch.v, A, coef, pix=px)
+        dt = time.perf_counter() - t0
+        return (n_vis * n * n + ch.nvis * n_pix) / 2.0, dt
+
+    # calibrate on a small sample, then size the real one to ~target_s
+    p0, t0 = run(min(64, ch.nvis), 64)
+    rate0 = p0 / max(t0, 1e-6)
+    pairs_goal = rate0 * target_s * 2.0
+    n_vis = int(min(ch.nvis, max(64, pairs_goal / 2.0 / (n * n))))
+    n_pix = int(min(n * n, max(64, pairs_goal / 2.0 / ch.nvis)))
+    pairs, dt = run(n_vis, n_pix)
+    return {"value": pairs / dt, "unit": "vis·pixel evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 direct sums: forward at {n_vis} of {ch.nvis} visibilities x {n * n} pixels "
+                      f"+ adjoint at {n_pix} of {n * n} pixels x {ch.nvis} visibilities; {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="workload configuration (1..5)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+
+    torch.cuda.set_device(0)
+    ds = synth.make_config(args.config)
+    ctx = Context.from_dataset(ds, args.precision)
+    I = ctx.image()
+    ctx.cg_init(I, init_to_floor=True)
+    for _ in range(args.warmup):
+        ctx.cg_step(I)
+    if args.graph:
+        ctx.cg_run(I, 1, graph=True)
+    torch.cuda.synchronize()
+    print(f"bench: warmup done ({ds.description})", file=sys.stderr, flush=True)
+
+    ctx.timing(True)
+    ctx.timing_read(0, reset=True)
+    ctx.timing_read(1, reset=True)
+    stream = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    if args.graph:
+        ctx.timing(False)
+        ctx.cg_run(I, args.steps, graph=True)
+    else:
+        for _ in range(args.steps):
+            ctx.cg_step(I)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    fwd_ms, fwd_n = ctx.timing_read(0)
+    adj_ms, adj_n = ctx.timing_read(1)
+    ctx.check()
+    pairs = ds.pairs
+    value = pairs * args.steps / (ms / 1e3)
+    flops_per_launch = 4.0 * pairs          # complex twiddle x real pixel (fwd) / Re(complex x complex) (adj)
+    kern = {}
+    if fwd_n:
+        kern["forward"] = fwd_ms / fwd_n
+    if adj_n:
+        kern["adjoint"] = adj_ms / adj_n
+    roof = None
+    if kern:
+        dom = max(kern, key=kern.get)
+        achieved = flops_per_launch / (kern[dom] / 1e3) / 1e12
+        workload = f"c{args.config}-{args.precision}"
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
+                "frac": achieved / PEAK[args.precision],
+                "traffic": traffic_from_profiles("k_adjoint" if dom == "adjoint" else "k_forward", workload),
+                "kernel": dom, "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
+                "other_kernel_ms": {k: v for k, v in kern.items() if k != dom}}
+    cpu = None
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(ds)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "vis·pixel evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": ds.description + "; one projected-CG iteration per step",
+                   "n": ds.n, "channels": ds.n_chan, "visibilities": ds.total_vis,
+                   "pairs_per_pass": pairs, "precision": args.precision,
+                   "graph": bool(args.graph), "parallelism": "single GPU"},
+        "cg_iters_per_s": args.steps / (ms / 1e3),
+        "wall_s": t_wall,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

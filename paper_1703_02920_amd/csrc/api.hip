@@ -290,6 +290,15 @@ int uvmem_set_prior(uvmem_ctx *c, double M, double lambda) {
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(c, UVMEM_EINVAL, "lambda must be >= 0");
     c->M = M;
     c->lam = lambda;
+    // the bound I >= M on the image's own number lattice: the smallest value
+    // of the image precision that is >= M (M itself in FP64)
+    if (c->prec == UVMEM_FP64) {
+        c->Mb = M;
+    } else {
+        float f = (float)M;
+        if ((double)f < M) f = std::nextafter(f, INFINITY);
+        c->Mb = (double)f;
+    }
     c->prior_set = true;
     return UVMEM_OK;
 }
@@ -482,7 +491,7 @@ int uvmem_cg_init(uvmem_ctx *c, void *I, int init_to_floor) {
     int s = check_ready(c);
     if (s) return s;
     if (!I) return fail(c, UVMEM_EINVAL, "null image");
-    if (init_to_floor) HIPCHK(c, launch_fill(c, I, c->M, c->stream));
+    if (init_to_floor) HIPCHK(c, launch_fill(c, I, c->Mb, c->stream));
     s = uvmem_phi_and_grad(c, I, c->d_g, nullptr);
     if (s) return s;
     HIPCHK(c, launch_cg_init_dir(c, I, c->stream));

@@ -85,6 +85,7 @@ struct uvmem_ctx {
     double cell = 0.0;
     bool cell_set = false;
     double M = 0.0, lam = 0.0;
+    double Mb = 0.0;                   // smallest image value >= M in the image precision (the bound)
     bool prior_set = false;
     bool finalized = false;
     std::string err;

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
                                                const R *__restrict__ beam, const R *__restrict__ I,
                                                R *__restrict__ out, R *__restrict__ gt,
                                                double *__restrict__ ppart, int n, int np, int n_pb,
-                                               double M, double lam, int mode) {
+                                               double M, double Mb, double lam, int mode) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const int s0 = slot_base[c], s1 = slot_base[c + 1];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
         out[q] = gr;
         if (mode == 2) {
             const double x = (double)I[q];
-            const bool act = (x <= M * (1.0 + BOUND_TOL)) && ((double)gr > 0.0);
+            const bool act = (x <= Mb * (1.0 + BOUND_TOL)) && ((double)gr > 0.0);
             const double gnew = act ? 0.0 : (double)gr;
             const double gold = (double)gt[q];
             gt[q] = (R)gnew;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(NTHR) void k_chan_phi(const double *__restrict__ vi
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const R *__restrict__ g,
                                                   R *__restrict__ gt, R *__restrict__ dir,
-                                                  double *__restrict__ ppart, int n, int n_pb, double M) {
+                                                  double *__restrict__ ppart, int n, int n_pb, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     double acc[1] = {0.0};
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double x = (double)I[q], gv = (double)g[q];
-        const bool act = (x <= M * (1.0 + BOUND_TOL)) && (gv > 0.0);
+        const bool act = (x <= Mb * (1.0 + BOUND_TOL)) && (gv > 0.0);
         const double gn = act ? 0.0 : gv;
         gt[q] = (R)gn;
         dir[q] = (R)0;
@@ -289,7 +289,7 @@ template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const R *__restrict__ g,
                                                  const R *__restrict__ gt, R *__restrict__ dir,
                                                  const double *__restrict__ scal, const double *__restrict__ chan,
-                                                 double *__restrict__ ppart, int n, int n_pb, double M) {
+                                                 double *__restrict__ ppart, int n, int n_pb, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const double beta = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_BETA];
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         const size_t q = (size_t)c * npix + p;
         const double x = (double)I[q], gv = (double)g[q], gtv = (double)gt[q];
         double d = -gtv + beta * (double)dir[q];
-        const bool atb = x <= M * (1.0 + BOUND_TOL);
+        const bool atb = x <= Mb * (1.0 + BOUND_TOL);
         if (atb && gv > 0.0) d = 0.0;
         else if (atb) d = fmax(d, 0.0);
         if (stop) d = 0.0;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
                                                   R *__restrict__ dir, const R *__restrict__ beam,
                                                   R *__restrict__ bop, const double *__restrict__ chan,
                                                   double *__restrict__ ppart, int n, int np, int n_pb,
-                                                  double M) {
+                                                  double M, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const bool restart = chan[(size_t)c * CH_N + CH_RESTART] != 0.0;
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         const int i = (int)(p / n), j = (int)(p % n);
         Bc[(size_t)i * np + j] = beam[q] * dr;
         const double x = (double)I[q];
-        if (d < 0.0) amax = fmin(amax, (x - M) / (-d));
+        if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
         acc[1] += d * d / x;
     }
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
                                                     const double *__restrict__ ls_prev, const double *__restrict__ pp_prev,
                                                     double *__restrict__ pp_out, double *__restrict__ scal,
                                                     double *__restrict__ chan, int *__restrict__ flag,
-                                                    int n, int n_pb, double M, double lam) {
+                                                    int n, int n_pb, double M, double Mb, double lam) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
         const size_t q = (size_t)c * npix + p;
         double x = (double)I[q];
         if (al != 0.0) {
-            x = fmax(x + al * (double)dir[q], M);
+            x = fmax(x + al * (double)dir[q], Mb);
             const R xr = (R)x;
             I[q] = xr;
             x = (double)xr;
@@ -615,14 +615,14 @@ template <typename R>
 hipError_t t_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st) {
     hipLaunchKernelGGL(k_grad<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
                        CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), pp(c, 1), c->n, c->np, c->n_pb,
-                       c->M, c->lam, mode);
+                       c->M, c->Mb, c->lam, mode);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t t_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_g),
-                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->M);
+                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->Mb);
     hipLaunchKernelGGL(k_chan_cg_init, dim3(c->nchan), dim3(NTHR), 0, st, pp(c, 0), c->n_pb, c->d_scal,
                        c->d_chan);
     return hipGetLastError();
@@ -682,12 +682,12 @@ hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) 
     const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
     // 1. direction update and projection; partial gt.d
     hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->M);
+                       c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->Mb);
     // 2. restart test
     hipLaunchKernelGGL(k_chan_gtd, gc, blk, 0, st, pp(c, 0), c->n_pb, c->d_scal, c->d_chan);
     // 3. restart, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
     hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir), CP<R>(c->d_beam),
-                       P<R>(c->d_bop), c->d_chan, pp(c, 1), c->n, c->np, c->n_pb, c->M);
+                       P<R>(c->d_bop), c->d_chan, pp(c, 1), c->n, c->np, c->n_pb, c->M, c->Mb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. Vd = F(d)
     return hipSuccess;
@@ -735,7 +735,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         // 8. final update of the step, I <- max(I + alpha d, M), entropy partial
         hipLaunchKernelGGL(k_cg_update<R>, gp, blk, 0, st, P<R>(I), CP<R>(c->d_dir), lsb(c, 1 - last),
                            pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->M,
-                           c->lam);
+                           c->Mb, c->lam);
         // 9. R <- R + alpha Vd, chi^2 partials
         if (c->n_visit)
             hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_ib,
@@ -746,7 +746,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
     // 11. gradient at the new point, projected gradient, PR partials
     const int last = (LS_STEPS - 1) % 2;
     hipLaunchKernelGGL(k_grad<R>, gp, blk, 0, st, c->d_gpart, c->d_slot_base, CP<R>(c->d_beam), CP<R>(I),
-                       P<R>(c->d_g), P<R>(c->d_gt), pp(c, last), c->n, c->np, c->n_pb, c->M, c->lam, 2);
+                       P<R>(c->d_g), P<R>(c->d_gt), pp(c, last), c->n, c->np, c->n_pb, c->M, c->Mb, c->lam, 2);
     // 12. beta and scalars
     hipLaunchKernelGGL(k_chan_beta, gc, blk, 0, st, c->d_vispart, c->d_vis_base, pp(c, 1 - last), pp(c, last),
                        c->n_pb, c->lam, c->d_scal, c->d_chan, user);

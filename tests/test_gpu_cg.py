@@ -1,0 +1,203 @@
+"""Projected CG on the GPU against the oracle's CG, graph replay, checkpoint
+and resume, determinism, channel batching with uneven and empty channels."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cg as ocg
+from _common import TOL, Problem, flush, rel, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_cg(prob, c, iters, I0):
+    ch = prob.chans[c]
+    p = ocg.Problem(prob.n, prob.cell, ch["u"], ch["v"], ch["vis"], ch["w"], prob.beam(c), prob.M, prob.lam)
+    return ocg.projected_cg(p, iters, I0=I0)
+
+
+# CG trajectory tolerances: FP64 rounding and the fixed-count line search
+# leave ~1e-10 differences that the iteration propagates; the FP32 path
+# carries its 1e-7-level evaluation error through the same iteration.
+CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7}, "fp32": {"phi": 1e-5, "img": 1e-3}}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_trajectory_c1(prec):
+    _cuda()
+    ds = synth.make_config(1)
+    iters = ds.cg_iters
+    flush(f"cg trajectory c1 {prec} {iters} iterations")
+    prob = Problem.from_dataset(ds)
+    I_ref, traj = _oracle_cg(prob, 0, iters, None)
+    ctx = prob.context(prec)
+    I = ctx.image()
+    ctx.cg_init(I, init_to_floor=True)
+    hist = ctx.cg_run(I, iters, graph=False).cpu().numpy()
+    ctx.check()
+    phis = hist[:, 0, 0]
+    ref_phis = np.array([t["phi"] for t in traj])
+    assert len(traj) == iters
+    e_phi = np.max(np.abs(phis - ref_phis) / np.abs(ref_phis))
+    e_img = rel(I.cpu().numpy()[0], I_ref)
+    alphas = hist[:, 0, 3]
+    e_alpha = np.max(np.abs(alphas - [t["alpha"] for t in traj]) / np.abs([t["alpha"] for t in traj]))
+    flush(f"  max rel phi {e_phi:.2e}, final image {e_img:.2e}, alpha {e_alpha:.2e}")
+    assert np.all(np.diff(phis) <= 1e-12 * np.abs(phis[:-1]))
+    assert float(I.min()) >= ds.prior_m * (1 - 1e-7)
+    assert np.all(hist[:, 0, 4] >= 0)
+    assert e_phi < CG_TOL[prec]["phi"] and e_img < CG_TOL[prec]["img"]
+
+
+def test_graph_replay_equals_eager():
+    """Each graph replay, with eager work and synchronisation in between,
+    gives the same bits as the eager step."""
+    _cuda()
+    flush("graph replay vs eager, c1 fp32")
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    a = prob.context("fp32")
+    b = prob.context("fp32")
+    Ia, Ib = a.image(), b.image()
+    a.cg_init(Ia)
+    b.cg_init(Ib)
+    for t in range(6):
+        sa = a.cg_step(Ia)
+        hb = b.cg_run(Ib, 1, graph=True)
+        torch.cuda.synchronize()
+        junk = (Ib * 2.0).sum().item()   # eager work between replays
+        assert np.isfinite(junk)
+        assert torch.equal(Ia, Ib), f"replay {t}"
+        assert torch.equal(sa, hb[0]), f"replay {t} scalars"
+    hb = b.cg_run(Ib, 3, graph=True)
+    for t in range(3):
+        sa = a.cg_step(Ia)
+        assert torch.equal(sa, hb[t])
+    assert torch.equal(Ia, Ib)
+
+
+def test_checkpoint_resume_bitwise():
+    _cuda()
+    flush("checkpoint/resume c1 fp32")
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context("fp32")
+    I = ctx.image()
+    ctx.cg_init(I)
+    ctx.cg_run(I, 4, graph=False)
+    blob = ctx.get_state()
+    I_save = I.clone()
+    ctx.cg_run(I, 4, graph=False)
+    I_straight = I.clone()
+    I.copy_(I_save)
+    ctx.set_state(blob)
+    ctx.cg_run(I, 4, graph=False)
+    assert torch.equal(I, I_straight)
+
+
+def test_phi_grad_deterministic():
+    _cuda()
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context("fp32")
+    I = torch.tensor(synth.eval_images(ds, "P3"), dtype=torch.float32, device="cuda")
+    s1, g1 = ctx.phi_and_grad(I)
+    s2, g2 = ctx.phi_and_grad(I)
+    assert torch.equal(s1, s2) and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_channel_batching_uneven_and_empty(prec):
+    """Several channels of different sizes and one empty channel in one set
+    of launches: each channel equals its own oracle evaluation; the empty one
+    has chi^2 = 0 and grad = lambda (ln(I/M) + 1)."""
+    _cuda()
+    flush(f"batching {prec}")
+    prob = Problem.random(64, [1500, 0, 333, 4097], seed=11, lam=0.05)
+    ctx = prob.context(prec)
+    img = synth.random_image(64, 12, lo=1e-3, hi=1.0, n_chan=4)
+    I = torch.tensor(img, dtype=ctx.dtype, device="cuda")
+    scal, grad = ctx.phi_and_grad(I)
+    scal, grad = scal.cpu().numpy(), grad.cpu().numpy()
+    Ih = I.cpu().numpy().astype(np.float64)
+    offs = prob.offsets()
+    R = ctx.residual().cpu().numpy()
+    for c in range(4):
+        ref = prob.oracle_phi_grad(c, Ih[c])
+        if c == 1:
+            assert scal[c, 1] == 0.0
+        else:
+            assert abs(scal[c, 1] - ref["chi2"]) < TOL[prec] * ref["chi2"]
+            assert rel(R[offs[c]:offs[c + 1]], ref["R"]) < TOL[prec]
+        assert abs(scal[c, 0] - ref["phi"]) < TOL[prec] * abs(ref["phi"])
+        assert rel(grad[c], ref["grad"]) < TOL[prec], c
+
+
+def test_cg_batched_channels_match_single_channel_runs():
+    """Cube mode: channels are independent, so a batched CG equals separate
+    single-channel CG runs of each channel (up to the split-K chunking of the
+    adjoint, which depends on the total visibility count)."""
+    _cuda()
+    prob = Problem.random(64, [900, 2500, 0], seed=21, lam=0.02)
+    ctx = prob.context("fp64")
+    I = ctx.image()
+    ctx.cg_init(I)
+    hb = ctx.cg_run(I, 5, graph=False).cpu().numpy()
+    for c in (0, 1, 2):
+        single = Problem(prob.n, prob.cell, [prob.chans[c]], prob.M, prob.lam).context("fp64")
+        Is = single.image()
+        single.cg_init(Is)
+        hs = single.cg_run(Is, 5, graph=False).cpu().numpy()
+        assert rel(Is[0].cpu().numpy(), I[c].cpu().numpy()) < 1e-10, c
+        assert np.allclose(hs[:, 0, :6], hb[:, c, :6], rtol=1e-9, atol=1e-300), c
+
+
+def test_phi_function_autograd_fd_fp64():
+    """PhiFunction backward vs central differences of the GPU FP64 Phi."""
+    _cuda()
+    from paper_1703_02920_amd.uvmem import PhiFunction
+    prob = Problem.random(16, [200], seed=31, lam=0.1, fwhm_px=6)
+    ctx = prob.context("fp64")
+    I = torch.tensor(synth.random_image(16, 31, lo=0.05, hi=1.0), dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    phi = PhiFunction.apply(I, ctx)
+    phi.backward()
+    g = I.grad.detach().cpu().numpy()[0]
+    x0 = I.detach().clone()
+    fd = np.zeros((16, 16))
+    for p in range(0, 256, 7):
+        i, j = divmod(p, 16)
+        h = 1e-5 * float(x0[0, i, j])
+        xp = x0.clone(); xp[0, i, j] += h
+        xm = x0.clone(); xm[0, i, j] -= h
+        fp = float(ctx.phi_and_grad(xp)[0][0, 0])
+        fm = float(ctx.phi_and_grad(xm)[0][0, 0])
+        fd[i, j] = (fp - fm) / (2 * h)
+        assert abs(fd[i, j] - g[i, j]) < 1e-6 * max(1.0, abs(g[i, j])), (i, j, fd[i, j], g[i, j])
+
+
+def test_domain_flag_and_errors():
+    _cuda()
+    from paper_1703_02920_amd.uvmem import EDOMAIN, ESTATE, UvmemError
+    prob = Problem.random(64, [300], seed=41)
+    ctx = prob.context("fp32")
+    I = ctx.image(fill=1e-3)
+    I[0, 3, 4] = 0.0
+    ctx.phi_and_grad(I)
+    with pytest.raises(UvmemError) as ei:
+        ctx.check()
+    assert ei.value.code == EDOMAIN
+    ctx.check()          # flag cleared
+    with pytest.raises(UvmemError) as ei:
+        ctx.set_prior(1e-3, 0.1)
+    assert ei.value.code == ESTATE
+    with pytest.raises(UvmemError) as ei:
+        ctx.cg_step(I)
+    assert ei.value.code == ESTATE
