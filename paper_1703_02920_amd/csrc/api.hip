@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -329,7 +330,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     const int tiles = c->adj_nt * c->adj_nt;
     // split-K chunk length: enough workgroups to fill the GPU several times
     // over, chunks of equal length across channels (uneven channels balance)
-    const int64_t target = 2048;
+    int64_t target = 512;
+    if (const char *env = std::getenv("UVMEM_ADJ_WGS")) target = std::max(1L, std::atol(env));
     int64_t klen = (c->ztot * tiles + target - 1) / target;
     klen = std::max<int64_t>(klen, ADJ_KMIN);
     klen = ((klen + 15) / 16) * 16;

@@ -186,8 +186,18 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
         const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const int i = (int)(p / n), j = (int)(p % n);
+        // fixed-order sum over the slots, eight independent loads in flight
+        const double *gp = gpart + (size_t)i * np + j;
         double G = 0.0;
-        for (int s = s0; s < s1; ++s) G += gpart[(size_t)s * np2 + (size_t)i * np + j];
+        int s = s0;
+        for (; s + 8 <= s1; s += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = gp[(size_t)(s + u) * np2];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) G += v[u];
+        }
+        for (; s < s1; ++s) G += gp[(size_t)s * np2];
         const size_t q = (size_t)c * npix + p;
         double gv = (double)beam[q] * G;
         if (mode >= 1) {
