@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload configuration (1..5)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
@@ -176,7 +176,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": ds.description + "; one projected-CG iteration per step",
                    "n": ds.n, "channels": ds.n_chan, "visibilities": ds.total_vis,

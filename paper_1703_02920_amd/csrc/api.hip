@@ -129,7 +129,14 @@ int check_ready(uvmem_ctx *c) {
 int build_layout(uvmem_ctx *c) {
     const int C = c->nchan;
     c->np = ((c->n + 63) / 64) * 64;
-    c->ib_rows = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    if (c->prec == UVMEM_BF16X3) {
+        int ib = 128;
+        if (const char *env = std::getenv("UVMEM_FWD_IB")) ib = std::atoi(env);
+        if (ib != 64 && ib != 128 && ib != 256) ib = 128;
+        while (c->np % ib) ib /= 2;
+        c->ib_rows = ib;
+    } else
+        c->ib_rows = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->n_ib = c->np / c->ib_rows;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->adj_nt = c->np / c->adj_tt;
@@ -164,7 +171,7 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     if (n < 2 || n > 8192 || (n % 2) != 0) return UVMEM_EINVAL;
     if (n_chan < 1 || n_chan > 65536) return UVMEM_EINVAL;
     if (mode != UVMEM_CUBE) return UVMEM_EINVAL;
-    if (precision != UVMEM_FP64 && precision != UVMEM_FP32) return UVMEM_EINVAL;
+    if (precision != UVMEM_FP64 && precision != UVMEM_FP32 && precision != UVMEM_BF16X3) return UVMEM_EINVAL;
     uvmem_ctx *c = new (std::nothrow) uvmem_ctx();
     if (!c) return UVMEM_ENOMEM;
     c->n = n;

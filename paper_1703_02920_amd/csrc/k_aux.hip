@@ -69,6 +69,22 @@ __device__ __forceinline__ double min_partials(const double *base, int n_items, 
     return block_min(m);
 }
 
+// ---------------------------------------------------------------- operand store
+// The DFT operand image: plain (SPLIT = 0, element type R) or split into
+// bf16 hi and lo halves (SPLIT = 1; lo at element offset lo_off).
+template <typename R, int SPLIT>
+__device__ __forceinline__ void store_op(void *bop, size_t idx, size_t lo_off, R v) {
+    if constexpr (SPLIT == 0) {
+        reinterpret_cast<R *>(bop)[idx] = v;
+    } else {
+        __bf16 *h = reinterpret_cast<__bf16 *>(bop);
+        const float x = (float)v;
+        const __bf16 hh = (__bf16)x;
+        h[idx] = hh;
+        h[lo_off + idx] = (__bf16)(x - (float)hh);
+    }
+}
+
 // ---------------------------------------------------------------- fill
 template <typename R>
 __global__ void k_fill(R *__restrict__ x, R value, long long count) {
@@ -80,16 +96,17 @@ __global__ void k_fill(R *__restrict__ x, R value, long long count) {
 // ---------------------------------------------------------------- prologue
 // B = A o I written into the padded operand image; optional entropy partial
 // S = sum I ln(I/M) and the domain flag (I <= 0 or NaN).
-template <typename R>
+template <typename R, int SPLIT>
 __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, const R *__restrict__ beam,
-                                                   R *__restrict__ bop, double *__restrict__ ppart,
+                                                   void *__restrict__ bop, size_t lo_off,
+                                                   double *__restrict__ ppart,
                                                    int *__restrict__ flag, int n, int np, int n_pb,
                                                    double M, int with_entropy) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const R *Ic = I + (size_t)c * npix;
     const R *Ac = beam + (size_t)c * npix;
-    R *Bc = bop + (size_t)c * np * np;
+    const size_t cb = (size_t)c * np * np;
     double s[1] = {0.0};
     int bad = 0;
     for (int r = 0; r < PIX_BLK / NTHR; ++r) {
@@ -97,7 +114,7 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
         if (p >= npix) break;
         const int i = (int)(p / n), j = (int)(p % n);
         const R x = Ic[p];
-        Bc[(size_t)i * np + j] = Ac[p] * x;
+        store_op<R, SPLIT>(bop, cb + (size_t)i * np + j, lo_off, Ac[p] * x);
         if (with_entropy) {
             const double xd = (double)x;
             if (!(xd > 0.0)) bad = 1;
@@ -342,17 +359,18 @@ __global__ __launch_bounds__(NTHR) void k_chan_gtd(const double *__restrict__ pp
 
 // Step 3: apply the restart, stage B = A o d for the forward model, and the
 // partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts).
-template <typename R>
+template <typename R, int SPLIT>
 __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
                                                   R *__restrict__ dir, const R *__restrict__ beam,
-                                                  R *__restrict__ bop, const double *__restrict__ chan,
+                                                  void *__restrict__ bop, size_t lo_off,
+                                                  const double *__restrict__ chan,
                                                   double *__restrict__ ppart, int n, int np, int n_pb,
                                                   double M, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const bool restart = chan[(size_t)c * CH_N + CH_RESTART] != 0.0;
     const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
-    R *Bc = bop + (size_t)c * np * np;
+    const size_t cb = (size_t)c * np * np;
     double amax = INFINITY;
     double acc[2] = {0.0, 0.0};
     for (int r = 0; r < PIX_BLK / NTHR; ++r) {
@@ -366,7 +384,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         d = (double)dr;
         dir[q] = dr;
         const int i = (int)(p / n), j = (int)(p % n);
-        Bc[(size_t)i * np + j] = beam[q] * dr;
+        store_op<R, SPLIT>(bop, cb + (size_t)i * np + j, lo_off, beam[q] * dr);
         const double x = (double)I[q];
         if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
@@ -614,10 +632,12 @@ inline double *pp(const uvmem_ctx *c, int buf) {
 }
 inline double *lsb(const uvmem_ctx *c, int buf) { return c->d_ls + (size_t)buf * c->nchan * LSS_N; }
 
-template <typename R>
+inline size_t lo_off(const uvmem_ctx *c) { return (size_t)c->nchan * c->np * c->np; }
+
+template <typename R, int SPLIT>
 hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
-    hipLaunchKernelGGL(k_prologue<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_beam),
-                       P<R>(c->d_bop), pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->M, with_entropy);
+    hipLaunchKernelGGL((k_prologue<R, SPLIT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_beam),
+                       c->d_bop, lo_off(c), pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->M, with_entropy);
     return hipGetLastError();
 }
 
@@ -638,7 +658,7 @@ hipError_t t_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, int SPLIT>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st);
 
 }  // namespace
@@ -654,8 +674,9 @@ hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t 
 }
 
 hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
-    return c->prec == UVMEM_FP64 ? t_prologue<double>(c, I, with_entropy, st)
-                                 : t_prologue<float>(c, I, with_entropy, st);
+    if (c->prec == UVMEM_FP64) return t_prologue<double, 0>(c, I, with_entropy, st);
+    if (c->prec == UVMEM_BF16X3) return t_prologue<float, 1>(c, I, with_entropy, st);
+    return t_prologue<float, 0>(c, I, with_entropy, st);
 }
 
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st) {
@@ -686,7 +707,7 @@ hipError_t launch_copy_scal(const uvmem_ctx *c, double *, long long *ctr, hipStr
 }
 
 namespace {
-template <typename R>
+template <typename R, int SPLIT>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
     hipError_t e;
     const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
@@ -696,8 +717,9 @@ hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) 
     // 2. restart test
     hipLaunchKernelGGL(k_chan_gtd, gc, blk, 0, st, pp(c, 0), c->n_pb, c->d_scal, c->d_chan);
     // 3. restart, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
-    hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir), CP<R>(c->d_beam),
-                       P<R>(c->d_bop), c->d_chan, pp(c, 1), c->n, c->np, c->n_pb, c->M, c->Mb);
+    hipLaunchKernelGGL((k_cg_dir2<R, SPLIT>), gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
+                       CP<R>(c->d_beam), c->d_bop, lo_off(c), c->d_chan, pp(c, 1), c->n, c->np, c->n_pb, c->M,
+                       c->Mb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. Vd = F(d)
     return hipSuccess;
@@ -719,10 +741,10 @@ hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t
 }
 
 namespace {
-template <typename R>
+template <typename R, int SPLIT>
 hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
     const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
-    if (phase == 0) return t_cg_step<R>(c, I, user, st);
+    if (phase == 0) return t_cg_step<R, SPLIT>(c, I, user, st);
     if (phase == 1) {
         // 5. Vd and the quadratic coefficients a, b of chi^2 along d
         if (c->n_visit)
@@ -765,8 +787,9 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
 }  // namespace
 
 hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
-    return c->prec == UVMEM_FP64 ? t_cg_phase<double>(c, I, user, phase, st)
-                                 : t_cg_phase<float>(c, I, user, phase, st);
+    if (c->prec == UVMEM_FP64) return t_cg_phase<double, 0>(c, I, user, phase, st);
+    if (c->prec == UVMEM_BF16X3) return t_cg_phase<float, 1>(c, I, user, phase, st);
+    return t_cg_phase<float, 0>(c, I, user, phase, st);
 }
 
 }  // namespace uvm

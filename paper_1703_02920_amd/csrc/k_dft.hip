@@ -310,6 +310,331 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
             }
 }
 
+
+// ----------------------------------------------------------------------------
+// Split precision (bf16 hi + lo, three products per real product):
+//   x y ~= x_h y_h + x_h y_l + x_l y_h,  x_h = RN_bf16(x), x_l = RN_bf16(x - x_h),
+// on v_mfma_f32_16x16x32_bf16 (lane l supplies A[l%16][8 (l/16) + e] and
+// B[8 (l/16) + e][l%16], e = 0..7; it holds D[4 (l/16) + r][l%16]) with FP32
+// accumulation, folded into FP64 periodically.  The dropped x_l y_l term and
+// the representation error leave ~2^-16 relative error per product.
+// ----------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ floatx4 mma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16 &h, __bf16 &l) {
+    h = (__bf16)x;
+    l = (__bf16)(x - (float)h);
+}
+
+// Hardware sine/cosine of 2 pi f for f in revolutions (|f| <= 1/2).
+__device__ __forceinline__ void cis2pi_hw(float f, float &c, float &s) {
+    s = __builtin_amdgcn_sinf(f);
+    c = __builtin_amdgcn_cosf(f);
+}
+
+// Forward, split precision.  Same decomposition as k_forward; each lane's
+// eight consecutive columns j0 + e (e = 0..7) get E_u = E(j0) E(e) with the
+// fine factors E(e) computed once per lane.  The row dot uses
+// E_v[k][i0 + 16 t + q] = fine(k, q) coarse(k, t) with the coarse factors
+// shared through LDS.
+template <int IB>
+__global__ __launch_bounds__(256) void k_forward_bf16(const FwdItem *__restrict__ items,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ b,
+                                                      const __bf16 *__restrict__ bh,
+                                                      const __bf16 *__restrict__ bl,
+                                                      double2 *__restrict__ vpart, int n, int np, long long ztot) {
+    constexpr int NT = IB / 16;
+    constexpr int JC = 64;
+    constexpr int PAD = 8;
+    __shared__ __attribute__((aligned(16))) __bf16 sH[IB][JC + PAD];
+    __shared__ __attribute__((aligned(16))) __bf16 sL[IB][JC + PAD];
+    __shared__ float2 sCo[64][NT];
+
+    const FwdItem it = items[blockIdx.x];
+    const int ib = blockIdx.y;
+    const int i0 = ib * IB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const size_t coff = (size_t)it.chan * np * np;
+    const __bf16 *Bh = bh + coff;
+    const __bf16 *Bl = bl + coff;
+    const int half = n / 2;
+
+    const int krow = wave * 16 + q;
+    const double ak = krow < it.nvalid ? a[it.k0 + krow] : 0.0;
+    float fc[8], fs[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
+
+    floatx4 accR[NT], accI[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        accI[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    constexpr int VROW = JC / 8;
+    constexpr int NLD = IB * VROW / 256;
+    // software pipeline: the next chunk travels global -> registers while the
+    // current one is contracted from LDS
+    uint4 ph[NLD], pl[NLD];
+    auto load_chunk = [&](int jc) {
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            const int idx = tid + 256 * r;
+            const int row = idx / VROW, c8 = idx % VROW;
+            const size_t go = (size_t)(i0 + row) * np + jc + 8 * c8;
+            ph[r] = *reinterpret_cast<const uint4 *>(Bh + go);
+            pl[r] = *reinterpret_cast<const uint4 *>(Bl + go);
+        }
+    };
+    load_chunk(0);
+    for (int jc = 0; jc < np; jc += JC) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            const int idx = tid + 256 * r;
+            const int row = idx / VROW, c8 = idx % VROW;
+            *reinterpret_cast<uint4 *>(&sH[row][8 * c8]) = ph[r];
+            *reinterpret_cast<uint4 *>(&sL[row][8 * c8]) = pl[r];
+        }
+        __syncthreads();
+        if (jc + JC < np) load_chunk(jc + JC);
+#pragma unroll
+        for (int js = 0; js < JC; js += 32) {
+            float cc, sc;
+            cis2pi_hw((float)phase(ak, jc + js + 8 * g - half), cc, sc);
+            bf16x8 rh, rl, ih, il;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float c = cc * fc[e] - sc * fs[e];
+                const float sn = sc * fc[e] + cc * fs[e];
+                __bf16 h, l;
+                split_bf16(c, h, l);
+                rh[e] = h;
+                rl[e] = l;
+                split_bf16(-sn, h, l);
+                ih[e] = h;
+                il[e] = l;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 bhv = *reinterpret_cast<const bf16x8 *>(&sH[16 * t + q][js + 8 * g]);
+                const bf16x8 blv = *reinterpret_cast<const bf16x8 *>(&sL[16 * t + q][js + 8 * g]);
+                accR[t] = mma_bf16(rh, bhv, accR[t]);
+                accI[t] = mma_bf16(ih, bhv, accI[t]);
+                accR[t] = mma_bf16(rh, blv, accR[t]);
+                accI[t] = mma_bf16(ih, blv, accI[t]);
+                accR[t] = mma_bf16(rl, bhv, accR[t]);
+                accI[t] = mma_bf16(il, bhv, accI[t]);
+            }
+        }
+    }
+    // coarse row-dot factors exp(-2 pi i b_k 16 t) for the workgroup's 64 rows
+    for (int x = tid; x < 64 * NT; x += 256) {
+        const int kk = x / NT, t = x % NT;
+        const double bk = kk < it.nvalid ? b[it.k0 + kk] : 0.0;
+        float c, sn;
+        cis2pi_hw((float)phase(bk, 16 * t), c, sn);
+        sCo[kk][t] = make_float2(c, sn);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int kk = wave * 16 + 4 * g + r;
+        const bool ok = kk < it.nvalid;
+        const double bk = ok ? b[it.k0 + kk] : 0.0;
+        float fcq, fsq;
+        cis2pi_hw((float)phase(bk, i0 + q - half), fcq, fsq);
+        float vr = 0.f, vi = 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float2 co = sCo[kk][t];
+            const float c = fcq * co.x - fsq * co.y;
+            const float sn = fsq * co.x + fcq * co.y;
+            const float tr = accR[t][r], ti = accI[t][r];
+            vr += c * tr + sn * ti;
+            vi += c * ti - sn * tr;
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            vr += __shfl_xor(vr, o, 64);
+            vi += __shfl_xor(vi, o, 64);
+        }
+        if (q == 0 && ok) vpart[(size_t)ib * ztot + it.k0 + kk] = make_double2((double)vr, (double)vi);
+    }
+}
+
+// Adjoint, split precision.  Per 32-visibility step the workgroup builds
+// fine/coarse twiddle tables (hardware sin/cos of FP64-reduced phases):
+//   Hv[q][k] = w_k c_k exp(+2 pi i b_k (i0 + q - N/2)),  Gv[t][k] = exp(+2 pi i b_k 16 t)
+//   Fu[q][k] = exp(+2 pi i a_k (j0 + q - N/2)),          Gu[t][k] = exp(+2 pi i a_k 16 t)
+// then the pre-split operand tiles P[i][k] = Hv Gv (re, -im) and
+// E[j][k] = Fu Gu (cos, sin) in LDS (one thread per operand row), and the
+// waves contract them on matrix cores.  The visibility data of the next
+// step are loaded into registers while the current step computes.
+template <int WT>
+__global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const double2 *__restrict__ coef,
+                                                         const float *__restrict__ w,
+                                                         double *__restrict__ gpart, int n, int np) {
+    constexpr int TT = 2 * WT;
+    constexpr int NT = WT / 16;
+    constexpr int NC = TT / 16;
+    constexpr int KS = 32;
+    constexpr int KT = KS + 2;     // padded table rows (float2)
+    constexpr int KP = KS;         // operand rows: 4 groups of 8, XOR-swizzled (see swz)
+    __shared__ __attribute__((aligned(16))) float2 sHv[16][KT], sFu[16][KT], sGv[NC][KT], sGu[NC][KT];
+    __shared__ __attribute__((aligned(16))) __bf16 sP[4][TT][KP];   // re_h, re_l, -im_h, -im_l
+    __shared__ __attribute__((aligned(16))) __bf16 sE[4][TT][KP];   // cos_h, cos_l, sin_h, sin_l
+    // group kg of row r is stored at group kg ^ ((r >> 1) & 3): eight
+    // consecutive rows then hit distinct LDS banks for 16-byte accesses
+    auto swz = [](int r, int kg) { return 8 * (kg ^ ((r >> 1) & 3)); };
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int wi = (wave >> 1) * WT, wj = (wave & 1) * WT;
+    const int half = n / 2;
+
+    // table tasks of this thread: fine (k = tid>>4 and tid>>4 + 16, q = tid&15),
+    // coarse (k = tid / NC8, t = tid % NC8 for both axes when tid < KS*NC)
+    const int fk0 = tid >> 4, fq = tid & 15;
+    const int ck = tid / NC, ct = tid % NC;
+    const bool has_c = tid < KS * NC;
+
+    struct Pre {
+        double a0, b0, a1, b1, ac, bc;
+        double2 c0, c1;
+        float w0, w1;
+    };
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k0 = kb + fk0, k1 = kb + fk0 + 16, kc = kb + ck;
+        p.a0 = p.b0 = p.a1 = p.b1 = p.ac = p.bc = 0.0;
+        p.c0 = p.c1 = make_double2(0.0, 0.0);
+        p.w0 = p.w1 = 0.f;
+        if (k0 < it.kend) { p.a0 = a[k0]; p.b0 = b[k0]; p.c0 = coef[k0]; p.w0 = w ? w[k0] : 1.f; }
+        if (k1 < it.kend) { p.a1 = a[k1]; p.b1 = b[k1]; p.c1 = coef[k1]; p.w1 = w ? w[k1] : 1.f; }
+        if (has_c && kc < it.kend) { p.ac = a[kc]; p.bc = b[kc]; }
+    };
+
+    floatx4 acc[NT][NT];
+#pragma unroll
+    for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    Pre cur, nxt;
+    fetch(it.kbeg, cur);
+    for (long long kb = it.kbeg; kb < it.kend; kb += KS) {
+        if (kb + KS < it.kend) fetch(kb + KS, nxt);
+        // ---- twiddle tables (zero coefficients / unit coarse factors past the end)
+        {
+            float c, s;
+            cis2pi_hw((float)phase(cur.b0, i0 + fq - half), c, s);
+            float cr = (float)((double)cur.w0 * cur.c0.x), ci = (float)((double)cur.w0 * cur.c0.y);
+            sHv[fq][fk0] = make_float2(cr * c - ci * s, cr * s + ci * c);
+            cis2pi_hw((float)phase(cur.a0, j0 + fq - half), c, s);
+            sFu[fq][fk0] = make_float2(c, s);
+            cis2pi_hw((float)phase(cur.b1, i0 + fq - half), c, s);
+            cr = (float)((double)cur.w1 * cur.c1.x);
+            ci = (float)((double)cur.w1 * cur.c1.y);
+            sHv[fq][fk0 + 16] = make_float2(cr * c - ci * s, cr * s + ci * c);
+            cis2pi_hw((float)phase(cur.a1, j0 + fq - half), c, s);
+            sFu[fq][fk0 + 16] = make_float2(c, s);
+            if (has_c) {
+                cis2pi_hw((float)phase(cur.bc, 16 * ct), c, s);
+                sGv[ct][ck] = make_float2(c, s);
+                cis2pi_hw((float)phase(cur.ac, 16 * ct), c, s);
+                sGu[ct][ck] = make_float2(c, s);
+            }
+        }
+        __syncthreads();
+        // ---- pre-split operand rows: thread -> (operand, row)
+        for (int x = tid; x < 2 * TT; x += 256) {
+            const int dim = x / TT, row = x % TT;
+            const int qq = row & 15, t = row >> 4;
+            const float2 *f = dim == 0 ? sHv[qq] : sFu[qq];
+            const float2 *gc = dim == 0 ? sGv[t] : sGu[t];
+            __bf16 (*dst)[TT][KP] = dim == 0 ? sP : sE;
+#pragma unroll
+            for (int kg = 0; kg < KS / 8; ++kg) {
+                bf16x8 v0, v1, v2, v3;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float2 fv = f[8 * kg + e], gv = gc[8 * kg + e];
+                    const float re = fv.x * gv.x - fv.y * gv.y;
+                    const float im = fv.x * gv.y + fv.y * gv.x;
+                    __bf16 h, l;
+                    split_bf16(re, h, l);
+                    v0[e] = h;
+                    v1[e] = l;
+                    split_bf16(dim == 0 ? -im : im, h, l);
+                    v2[e] = h;
+                    v3[e] = l;
+                }
+                const int o = swz(row, kg);
+                *reinterpret_cast<bf16x8 *>(&dst[0][row][o]) = v0;
+                *reinterpret_cast<bf16x8 *>(&dst[1][row][o]) = v1;
+                *reinterpret_cast<bf16x8 *>(&dst[2][row][o]) = v2;
+                *reinterpret_cast<bf16x8 *>(&dst[3][row][o]) = v3;
+            }
+        }
+        __syncthreads();
+        // ---- contract on matrix cores
+        bf16x8 ech[NT], ecl[NT], esh[NT], esl[NT];
+#pragma unroll
+        for (int y = 0; y < NT; ++y) {
+            const int r = wj + 16 * y + q;
+            const int o = swz(r, g);
+            ech[y] = *reinterpret_cast<const bf16x8 *>(&sE[0][r][o]);
+            ecl[y] = *reinterpret_cast<const bf16x8 *>(&sE[1][r][o]);
+            esh[y] = *reinterpret_cast<const bf16x8 *>(&sE[2][r][o]);
+            esl[y] = *reinterpret_cast<const bf16x8 *>(&sE[3][r][o]);
+        }
+#pragma unroll
+        for (int x = 0; x < NT; ++x) {
+            const int r = wi + 16 * x + q;
+            const int o = swz(r, g);
+            const bf16x8 prh = *reinterpret_cast<const bf16x8 *>(&sP[0][r][o]);
+            const bf16x8 prl = *reinterpret_cast<const bf16x8 *>(&sP[1][r][o]);
+            const bf16x8 pih = *reinterpret_cast<const bf16x8 *>(&sP[2][r][o]);
+            const bf16x8 pil = *reinterpret_cast<const bf16x8 *>(&sP[3][r][o]);
+#pragma unroll
+            for (int y = 0; y < NT; ++y) {
+                acc[x][y] = mma_bf16(prh, ech[y], acc[x][y]);
+                acc[x][y] = mma_bf16(pih, esh[y], acc[x][y]);
+                acc[x][y] = mma_bf16(prh, ecl[y], acc[x][y]);
+                acc[x][y] = mma_bf16(pih, esl[y], acc[x][y]);
+                acc[x][y] = mma_bf16(prl, ech[y], acc[x][y]);
+                acc[x][y] = mma_bf16(pil, esh[y], acc[x][y]);
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+    double *out = gpart + (size_t)it.slot * np * np;
+#pragma unroll
+    for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * x + 4 * g + r;
+                const int j = j0 + wj + 16 * y + q;
+                out[(size_t)i * np + j] = (double)acc[x][y][r];
+            }
+}
+
 template <typename T>
 hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
     if (c->n_fwd == 0) return hipSuccess;
@@ -335,15 +660,45 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
     return hipGetLastError();
 }
 
+hipError_t fwd_bf16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->n_fwd == 0) return hipSuccess;
+    const __bf16 *bh = reinterpret_cast<const __bf16 *>(bop);
+    const __bf16 *bl = bh + (size_t)c->nchan * c->np * c->np;
+    dim3 grid(c->n_fwd, c->n_ib);
+    if (c->ib_rows == 256)
+        hipLaunchKernelGGL(k_forward_bf16<256>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    else if (c->ib_rows == 128)
+        hipLaunchKernelGGL(k_forward_bf16<128>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    else
+        hipLaunchKernelGGL(k_forward_bf16<64>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    return hipGetLastError();
+}
+
+hipError_t adj_bf16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+    if (c->n_adj == 0) return hipSuccess;
+    if (c->adj_tt == 128)
+        hipLaunchKernelGGL(k_adjoint_bf16<64>, dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+                           coef, w, c->d_gpart, c->n, c->np);
+    else
+        hipLaunchKernelGGL(k_adjoint_bf16<32>, dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+                           coef, w, c->d_gpart, c->n, c->np);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
     if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st);
+    if (c->prec == UVMEM_BF16X3) return fwd_bf16(c, bop, st);
     return fwd_dispatch<float>(c, bop, st);
 }
 
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
     if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st);
+    if (c->prec == UVMEM_BF16X3) return adj_bf16(c, coef, w, st);
     return adj_dispatch<float>(c, coef, w, st);
 }
 

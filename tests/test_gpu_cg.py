@@ -25,11 +25,18 @@ def _oracle_cg(prob, c, iters, I0):
 
 # CG trajectory tolerances: FP64 rounding and the fixed-count line search
 # leave ~1e-10 differences that the iteration propagates; the FP32 path
-# carries its 1e-7-level evaluation error through the same iteration.
-CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7}, "fp32": {"phi": 1e-5, "img": 1e-3}}
+# carries its 1e-7-level evaluation error through the same iteration.  On
+# this problem every step after the first ends on alpha_max (one more pixel
+# reaches the floor), and alpha_max = min (I - M)/(-d) is decided by pixels
+# just above the floor: the split path's ~1e-5 evaluation error changes
+# which pixel binds, so its trajectory is held to the first step tightly and
+# to the whole run and final image loosely.
+CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7, "first": 1e-12},
+          "fp32": {"phi": 1e-5, "img": 1e-3, "first": 1e-6},
+          "bf16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4}}
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_cg_trajectory_c1(prec):
     _cuda()
     ds = synth.make_config(1)
@@ -50,10 +57,15 @@ def test_cg_trajectory_c1(prec):
     alphas = hist[:, 0, 3]
     e_alpha = np.max(np.abs(alphas - [t["alpha"] for t in traj]) / np.abs([t["alpha"] for t in traj]))
     flush(f"  max rel phi {e_phi:.2e}, final image {e_img:.2e}, alpha {e_alpha:.2e}")
+    flush("  alpha gpu/oracle: " + " ".join(f"{x:.4f}" for x in alphas / np.array([t["alpha"] for t in traj])))
+    flush("  phi rel err: " + " ".join(f"{x:.1e}" for x in np.abs(phis - ref_phis) / np.abs(ref_phis)))
+    flush("  alpha_max hit oracle: " + "".join("1" if t["alpha"] == t["alpha_max"] else "0" for t in traj))
+    flush("  alpha_max hit gpu:    " + "".join("1" if x == y else "0" for x, y in zip(alphas, hist[:, 0, 6])))
     assert np.all(np.diff(phis) <= 1e-12 * np.abs(phis[:-1]))
     assert float(I.min()) >= ds.prior_m * (1 - 1e-7)
     assert np.all(hist[:, 0, 4] >= 0)
     assert e_phi < CG_TOL[prec]["phi"] and e_img < CG_TOL[prec]["img"]
+    assert abs(phis[0] - ref_phis[0]) < CG_TOL[prec]["first"] * abs(ref_phis[0])
 
 
 def test_graph_replay_equals_eager():
@@ -113,7 +125,7 @@ def test_phi_grad_deterministic():
     assert torch.equal(s1, s2) and torch.equal(g1, g2)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_channel_batching_uneven_and_empty(prec):
     """Several channels of different sizes and one empty channel in one set
     of launches: each channel equals its own oracle evaluation; the empty one
