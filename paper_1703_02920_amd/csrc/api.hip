@@ -141,6 +141,8 @@ int build_layout(uvmem_ctx *c) {
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->adj_nt = c->np / c->adj_tt;
     c->n_pb = (int)(((int64_t)c->n * c->n + PIX_BLK - 1) / PIX_BLK);
+    c->ls_steps = LS_STEPS;
+    if (const char *env = std::getenv("UVMEM_LS_STEPS")) c->ls_steps = std::max(1, std::min(64, std::atoi(env)));
     c->off.assign(C + 1, 0);
     for (int ch = 0; ch < C; ++ch) c->off[ch + 1] = c->off[ch] + c->nvis[ch];
     c->ztot = c->off[C];

@@ -21,11 +21,14 @@ constexpr int PIX_BLK = 1024;
 // Minimum visibilities per adjoint split-K chunk (multiple of 16).
 constexpr int ADJ_KMIN = 256;
 // Partial-sum slots per pixel / visibility item.
-constexpr int NPART = 4;
+constexpr int NPART = 8;
+// Trial steps evaluated per line-search pass.
+constexpr int LS_K = 4;
 // Relative tolerance that decides "pixel at the bound I <= M (1 + tol)".
 constexpr double BOUND_TOL = 1e-12;
-// Fixed number of line-search launches per CG step (Newton / bisection).
-constexpr int LS_STEPS = 12;
+// Default number of line-search passes per CG step; a channel whose search
+// has converged skips the remaining passes.
+constexpr int LS_STEPS = 6;
 
 // One forward workgroup: FWD_KV visibilities [k0, k0 + nvalid) of a channel.
 struct FwdItem {
@@ -55,16 +58,19 @@ struct VisItem {
 
 // Device-side line-search state of one channel (double[LSS_N]).
 enum {
-    LSS_PHASE = 0,   // 0 = check alpha_max, 1 = grow bracket, 2 = Newton, 3 = done
-    LSS_LO,
-    LSS_HI,          // < 0 means +infinity
-    LSS_TRY,         // trial step evaluated by the next pixel pass
-    LSS_ALPHA,       // accepted step once done
+    LSS_PHASE = 0,   // 0 = searching, 3 = done
+    LSS_LO,          // largest step known to have phi' < 0
+    LSS_HI,          // bracket end (< 0 means +infinity)
+    LSS_FLO, LSS_HLO,   // phi', phi'' at LO
+    LSS_FHI, LSS_HHI,   // phi', phi'' at HI (when HI_EVAL)
+    LSS_HI_EVAL,     // 1 once phi'(HI) > 0 is known
+    LSS_T0,          // LS_K trial steps (ascending) evaluated by the next pass
+    LSS_ALPHA = LSS_T0 + 4,   // accepted step once done
     LSS_A,           // sum w |Vd|^2
     LSS_B,           // sum w Re(conj(R) Vd)
     LSS_AMAX,        // alpha_max (< 0 means +infinity)
-    LSS_STOP,        // 1 if the channel has stopped (no descent / zero gradient)
-    LSS_N = 12
+    LSS_STOP,        // 1 if the channel has stopped
+    LSS_N = 24
 };
 
 // Per-channel flags / CG bookkeeping kept on the device (double).
@@ -104,6 +110,7 @@ struct uvmem_ctx {
     int adj_tt = 0, adj_nt = 0;        // adjoint tile side, tiles per side
     int n_slots = 0;
     int n_pb = 0;                      // pixel blocks per channel
+    int ls_steps = 8;                  // line-search passes per CG step
     std::vector<int> h_slot_base;      // nchan+1
     std::vector<int> h_vis_base;       // nchan+1
     int n_fwd = 0, n_adj = 0, n_visit = 0;

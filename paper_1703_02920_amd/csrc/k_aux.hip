@@ -198,23 +198,43 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
     const long long npix = (long long)n * n;
     const int s0 = slot_base[c], s1 = slot_base[c + 1];
     const size_t np2 = (size_t)np * np;
-    double acc[2] = {0.0, 0.0};
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
+    constexpr int RP = PIX_BLK / NTHR;
+    // fixed-order sum over the slots for the thread's RP pixels, 8 slots x RP
+    // pixels of independent loads in flight
+    size_t off[RP];
+    bool okp[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
         const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
-        if (p >= npix) break;
-        const int i = (int)(p / n), j = (int)(p % n);
-        // fixed-order sum over the slots, eight independent loads in flight
-        const double *gp = gpart + (size_t)i * np + j;
-        double G = 0.0;
-        int s = s0;
-        for (; s + 8 <= s1; s += 8) {
-            double v[8];
+        okp[r] = p < npix;
+        const long long pc = okp[r] ? p : 0;
+        off[r] = (size_t)(pc / n) * np + (size_t)(pc % n);
+    }
+    double Gs[RP];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = gp[(size_t)(s + u) * np2];
+    for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {
+        double v[RP][8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) G += v[u];
-        }
-        for (; s < s1; ++s) G += gp[(size_t)s * np2];
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[r][u] = gpart[(size_t)(s + u) * np2 + off[r]];
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
+    }
+    for (; s < s1; ++s) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) Gs[r] += gpart[(size_t)s * np2 + off[r]];
+    }
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+        if (!okp[r]) break;
+        const double G = Gs[r];
         const size_t q = (size_t)c * npix + p;
         double gv = (double)beam[q] * G;
         if (mode >= 1) {
@@ -340,36 +360,34 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
     if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
 }
 
-// Step 2: restart test per channel.
-__global__ __launch_bounds__(NTHR) void k_chan_gtd(const double *__restrict__ ppart, int n_pb,
-                                                   const double *__restrict__ scal, double *__restrict__ chan) {
-    const int c = blockIdx.x;
-    double gtd[1];
-    sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
-    if (threadIdx.x == 0) {
-        double *ch = chan + (size_t)c * CH_N;
-        const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
-        if (gg == 0.0) ch[CH_STOP] = 1.0;
-        const bool restart = gtd[0] >= 0.0;
-        ch[CH_RESTART] = restart ? 1.0 : 0.0;
-        ch[CH_GTD] = restart ? -gg : gtd[0];
-        ch[CH_GG_OLD] = gg;
-    }
-}
-
 // Step 3: apply the restart, stage B = A o d for the forward model, and the
 // partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts).
 template <typename R, int SPLIT>
 __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
                                                   R *__restrict__ dir, const R *__restrict__ beam,
                                                   void *__restrict__ bop, size_t lo_off,
-                                                  const double *__restrict__ chan,
+                                                  const double *__restrict__ pp_gtd,
+                                                  const double *__restrict__ scal,
+                                                  double *__restrict__ chan,
                                                   double *__restrict__ ppart, int n, int np, int n_pb,
                                                   double M, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
-    const bool restart = chan[(size_t)c * CH_N + CH_RESTART] != 0.0;
-    const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
+    // step 2, recomputed by every workgroup of the channel: restart with
+    // d = -gt when gt.d >= 0; stop when the projected gradient is zero
+    double gtd[1];
+    sum_partials<1>(pp_gtd + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
+    const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
+    const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0 || gg == 0.0;
+    const bool restart = gtd[0] >= 0.0;
+    __syncthreads();
+    if (pb == 0 && threadIdx.x == 0) {
+        double *ch = chan + (size_t)c * CH_N;
+        if (stop) ch[CH_STOP] = 1.0;
+        ch[CH_RESTART] = restart ? 1.0 : 0.0;
+        ch[CH_GTD] = restart ? -gg : gtd[0];
+        ch[CH_GG_OLD] = gg;
+    }
     const size_t cb = (size_t)c * np * np;
     double amax = INFINITY;
     double acc[2] = {0.0, 0.0};
@@ -403,124 +421,197 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
 // ---- line search: exact minimisation of the convex phi on [0, alpha_max]
 //   phi'(al)  = b + a al + lambda sum d (ln((I + al d)/M) + 1)
 //   phi''(al) = a + lambda sum d^2 / (I + al d)
-// State machine shared by all workgroups of a channel (see update_ls).
-enum { PH_CHECK = 0, PH_GROW = 1, PH_NEWTON = 2, PH_DONE = 3 };
+// phi' is increasing; its entropy part is concave (log-like), so a single
+// Newton sequence from the left creeps.  Each pass evaluates phi', phi'' at
+// LS_K trial steps inside the current bracket [LO, HI] -- Newton steps from
+// both ends, the secant step and fill-in points, or a geometric ladder while
+// HI is unbounded -- and keeps the smallest bracket.  The state is advanced
+// identically by every workgroup of the channel.
+enum { PH_SEARCH = 0, PH_DONE = 3 };
 
 __device__ __forceinline__ void ls_finish(double *st, double al) {
     st[LSS_PHASE] = PH_DONE;
     st[LSS_ALPHA] = al;
-    st[LSS_TRY] = al;
+#pragma unroll
+    for (int m = 0; m < LS_K; ++m) st[LSS_T0 + m] = al;
 }
 
-// Advance the state given phi'(try) = f1 and phi''(try) = f2.
-__device__ void update_ls(double *st, double f1, double f2) {
-    const int ph = (int)st[LSS_PHASE];
-    const double t = st[LSS_TRY];
-    if (ph == PH_DONE) return;
-    if (ph == PH_CHECK) {
-        if (f1 <= 0.0) { ls_finish(st, t); return; }
-        st[LSS_HI] = t;
-        st[LSS_PHASE] = PH_NEWTON;
-        // restart Newton from the root of the chi^2 part when inside the bracket
-        const double a = st[LSS_A], b = st[LSS_B];
-        double nxt = 0.5 * (st[LSS_LO] + st[LSS_HI]);
-        if (a > 0.0) {
-            const double gsx = -b / a;
-            if (gsx > st[LSS_LO] && gsx < st[LSS_HI]) nxt = gsx;
-        }
-        st[LSS_TRY] = nxt;
-        return;
-    }
-    if (f1 == 0.0) { ls_finish(st, t); return; }
-    if (f1 > 0.0) st[LSS_HI] = t; else st[LSS_LO] = t;
-    if (ph == PH_GROW && f1 < 0.0) {
-        double nxt = f2 > 0.0 ? t - f1 / f2 : 2.0 * t;
-        if (!(nxt > t) || !isfinite(nxt)) nxt = 2.0 * t;
-        st[LSS_TRY] = nxt;
-        return;
-    }
-    st[LSS_PHASE] = PH_NEWTON;
+__device__ void ls_propose(double *st) {
     const double lo = st[LSS_LO], hi = st[LSS_HI];
-    double nxt = f2 > 0.0 ? t - f1 / f2 : 0.5 * (lo + hi);
-    if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
-    if (fabs(nxt - t) <= 1e-13 * fabs(nxt)) { ls_finish(st, nxt); return; }
-    st[LSS_TRY] = nxt;
+    const double tn = lo - st[LSS_FLO] / st[LSS_HLO];   // > lo (FLO < 0, HLO > 0)
+    double t[LS_K];
+    if (hi < 0.0) {
+        const double base = (tn > lo && isfinite(tn)) ? tn : (lo > 0.0 ? 2.0 * lo : 1.0);
+        t[0] = base;
+        t[1] = 4.0 * base;
+        t[2] = 16.0 * base;
+        t[3] = 64.0 * base;
+    } else if (st[LSS_HI_EVAL] == 0.0) {
+        // alpha_max not evaluated yet: it is the last trial
+        const double t0 = (tn > lo && tn < hi) ? tn : lo + 0.5 * (hi - lo);
+        t[0] = t0;
+        t[1] = t0 + (hi - t0) / 3.0;
+        t[2] = t0 + 2.0 * (hi - t0) / 3.0;
+        t[3] = hi;
+    } else {
+        const double w = hi - lo;
+        const double th = hi - st[LSS_FHI] / st[LSS_HHI];
+        const double ts = lo - st[LSS_FLO] * w / (st[LSS_FHI] - st[LSS_FLO]);
+        double c[3] = {tn, ts, th};
+        for (int m = 0; m < 3; ++m)
+            if (!(c[m] > lo && c[m] < hi)) c[m] = lo + 0.25 * (m + 1) * w;
+        double mn = fmin(c[0], fmin(c[1], c[2])), mx = fmax(c[0], fmax(c[1], c[2]));
+        t[0] = c[0];
+        t[1] = c[1];
+        t[2] = c[2];
+        t[3] = mx > mn ? 0.5 * (mn + mx) : lo + 0.5 * w;
+    }
+    // ascending order (insertion sort of four)
+    for (int i = 1; i < LS_K; ++i)
+        for (int j = i; j > 0 && t[j] < t[j - 1]; --j) {
+            const double x = t[j]; t[j] = t[j - 1]; t[j - 1] = x;
+        }
+#pragma unroll
+    for (int m = 0; m < LS_K; ++m) st[LSS_T0 + m] = t[m];
 }
 
-// Step 6: initialise the line search of each channel.
-__global__ __launch_bounds__(NTHR) void k_chan_ls_init(const double *__restrict__ vispart, const int *__restrict__ vis_base,
-                                                       const double *__restrict__ ppart, int n_pb, double lam,
-                                                       const double *__restrict__ chan, double *__restrict__ ls) {
-    const int c = blockIdx.x;
-    double ab[2], ent[2];
-    sum_partials<2>(vispart + (size_t)vis_base[c] * NPART, vis_base[c + 1] - vis_base[c], 0, ab);
-    sum_partials<2>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, ent);
-    const double amax = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 2);
-    if (threadIdx.x == 0) {
-        double *st = ls + (size_t)c * LSS_N;
-        const double a = ab[0], b = ab[1];
-        const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
-        st[LSS_A] = a;
-        st[LSS_B] = b;
-        st[LSS_AMAX] = isfinite(amax) ? amax : -1.0;
-        st[LSS_LO] = 0.0;
-        st[LSS_HI] = isfinite(amax) ? amax : -1.0;
-        st[LSS_STOP] = stop ? 1.0 : 0.0;
-        const double f1 = b + lam * ent[0];     // phi'(0)
-        const double f2 = a + lam * ent[1];     // phi''(0)
-        if (stop || !(f1 < 0.0)) {
-            ls_finish(st, 0.0);
-        } else if (isfinite(amax)) {
-            st[LSS_PHASE] = PH_CHECK;
-            st[LSS_TRY] = amax;
-        } else {
-            st[LSS_PHASE] = PH_GROW;
-            double t = f2 > 0.0 ? -f1 / f2 : 1.0;
-            if (!(t > 0.0) || !isfinite(t)) t = 1.0;
-            st[LSS_TRY] = t;
-        }
+// Initial state from a, b, e1 = lambda sum d (ln(I/M) + 1), e2 = lambda sum
+// d^2/I (so phi'(0) = b + e1, phi''(0) = a + e2) and alpha_max.
+__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop) {
+    st[LSS_A] = a;
+    st[LSS_B] = b;
+    st[LSS_AMAX] = isfinite(amax) ? amax : -1.0;
+    st[LSS_STOP] = stop ? 1.0 : 0.0;
+    st[LSS_LO] = 0.0;
+    st[LSS_HI] = isfinite(amax) ? amax : -1.0;
+    st[LSS_FLO] = b + e1;
+    st[LSS_HLO] = a + e2;
+    st[LSS_FHI] = 0.0;
+    st[LSS_HHI] = 0.0;
+    st[LSS_HI_EVAL] = 0.0;
+    st[LSS_PHASE] = PH_SEARCH;
+    if (stop || !(st[LSS_FLO] < 0.0) || !(st[LSS_HLO] > 0.0) || (isfinite(amax) && amax <= 0.0)) {
+        ls_finish(st, 0.0);
+        return;
+    }
+    ls_propose(st);
+}
+
+// Advance the state with phi'(T_m) = f[m], phi''(T_m) = h[m].
+__device__ void ls_update(double *st, const double *f, const double *h) {
+    if ((int)st[LSS_PHASE] == PH_DONE) return;
+    int m = 0;
+    while (m < LS_K && f[m] <= 0.0) ++m;
+    if (m > 0 && f[m - 1] == 0.0) { ls_finish(st, st[LSS_T0 + m - 1]); return; }
+    if (m > 0) {
+        st[LSS_LO] = st[LSS_T0 + m - 1];
+        st[LSS_FLO] = f[m - 1];
+        st[LSS_HLO] = h[m - 1];
+    }
+    if (m < LS_K) {
+        st[LSS_HI] = st[LSS_T0 + m];
+        st[LSS_FHI] = f[m];
+        st[LSS_HHI] = h[m];
+        st[LSS_HI_EVAL] = 1.0;
+    } else if (st[LSS_HI] >= 0.0 && st[LSS_HI_EVAL] == 0.0 && st[LSS_T0 + LS_K - 1] == st[LSS_HI]) {
+        // phi'(alpha_max) <= 0: the minimiser on [0, alpha_max] is alpha_max
+        ls_finish(st, st[LSS_HI]);
+        return;
+    }
+    const double lo = st[LSS_LO], hi = st[LSS_HI];
+    if (st[LSS_HI_EVAL] != 0.0 && hi - lo <= 1e-13 * hi) {
+        const double ts = lo - st[LSS_FLO] * (hi - lo) / (st[LSS_FHI] - st[LSS_FLO]);
+        ls_finish(st, (ts >= lo && ts <= hi) ? ts : lo);
+        return;
+    }
+    ls_propose(st);
+}
+
+// Accepted step when the pass budget ran out: the secant step of the
+// bracket, or the largest step known to descend.
+__device__ double ls_fallback(const double *st) {
+    const double lo = st[LSS_LO], hi = st[LSS_HI];
+    if (st[LSS_HI_EVAL] != 0.0) {
+        const double ts = lo - st[LSS_FLO] * (hi - lo) / (st[LSS_FHI] - st[LSS_FLO]);
+        if (ts >= lo && ts <= hi) return ts;
+    }
+    return lo;
+}
+
+// Sum the LS_K (phi' entropy part, phi'' entropy part) partials of a channel
+// and turn them into phi', phi'' at the trial steps.
+__device__ __forceinline__ void ls_eval(const double *st, const double *pp, int n_pb, double lam,
+                                        double *f, double *h) {
+    double e[2 * LS_K];
+    sum_partials<2 * LS_K>(pp, n_pb, 0, e);
+#pragma unroll
+    for (int m = 0; m < LS_K; ++m) {
+        const double t = st[LSS_T0 + m];
+        f[m] = st[LSS_B] + st[LSS_A] * t + lam * e[2 * m];
+        h[m] = st[LSS_A] + lam * e[2 * m + 1];
     }
 }
 
-// Reads the previous state and partials (if any), advances the state (all
-// workgroups of the channel compute the same bits; workgroup 0 stores it) and
-// evaluates phi' and phi'' partials at the new trial step.
+// Pass of the line search: pass 0 initialises the state; later passes
+// advance it with the previous pass's partials.  Every workgroup of the
+// channel computes the same state; workgroup 0 stores it.  Then each
+// workgroup evaluates the phi', phi'' partials at the LS_K trial steps.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const R *__restrict__ dir,
                                                   const double *__restrict__ ls_prev, double *__restrict__ ls_next,
                                                   const double *__restrict__ pp_prev, double *__restrict__ pp_next,
+                                                  const double *__restrict__ vispart, const int *__restrict__ vis_base,
+                                                  const double *__restrict__ chan,
                                                   int n, int n_pb, double M, double lam, int first) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
-    if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
-    __syncthreads();
-    if (!first && (int)st[LSS_PHASE] != PH_DONE) {
-        double e[2];
-        sum_partials<2>(pp_prev + (size_t)c * n_pb * NPART, n_pb, 0, e);
+    if (first) {
+        double ab[2], ent[2];
+        sum_partials<2>(vispart + (size_t)vis_base[c] * NPART, vis_base[c + 1] - vis_base[c], 0, ab);
+        sum_partials<2>(pp_prev + (size_t)c * n_pb * NPART, n_pb, 0, ent);
+        const double amax = min_partials(pp_prev + (size_t)c * n_pb * NPART, n_pb, 2);
         if (threadIdx.x == 0) {
-            const double t = st[LSS_TRY];
-            update_ls(st, st[LSS_B] + st[LSS_A] * t + lam * e[0], st[LSS_A] + lam * e[1]);
+            const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
+            ls_init(st, ab[0], ab[1], lam * ent[0], lam * ent[1], amax, stop);
         }
+        __syncthreads();
+    } else {
+        if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
+        __syncthreads();
+        if ((int)st[LSS_PHASE] != PH_DONE) {
+            double f[LS_K], h[LS_K];
+            ls_eval(st, pp_prev + (size_t)c * n_pb * NPART, n_pb, lam, f, h);
+            if (threadIdx.x == 0) ls_update(st, f, h);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (pb == 0 && threadIdx.x < LSS_N) ls_next[(size_t)c * LSS_N + threadIdx.x] = st[threadIdx.x];
     if ((int)st[LSS_PHASE] == PH_DONE) return;
-    const double al = st[LSS_TRY];
-    double acc[2] = {0.0, 0.0};
+    double tr[LS_K];
+#pragma unroll
+    for (int m = 0; m < LS_K; ++m) tr[m] = st[LSS_T0 + m];
+    double acc[2 * LS_K];
+#pragma unroll
+    for (int m = 0; m < 2 * LS_K; ++m) acc[m] = 0.0;
     for (int r = 0; r < PIX_BLK / NTHR; ++r) {
         const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double d = (double)dir[q];
-        const double x = (double)I[q] + al * d;
-        acc[0] += d * (log(x / M) + 1.0);
-        acc[1] += d * d / x;
+        if (d == 0.0) continue;
+        const double x0 = (double)I[q];
+#pragma unroll
+        for (int m = 0; m < LS_K; ++m) {
+            const double x = x0 + tr[m] * d;
+            acc[2 * m] += d * (log(x / M) + 1.0);
+            acc[2 * m + 1] += d * d / x;
+        }
     }
-    block_sum<2>(acc);
+    block_sum<2 * LS_K>(acc);
     if (threadIdx.x == 0) {
-        pp_next[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
-        pp_next[((size_t)c * n_pb + pb) * NPART + 1] = acc[1];
+#pragma unroll
+        for (int m = 0; m < 2 * LS_K; ++m) pp_next[((size_t)c * n_pb + pb) * NPART + m] = acc[m];
     }
 }
 
@@ -538,18 +629,11 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
     if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
     __syncthreads();
     if ((int)st[LSS_PHASE] != PH_DONE) {
-        double e[2];
-        sum_partials<2>(pp_prev + (size_t)c * n_pb * NPART, n_pb, 0, e);
+        double f[LS_K], h[LS_K];
+        ls_eval(st, pp_prev + (size_t)c * n_pb * NPART, n_pb, lam, f, h);
         if (threadIdx.x == 0) {
-            const double t = st[LSS_TRY];
-            update_ls(st, st[LSS_B] + st[LSS_A] * t + lam * e[0], st[LSS_A] + lam * e[1]);
-            if ((int)st[LSS_PHASE] != PH_DONE) {
-                // not converged within the fixed budget: take the bracketed trial
-                double al = st[LSS_TRY];
-                if (st[LSS_HI] >= 0.0) al = fmin(al, st[LSS_HI]);
-                al = fmax(al, st[LSS_LO]);
-                ls_finish(st, al);
-            }
+            ls_update(st, f, h);
+            if ((int)st[LSS_PHASE] != PH_DONE) ls_finish(st, ls_fallback(st));
         }
     }
     __syncthreads();
@@ -714,12 +798,10 @@ hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) 
     // 1. direction update and projection; partial gt.d
     hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
                        c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->Mb);
-    // 2. restart test
-    hipLaunchKernelGGL(k_chan_gtd, gc, blk, 0, st, pp(c, 0), c->n_pb, c->d_scal, c->d_chan);
-    // 3. restart, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
+    // 2-3. restart test, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
     hipLaunchKernelGGL((k_cg_dir2<R, SPLIT>), gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       CP<R>(c->d_beam), c->d_bop, lo_off(c), c->d_chan, pp(c, 1), c->n, c->np, c->n_pb, c->M,
-                       c->Mb);
+                       CP<R>(c->d_beam), c->d_bop, lo_off(c), pp(c, 0), c->d_scal, c->d_chan, pp(c, 1), c->n,
+                       c->np, c->n_pb, c->M, c->Mb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. Vd = F(d)
     return hipSuccess;
@@ -751,19 +833,17 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
             hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_ib,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
                                c->d_scal, c->d_vispart, 2);
-        // 6. line-search initialisation
-        hipLaunchKernelGGL(k_chan_ls_init, gc, blk, 0, st, c->d_vispart, c->d_vis_base, pp(c, 1), c->n_pb,
-                           c->lam, c->d_chan, lsb(c, 0));
-        // 7. fixed number of Newton / bisection evaluations
-        for (int t = 0; t < LS_STEPS; ++t) {
-            // launch t: state S^t-1 from ls[t%2] (S^0 from the initialisation),
-            // partials P^t-1 from pp[(t+1)%2]; writes S^t to ls[(t+1)%2] and
-            // P^t (phi', phi'' at the new trial) to pp[t%2]
+        // 6-7. line search: pass 0 initialises the state (from the visibility
+        // partials and the direction pass's partials in pp[1]); pass t > 0
+        // advances S^t-1 (ls[t%2]) with P^t-1 (pp[(t+1)%2]); every pass
+        // stores S^t in ls[(t+1)%2] and evaluates P^t into pp[t%2]
+        const int L = c->ls_steps;
+        for (int t = 0; t < L; ++t) {
             hipLaunchKernelGGL(k_ls_step<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_dir), lsb(c, t % 2),
-                               lsb(c, (t + 1) % 2), pp(c, (t + 1) % 2), pp(c, t % 2), c->n, c->n_pb, c->M,
-                               c->lam, t == 0 ? 1 : 0);
+                               lsb(c, (t + 1) % 2), pp(c, (t + 1) % 2), pp(c, t % 2), c->d_vispart,
+                               c->d_vis_base, c->d_chan, c->n, c->n_pb, c->M, c->lam, t == 0 ? 1 : 0);
         }
-        const int last = (LS_STEPS - 1) % 2;   // pp buffer holding the last partials
+        const int last = (L - 1) % 2;   // pp buffer holding the last partials
         // 8. final update of the step, I <- max(I + alpha d, M), entropy partial
         hipLaunchKernelGGL(k_cg_update<R>, gp, blk, 0, st, P<R>(I), CP<R>(c->d_dir), lsb(c, 1 - last),
                            pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->M,
@@ -776,7 +856,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         return hipGetLastError();
     }
     // 11. gradient at the new point, projected gradient, PR partials
-    const int last = (LS_STEPS - 1) % 2;
+    const int last = (c->ls_steps - 1) % 2;
     hipLaunchKernelGGL(k_grad<R>, gp, blk, 0, st, c->d_gpart, c->d_slot_base, CP<R>(c->d_beam), CP<R>(I),
                        P<R>(c->d_g), P<R>(c->d_gt), pp(c, last), c->n, c->np, c->n_pb, c->M, c->Mb, c->lam, 2);
     // 12. beta and scalars
