@@ -138,6 +138,11 @@ int build_layout(uvmem_ctx *c) {
     } else
         c->ib_rows = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->n_ib = c->np / c->ib_rows;
+    // FP32 sums at most 256 image columns in one FP32 accumulator; the
+    // column blocks are combined in FP64 with the row blocks
+    c->jb_cols = (c->prec == UVMEM_FP32) ? std::min(c->np, 256) : c->np;
+    c->n_jb = c->np / c->jb_cols;
+    c->n_fparts = c->n_ib * c->n_jb;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->adj_nt = c->np / c->adj_tt;
     c->n_pb = (int)(((int64_t)c->n * c->n + PIX_BLK - 1) / PIX_BLK);
@@ -343,6 +348,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     if (const char *env = std::getenv("UVMEM_ADJ_WGS")) target = std::max(1L, std::atol(env));
     int64_t klen = (c->ztot * tiles + target - 1) / target;
     klen = std::max<int64_t>(klen, ADJ_KMIN);
+    // the split-precision adjoint accumulates a chunk in FP32 only: bound it
+    if (c->prec == UVMEM_BF16X3) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
     klen = ((klen + 15) / 16) * 16;
     int slot = 0;
     for (int ch = 0; ch < C; ++ch) {
@@ -409,7 +416,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_vis_base, C + 1));
     ok(dalloc(c, &c->d_R, c->ztot));
     ok(dalloc(c, &c->d_Vd, c->ztot));
-    ok(dalloc(c, &c->d_vpart, (size_t)c->n_ib * c->ztot));
+    ok(dalloc(c, &c->d_vpart, (size_t)c->n_fparts * c->ztot));
     ok(dalloc(c, &c->d_gpart, (size_t)c->n_slots * np * np));
     ok(dalloc(c, (char **)&c->d_bop, (size_t)C * np * np * rs));
     ok(dalloc(c, (char **)&c->d_g, C * npix * rs));
@@ -676,7 +683,7 @@ int uvmem_timing_read(uvmem_ctx *c, int which, double *total_ms, int64_t *count,
 
 int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     if (!c || !out) return UVMEM_EINVAL;
-    const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_ib, c->adj_tt, c->n_slots,
+    const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
                             c->n_fwd, c->n_adj, c->n_visit, (int64_t)c->bytes_device};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];

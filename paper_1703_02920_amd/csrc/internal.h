@@ -20,6 +20,9 @@ constexpr int VIS_BLK = 2048;
 constexpr int PIX_BLK = 1024;
 // Minimum visibilities per adjoint split-K chunk (multiple of 16).
 constexpr int ADJ_KMIN = 256;
+// Maximum visibilities per split-K chunk of the split-precision adjoint,
+// whose chunk sums are FP32 only (bounds their rounding growth).
+constexpr int ADJ_KMAX_SPLIT = 32768;
 // Partial-sum slots per pixel / visibility item.
 constexpr int NPART = 8;
 // Trial steps evaluated per line-search pass.
@@ -106,7 +109,9 @@ struct uvmem_ctx {
     // layout
     std::vector<int64_t> off;          // channel offsets, size nchan+1
     int64_t ztot = 0;
-    int ib_rows = 0, n_ib = 0;         // forward i-blocks
+    int ib_rows = 0, n_ib = 0;         // forward i-blocks (image rows per block)
+    int jb_cols = 0, n_jb = 1;         // forward j-blocks (image columns per block)
+    int n_fparts = 0;                  // forward partials per visibility: n_ib * n_jb
     int adj_tt = 0, adj_nt = 0;        // adjoint tile side, tiles per side
     int n_slots = 0;
     int n_pb = 0;                      // pixel blocks per channel

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
 // mode 2: Vd_k = V_k -> Vd; partial[0] = sum w |Vd|^2, partial[1] = sum w Re(conj(R) Vd)
 // mode 3: R_k += alpha_c Vd_k; partial[0] = sum w |R|^2
 __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
-                                              const double2 *__restrict__ vpart, int n_ib, long long ztot,
+                                              const double2 *__restrict__ vpart, int n_parts, long long ztot,
                                               const float2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
     for (long long k = it.kbeg + threadIdx.x; k < it.kend; k += NTHR) {
         double2 v = make_double2(0.0, 0.0);
         if (mode != 3) {
-            for (int ib = 0; ib < n_ib; ++ib) {
+            for (int ib = 0; ib < n_parts; ++ib) {
                 const double2 p = vpart[(size_t)ib * ztot + k];
                 v.x += p.x;
                 v.y += p.y;
@@ -765,7 +765,7 @@ hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, 
 
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st) {
     if (c->n_visit == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_ib,
+    hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart, mode);
     return hipGetLastError();
 }
@@ -830,7 +830,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
     if (phase == 1) {
         // 5. Vd and the quadratic coefficients a, b of chi^2 along d
         if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_ib,
+            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
                                c->d_scal, c->d_vispart, 2);
         // 6-7. line search: pass 0 initialises the state (from the visibility
@@ -850,7 +850,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
                            c->Mb, c->lam);
         // 9. R <- R + alpha Vd, chi^2 partials
         if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_ib,
+            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
                                c->d_scal, c->d_vispart, 3);
         return hipGetLastError();

@@ -78,15 +78,17 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
                                                  const double *__restrict__ a,
                                                  const double *__restrict__ b,
                                                  const T *__restrict__ bop, double2 *__restrict__ vpart,
-                                                 int n, int np, long long ztot) {
+                                                 int n, int np, long long ztot, int jb_cols, int n_jb) {
     typedef typename Mfma<T>::acc acc_t;
     typedef typename Vec4<T>::type T4;
     constexpr int NT = IB / 16;
     __shared__ __attribute__((aligned(16))) T sB[IB][JC + JPAD];
 
     const FwdItem it = items[blockIdx.x];
-    const int ib = blockIdx.y;
+    const int part = blockIdx.y;            // (row block, column block)
+    const int ib = part / n_jb, jb = part % n_jb;
     const int i0 = ib * IB;
+    const int j_beg = jb * jb_cols, j_end = j_beg + jb_cols;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane & 15, g = lane >> 4;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
 
     constexpr int V_PER_ROW = JC / 4;                 // 4-wide vectors per staged row
     constexpr int NLOAD = IB * V_PER_ROW / 256;       // vectors per thread
-    for (int jc = 0; jc < np; jc += JC) {
+    for (int jc = j_beg; jc < j_end; jc += JC) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
             vr += __shfl_xor(vr, o, 64);
             vi += __shfl_xor(vi, o, 64);
         }
-        if (q == 0 && ok) vpart[(size_t)ib * ztot + it.k0 + kk] = make_double2(vr, vi);
+        if (q == 0 && ok) vpart[(size_t)part * ztot + it.k0 + kk] = make_double2(vr, vi);
     }
 }
 
@@ -638,13 +640,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
 template <typename T>
 hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
     if (c->n_fwd == 0) return hipSuccess;
-    dim3 grid(c->n_fwd, c->n_ib);
+    dim3 grid(c->n_fwd, c->n_fparts);
     if (c->ib_rows == 128)
         hipLaunchKernelGGL((k_forward<T, 128>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
-                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot, c->jb_cols, c->n_jb);
     else
         hipLaunchKernelGGL((k_forward<T, 64>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
-                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot, c->jb_cols, c->n_jb);
     return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import List, Optional
 
 import numpy as np
@@ -202,7 +203,31 @@ def sample_sky(comp: Components, n: int, cell: float) -> np.ndarray:
 def sky_visibilities(comp: Components, u: np.ndarray, v: np.ndarray,
                      cell: float, fwhm: float, floor: float = 0.0) -> np.ndarray:
     """Closed-form visibilities of (continuous sky x Gaussian beam), see module
-    docstring.  Returns complex128 [Z]."""
+    docstring.  Returns complex128 [Z].  Components are split into contiguous
+    groups summed on worker threads; the group sums are added in group order,
+    so the result does not depend on the thread count."""
+    n_comp = comp.x0.shape[0]
+    work = n_comp * u.shape[0]
+    groups = 1 if work < 2e7 else min(32, n_comp)
+    if groups == 1:
+        return _sky_vis_serial(comp, u, v, cell, fwhm, floor)
+    from concurrent.futures import ThreadPoolExecutor
+    edges = np.linspace(0, n_comp, groups + 1).astype(int)
+    parts = [Components(comp.x0[a:b], comp.y0[a:b], comp.amp[a:b], comp.sig[a:b])
+             for a, b in zip(edges[:-1], edges[1:])]
+    workers = min(groups, max(1, (os.cpu_count() or 1)), 16)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        sums = list(ex.map(lambda cp: _sky_vis_serial(cp, u, v, cell, fwhm, 0.0), parts))
+    out = np.zeros(u.shape[0], dtype=np.complex128)
+    for part in sums:
+        out += part
+    if floor:
+        out += _sky_vis_serial(Components.empty(), u, v, cell, fwhm, floor)
+    return out
+
+
+def _sky_vis_serial(comp: Components, u: np.ndarray, v: np.ndarray,
+                    cell: float, fwhm: float, floor: float = 0.0) -> np.ndarray:
     sA2 = fwhm_to_sigma(fwhm) ** 2
     q2 = u * u + v * v
     out = np.zeros(u.shape[0], dtype=np.complex128)
@@ -334,10 +359,53 @@ def _disk_spiral(n: int, cell: float) -> Components:
     return comp
 
 
-def make_config(c: int, channels: Optional[int] = None) -> Dataset:
+CACHE_VERSION = 1
+
+
+def make_config(c: int, channels: Optional[int] = None, cache: bool = True) -> Dataset:
     """Build workload configuration c (1..5).  `channels` truncates c4 to its
     first few channels (for quick tests); the data of the kept channels are
-    identical to the full configuration's."""
+    identical to the full configuration's.  Generated data sets are cached as
+    .npz files in $UVMEM_SYNTH_CACHE (default: the system temp directory)."""
+    if cache:
+        import tempfile
+        root = os.environ.get("UVMEM_SYNTH_CACHE", os.path.join(tempfile.gettempdir(), "uvmem_synth"))
+        path = os.path.join(root, f"c{c}_{channels or 'all'}_v{CACHE_VERSION}.npz")
+        if os.path.exists(path):
+            try:
+                return _load(path)
+            except Exception:
+                pass
+        ds = _make_config(c, channels)
+        try:
+            os.makedirs(root, exist_ok=True)
+            _save(ds, path)
+        except OSError:
+            pass
+        return ds
+    return _make_config(c, channels)
+
+
+def _save(ds: Dataset, path: str) -> None:
+    arrs = dict(n=ds.n, cell=ds.cell, sky=ds.sky, prior_m=ds.prior_m, lam=ds.lam, cg_iters=ds.cg_iters,
+                name=ds.name, description=ds.description, n_chan=ds.n_chan)
+    for i, ch in enumerate(ds.channels):
+        arrs.update({f"u{i}": ch.u, f"v{i}": ch.v, f"vis{i}": ch.vis, f"w{i}": ch.w,
+                     f"fwhm{i}": ch.fwhm, f"lam{i}": ch.wavelength})
+    tmp = path + ".tmp%d.npz" % os.getpid()
+    np.savez(tmp, **arrs)
+    os.replace(tmp, path)
+
+
+def _load(path: str) -> Dataset:
+    z = np.load(path, allow_pickle=False)
+    chans = [Channel(z[f"u{i}"], z[f"v{i}"], z[f"vis{i}"], z[f"w{i}"], float(z[f"fwhm{i}"]), float(z[f"lam{i}"]))
+             for i in range(int(z["n_chan"]))]
+    return Dataset(str(z["name"]), int(z["n"]), float(z["cell"]), chans, z["sky"], float(z["prior_m"]),
+                   float(z["lam"]), int(z["cg_iters"]), str(z["description"]))
+
+
+def _make_config(c: int, channels: Optional[int] = None) -> Dataset:
     if c not in _CFG:
         raise ValueError(f"unknown configuration {c}")
     p = _CFG[c]

@@ -185,7 +185,7 @@ class Context:
     def info(self) -> dict:
         out = (ctypes.c_int64 * 12)()
         self._call("uvmem_info", out, 12)
-        keys = ["n", "np", "n_chan", "prec", "ztot", "n_ib", "adj_tile", "n_slots", "n_fwd_items",
+        keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_items",
                 "n_adj_items", "n_vis_items", "device_bytes"]
         return dict(zip(keys, [int(x) for x in out]))
 
