@@ -135,8 +135,12 @@ int build_layout(uvmem_ctx *c) {
         if (ib != 64 && ib != 128 && ib != 256) ib = 128;
         while (c->np % ib) ib /= 2;
         c->ib_rows = ib;
-    } else
-        c->ib_rows = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    } else {
+        int ib = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+        if (c->prec == UVMEM_FP32)
+            if (const char *env = std::getenv("UVMEM_FWD_IB")) ib = std::atoi(env) == 64 ? 64 : ib;
+        c->ib_rows = ib;
+    }
     c->n_ib = c->np / c->ib_rows;
     // FP32 sums at most 256 image columns in one FP32 accumulator; the
     // column blocks are combined in FP64 with the row blocks

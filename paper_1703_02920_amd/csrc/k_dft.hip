@@ -58,6 +58,10 @@ __device__ __forceinline__ double phase(double a, int m) {
     return t - rint(t);
 }
 
+template <typename T> struct C2T;
+template <> struct C2T<float> { typedef float2 type; };
+template <> struct C2T<double> { typedef double2 type; };
+
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
@@ -65,12 +69,11 @@ template <> struct Vec4<double> { typedef double4 type; };
 // ----------------------------------------------------------------------------
 // Forward.  Workgroup = 4 waves; wave w owns the 16 visibilities
 // k0 + 16 w + (0..15) as MFMA rows and all IB image rows of i-block blockIdx.y
-// as MFMA columns; the image block is staged through LDS in JC-column chunks.
+// as MFMA columns; the image block is staged through LDS in 32-column chunks.
 // Within a 16-column super-step, MFMA #s (s = 0..3) of lane group g = l/16
 // contracts column j = jbase + 4 g + s, so each lane reads 4 consecutive
 // image values with one vector load.
 // ----------------------------------------------------------------------------
-constexpr int JC = 32;
 constexpr int JPAD = 4;
 
 template <typename T, int IB>
@@ -81,8 +84,11 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
                                                  int n, int np, long long ztot, int jb_cols, int n_jb) {
     typedef typename Mfma<T>::acc acc_t;
     typedef typename Vec4<T>::type T4;
+    typedef typename C2T<T>::type C2;
     constexpr int NT = IB / 16;
-    __shared__ __attribute__((aligned(16))) T sB[IB][JC + JPAD];
+    constexpr int JCF = 32;                           // image columns per staged chunk
+    __shared__ __attribute__((aligned(16))) T sB[IB][JCF + JPAD];
+    __shared__ C2 sCo[64][NT + 1];
 
     const FwdItem it = items[blockIdx.x];
     const int part = blockIdx.y;            // (row block, column block)
@@ -97,6 +103,10 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
 
     const int krow = wave * 16 + q;
     const double ak = krow < it.nvalid ? a[it.k0 + krow] : 0.0;
+    // E_u[k][j0 + 4 g + s] = E(j0 - N/2) E(4 g + s): per-lane fine factors
+    T fc[4], fs[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
 
     acc_t accR[NT], accI[NT];
 #pragma unroll
@@ -105,28 +115,27 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
         accI[t] = Mfma<T>::zero();
     }
 
-    constexpr int V_PER_ROW = JC / 4;                 // 4-wide vectors per staged row
+    constexpr int V_PER_ROW = JCF / 4;                // 4-wide vectors per staged row
     constexpr int NLOAD = IB * V_PER_ROW / 256;       // vectors per thread
-    for (int jc = j_beg; jc < j_end; jc += JC) {
+    for (int jc = j_beg; jc < j_end; jc += JCF) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
-            int idx = tid + 256 * r;
-            int row = idx / V_PER_ROW, c4 = idx % V_PER_ROW;
-            T4 v = *reinterpret_cast<const T4 *>(B + (size_t)(i0 + row) * np + jc + 4 * c4);
-            *reinterpret_cast<T4 *>(&sB[row][4 * c4]) = v;
+            const int idx = tid + 256 * r;
+            const int row = idx / V_PER_ROW, c4 = idx % V_PER_ROW;
+            *reinterpret_cast<T4 *>(&sB[row][4 * c4]) =
+                *reinterpret_cast<const T4 *>(B + (size_t)(i0 + row) * np + jc + 4 * c4);
         }
         __syncthreads();
 #pragma unroll
-        for (int js = 0; js < JC; js += 16) {
+        for (int js = 0; js < JCF; js += 16) {
+            T cc, sc;
+            cis2pi((T)phase(ak, jc + js - half), cc, sc);
             T cr[4], ci[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                int m = jc + js + 4 * g + s - half;
-                T c, sn;
-                cis2pi((T)phase(ak, m), c, sn);
-                cr[s] = c;
-                ci[s] = -sn;
+                cr[s] = cc * fc[s] - sc * fs[s];
+                ci[s] = -(sc * fc[s] + cc * fs[s]);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -144,20 +153,30 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
     }
 
     // Row dot with E_v, accumulated in FP64: lane holds T[k][i] for
-    // k = 16 w + drow(g, r), i = i0 + 16 t + q.
+    // k = 16 w + drow(g, r), i = i0 + 16 t + q.  E_v[k][i0 + 16 t + q] =
+    // E(b_k (i0 + q - N/2)) E(16 b_k t), the second factor shared via LDS.
+    for (int x = tid; x < 64 * NT; x += 256) {
+        const int kk = x / NT, t = x % NT;
+        const double bk = kk < it.nvalid ? b[it.k0 + kk] : 0.0;
+        T c, sn;
+        cis2pi((T)phase(bk, 16 * t), c, sn);
+        sCo[kk][t] = C2{c, sn};
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int kk = wave * 16 + Mfma<T>::drow(g, r);
         const bool ok = kk < it.nvalid;
         const double bk = ok ? b[it.k0 + kk] : 0.0;
+        T fcq, fsq;
+        cis2pi((T)phase(bk, i0 + q - half), fcq, fsq);
         double vr = 0.0, vi = 0.0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            int m = i0 + 16 * t + q - half;
-            T c, sn;
-            cis2pi((T)phase(bk, m), c, sn);
-            double tr = (double)accR[t][r], ti = (double)accI[t][r];
-            double cd = (double)c, sd = (double)sn;
+            const C2 co = sCo[kk][t];
+            const double cd = (double)(fcq * co.x - fsq * co.y);
+            const double sd = (double)(fsq * co.x + fcq * co.y);
+            const double tr = (double)accR[t][r], ti = (double)accI[t][r];
             vr += cd * tr + sd * ti;
             vi += cd * ti - sd * tr;
         }
@@ -181,9 +200,6 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
 // 4 g + s of the step.  FP32 accumulators are folded into FP64 ones every
 // FLUSH super-steps.
 // ----------------------------------------------------------------------------
-template <typename T> struct C2T;
-template <> struct C2T<float> { typedef float2 type; };
-template <> struct C2T<double> { typedef double2 type; };
 
 template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ items,
@@ -198,7 +214,11 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
     constexpr int NT = WT / 16;
     constexpr int NC = TT / 16;
     constexpr int FLUSH = 16;
-    __shared__ C2 sHv[16][16], sFu[16][16], sGv[16][NC], sGu[16][NC];
+    __shared__ C2 sHv[2][16][16], sFu[2][16][16], sGv[2][16][NC], sGu[2][16][NC];
+    // FP64 fold of the FP32 sums, one slot per (wave, tile, register, lane):
+    // each lane reads and writes only its own slots
+    constexpr int NACC = sizeof(T) == 4 ? 4 * NT * NT * 4 * 64 : 1;
+    __shared__ double sAcc[NACC];
 
     const AdjItem it = items[blockIdx.x];
     const int i0 = it.ti * TT, j0 = it.tj * TT;
@@ -210,91 +230,126 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
     const int half = n / 2;
 
     acc_t acc[NT][NT];
-    double dacc[NT][NT][4];
+    auto slot = [&](int x, int y, int r) { return (((wave * NT + x) * NT + y) * 4 + r) * 64 + lane; };
 #pragma unroll
     for (int x = 0; x < NT; ++x)
 #pragma unroll
         for (int y = 0; y < NT; ++y) {
             acc[x][y] = Mfma<T>::zero();
+            if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dacc[x][y][r] = 0.0;
+                for (int r = 0; r < 4; ++r) sAcc[slot(x, y, r)] = 0.0;
+            }
         }
 
-    int step = 0;
-    for (long long kb = it.kbeg; kb < it.kend; kb += 16, ++step) {
-        // ---- generate the step's twiddle tables
-        {
-            const int kk = tid >> 4, qq = tid & 15;
-            const long long k = kb + kk;
-            const bool ok = k < it.kend;
-            C2 hv = {0, 0}, fu = {0, 0};
-            if (ok) {
-                const double bk = b[k], ak = a[k];
-                double2 cc = coef[k];
-                double ww = w ? (double)w[k] : 1.0;
-                T c, s;
-                cis2pi((T)phase(bk, i0 + qq - half), c, s);
-                double cr = ww * cc.x, cim = ww * cc.y;
-                hv.x = (T)(cr * (double)c - cim * (double)s);
-                hv.y = (T)(cr * (double)s + cim * (double)c);
-                cis2pi((T)phase(ak, j0 + qq - half), c, s);
-                fu.x = c;
-                fu.y = s;
-            }
-            sHv[kk][qq] = hv;
-            sFu[kk][qq] = fu;
-            if (tid < 32 * NC) {
-                const int which = tid / (16 * NC);
-                const int r2 = tid % (16 * NC);
-                const int k2 = r2 / NC, t2 = r2 % NC;
-                const long long kg = kb + k2;
-                C2 gval = {1, 0};
-                if (kg < it.kend) {
-                    const double ab = which ? a[kg] : b[kg];
-                    T c, s;
-                    cis2pi((T)phase(ab, 16 * t2), c, s);
-                    gval.x = c;
-                    gval.y = s;
-                }
-                if (which) sGu[k2][t2] = gval; else sGv[k2][t2] = gval;
-            }
+    // this thread's table tasks: fine (k = tid >> 4, q = tid & 15) and, for
+    // tid < 32 NC, one coarse entry (axis `which`, k2, t2); the visibility data
+    // of the next step are loaded while the current step computes
+    const int fkk = tid >> 4, fqq = tid & 15;
+    const bool has_c = tid < 32 * NC;
+    const int which = tid / (16 * NC);
+    const int ck2 = (tid % (16 * NC)) / NC, ct2 = tid % NC;
+    struct Pre {
+        double a, b, cab;
+        double2 c;
+        float w;
+    };
+    // branch-free prefetch: indices past the chunk end are clamped to its last
+    // visibility and their weight is zeroed (so the step's tables are zero)
+    const double *cab_src = which ? a : b;
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k = kb + fkk, kc = kb + ck2;
+        const long long kl = k < it.kend ? k : it.kend - 1;
+        const long long kcl = kc < it.kend ? kc : it.kend - 1;
+        p.a = a[kl];
+        p.b = b[kl];
+        p.c = coef[kl];
+        const float wv = w ? w[kl] : 1.f;
+        p.w = k < it.kend ? wv : 0.f;
+        p.cab = cab_src[kcl];
+    };
+    // twiddle tables of the step starting at kb from its prefetched data, into
+    // buffer `buf` (branch-free: entries past the chunk end are zero)
+    auto gen = [&](int buf, long long kb, const Pre &p) {
+        T c, s;
+        cis2pi((T)phase(p.b, i0 + fqq - half), c, s);
+        const double cr = (double)p.w * p.c.x, cim = (double)p.w * p.c.y;
+        C2 hv, fu;
+        hv.x = (T)(cr * (double)c - cim * (double)s);
+        hv.y = (T)(cr * (double)s + cim * (double)c);
+        cis2pi((T)phase(p.a, j0 + fqq - half), c, s);
+        const bool live = kb + fkk < it.kend;
+        fu.x = live ? c : (T)0;
+        fu.y = live ? s : (T)0;
+        sHv[buf][fkk][fqq] = hv;
+        sFu[buf][fkk][fqq] = fu;
+        if (has_c) {
+            cis2pi((T)phase(p.cab, 16 * ct2), c, s);
+            C2 *dst = which ? &sGu[buf][ck2][ct2] : &sGv[buf][ck2][ct2];
+            *dst = C2{c, s};
         }
-        __syncthreads();
-        // ---- contract the step on matrix cores
+    };
+    Pre cur, nxt;
+    fetch(it.kbeg, cur);
+    gen(0, it.kbeg, cur);
+    fetch(it.kbeg + 16, cur);       // cur now holds the data of the second step
+    __syncthreads();
+    int buf = 0;
+    // outer loop: groups of FLUSH steps whose FP32 sums are folded into FP64
+    // (FP64 operands accumulate directly; one group covers the whole chunk)
+    const long long group = sizeof(T) == 4 ? 16LL * FLUSH : (it.kend - it.kbeg);
+    for (long long kg = it.kbeg; kg < it.kend; kg += group) {
+        const long long kg_end = kg + group < it.kend ? kg + group : it.kend;
+        for (long long kb = kg; kb < kg_end; kb += 16) {
+            // data two steps ahead; tables one step ahead into the other buffer
+            fetch(kb + 32, nxt);
+            gen(buf ^ 1, kb + 16, cur);
+            // ---- contract this step on matrix cores
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int kk = 4 * g + s;
-            const C2 h = sHv[kk][q];
-            const C2 f = sFu[kk][q];
-            T pr[NT], pn[NT], ec[NT], es[NT];
+            for (int s = 0; s < 4; ++s) {
+                const int kk = 4 * g + s;
+                const C2 h = sHv[buf][kk][q];
+                const C2 f = sFu[buf][kk][q];
+                T pr[NT], pn[NT], ec[NT], es[NT];
 #pragma unroll
-            for (int x = 0; x < NT; ++x) {
-                const C2 gv = sGv[kk][ci0 + x];
-                pr[x] = h.x * gv.x - h.y * gv.y;
-                pn[x] = -(h.x * gv.y + h.y * gv.x);
+                for (int x = 0; x < NT; ++x) {
+                    const C2 gv = sGv[buf][kk][ci0 + x];
+                    pr[x] = h.x * gv.x - h.y * gv.y;
+                    pn[x] = -(h.x * gv.y + h.y * gv.x);
+                }
+#pragma unroll
+                for (int y = 0; y < NT; ++y) {
+                    const C2 gu = sGu[buf][kk][cj0 + y];
+                    ec[y] = f.x * gu.x - f.y * gu.y;
+                    es[y] = f.x * gu.y + f.y * gu.x;
+                }
+#pragma unroll
+                for (int x = 0; x < NT; ++x)
+#pragma unroll
+                    for (int y = 0; y < NT; ++y) {
+                        acc[x][y] = Mfma<T>::mma(pr[x], ec[y], acc[x][y]);
+                        acc[x][y] = Mfma<T>::mma(pn[x], es[y], acc[x][y]);
+                    }
             }
+            // interleave the next step's loads, table work and this step's
+            // operand arithmetic between the matrix-core instructions
 #pragma unroll
-            for (int y = 0; y < NT; ++y) {
-                const C2 gu = sGu[kk][cj0 + y];
-                ec[y] = f.x * gu.x - f.y * gu.y;
-                es[y] = f.x * gu.y + f.y * gu.x;
+            for (int i = 0; i < 8 * NT * NT; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // up to three VALU
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
             }
+            __syncthreads();
+            buf ^= 1;
+            cur = nxt;
+        }
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
             for (int x = 0; x < NT; ++x)
 #pragma unroll
                 for (int y = 0; y < NT; ++y) {
-                    acc[x][y] = Mfma<T>::mma(pr[x], ec[y], acc[x][y]);
-                    acc[x][y] = Mfma<T>::mma(pn[x], es[y], acc[x][y]);
-                }
-        }
-        __syncthreads();
-        if (sizeof(T) == 4 && (step % FLUSH) == FLUSH - 1) {
 #pragma unroll
-            for (int x = 0; x < NT; ++x)
-#pragma unroll
-                for (int y = 0; y < NT; ++y) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dacc[x][y][r] += (double)acc[x][y][r];
+                    for (int r = 0; r < 4; ++r) sAcc[slot(x, y, r)] += (double)acc[x][y][r];
                     acc[x][y] = Mfma<T>::zero();
                 }
         }
@@ -308,7 +363,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * (ci0 + x) + Mfma<T>::drow(g, r);
                 const int j = j0 + 16 * (cj0 + y) + q;
-                out[(size_t)i * np + j] = dacc[x][y][r] + (double)acc[x][y][r];
+                out[(size_t)i * np + j] = sizeof(T) == 4 ? sAcc[slot(x, y, r)] : (double)acc[x][y][r];
             }
 }
 
