@@ -113,9 +113,10 @@ def main():
     ds = synth.make_config(args.config)
     ctx = Context.from_dataset(ds, args.precision)
     I = ctx.image()
+    scal = ctx.scalars()
     ctx.cg_init(I, init_to_floor=True)
     for _ in range(args.warmup):
-        ctx.cg_step(I)
+        ctx.cg_step(I, scal)
     if args.graph:
         ctx.cg_run(I, 1, graph=True)
     torch.cuda.synchronize()
@@ -135,7 +136,7 @@ def main():
         ctx.cg_run(I, args.steps, graph=True)
     else:
         for _ in range(args.steps):
-            ctx.cg_step(I)
+            ctx.cg_step(I, scal)
     e1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall

@@ -348,7 +348,9 @@ int uvmem_finalize(uvmem_ctx *c) {
     const int tiles = c->adj_nt * c->adj_nt;
     // split-K chunk length: enough workgroups to fill the GPU several times
     // over, chunks of equal length across channels (uneven channels balance)
-    int64_t target = 512;
+    // adjoint workgroups per launch: one round on 256 CUs (FP32/FP64 kernels
+    // hold one workgroup per CU; the split kernel holds two)
+    int64_t target = c->prec == UVMEM_BF16X3 ? 512 : 256;
     if (const char *env = std::getenv("UVMEM_ADJ_WGS")) target = std::max(1L, std::atol(env));
     int64_t klen = (c->ztot * tiles + target - 1) / target;
     klen = std::max<int64_t>(klen, ADJ_KMIN);

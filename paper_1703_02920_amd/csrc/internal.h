@@ -31,7 +31,7 @@ constexpr int LS_K = 4;
 constexpr double BOUND_TOL = 1e-12;
 // Default number of line-search passes per CG step; a channel whose search
 // has converged skips the remaining passes.
-constexpr int LS_STEPS = 6;
+constexpr int LS_STEPS = 4;
 
 // One forward workgroup: FWD_KV visibilities [k0, k0 + nvalid) of a channel.
 struct FwdItem {

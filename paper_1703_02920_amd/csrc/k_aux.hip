@@ -142,28 +142,40 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
     const VisItem it = items[blockIdx.x];
     double acc[2] = {0.0, 0.0};
     const double alpha = mode == 3 ? scal[(size_t)it.chan * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
-    for (long long k = it.kbeg + threadIdx.x; k < it.kend; k += NTHR) {
-        double2 v = make_double2(0.0, 0.0);
-        if (mode != 3) {
-            for (int ib = 0; ib < n_parts; ++ib) {
-                const double2 p = vpart[(size_t)ib * ztot + k];
-                v.x += p.x;
-                v.y += p.y;
+    constexpr int U = VIS_BLK / NTHR;   // visibilities per thread, loads issued together
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = make_double2(0.0, 0.0);
+    if (mode != 3) {
+        for (int ib = 0; ib < n_parts; ++ib) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long k = it.kbeg + threadIdx.x + (long long)u * NTHR;
+                if (k < it.kend) {
+                    const double2 p = vpart[(size_t)ib * ztot + k];
+                    v[u].x += p.x;
+                    v[u].y += p.y;
+                }
             }
         }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const long long k = it.kbeg + threadIdx.x + (long long)u * NTHR;
+        if (k >= it.kend) continue;
         const double ww = (double)w[k];
         if (mode == 0) {
-            out[k] = v;
+            out[k] = v[u];
         } else if (mode == 1) {
             const float2 o = vo[k];
-            const double2 r = make_double2(v.x - (double)o.x, v.y - (double)o.y);
+            const double2 r = make_double2(v[u].x - (double)o.x, v[u].y - (double)o.y);
             R[k] = r;
             acc[0] += ww * (r.x * r.x + r.y * r.y);
         } else if (mode == 2) {
-            Vd[k] = v;
+            Vd[k] = v[u];
             const double2 r = R[k];
-            acc[0] += ww * (v.x * v.x + v.y * v.y);
-            acc[1] += ww * (r.x * v.x + r.y * v.y);
+            acc[0] += ww * (v[u].x * v[u].x + v[u].y * v[u].y);
+            acc[1] += ww * (r.x * v[u].x + r.y * v[u].y);
         } else {
             const double2 d = Vd[k];
             double2 r = R[k];
