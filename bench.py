@@ -90,21 +90,181 @@ def cpu_baseline(ds, target_s: float = 12.0):
             "seconds": dt}
 
 
+def run_steps(ctx, steps, warmup, graph):
+    """cg_init, warm-up steps, then `steps` timed CG iterations; returns
+    (ms for the timed region, wall seconds, per-kernel average ms)."""
+    import torch
+    I = ctx.image()
+    scal = ctx.scalars()
+    ctx.cg_init(I, init_to_floor=True)
+    for _ in range(warmup):
+        ctx.cg_step(I, scal)
+    if graph:
+        ctx.cg_run(I, 1, graph=True)
+    torch.cuda.synchronize()
+    ctx.timing(not graph)
+    ctx.timing_read(0, reset=True)
+    ctx.timing_read(1, reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(ctx.stream)
+    if graph:
+        ctx.cg_run(I, steps, graph=True)
+    else:
+        for _ in range(steps):
+            ctx.cg_step(I, scal)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    kern = {}
+    for which, name in ((0, "forward"), (1, "adjoint")):
+        tot, cnt = ctx.timing_read(which)
+        if cnt:
+            kern[name] = tot / cnt
+    ctx.timing(False)
+    ctx.check()
+    return ms, t_wall, kern
+
+
+def eval_error(ds, ctx_a, ctx_b):
+    """Relative differences of Phi and grad Phi between two precisions at the
+    P3 evaluation image (same inputs)."""
+    import numpy as np
+    import torch
+    from paper_1703_02920_amd import synth
+    img = torch.tensor(synth.eval_images(ds, "P3"), dtype=torch.float32, device=ctx_a.device)
+    sa, ga = ctx_a.phi_and_grad(img)
+    sb, gb = ctx_b.phi_and_grad(img)
+    torch.cuda.synchronize()
+    phi_a, phi_b = float(sa[:, 0].sum()), float(sb[:, 0].sum())
+    ga, gb = ga.double().cpu().numpy(), gb.double().cpu().numpy()
+    return {"phi": abs(phi_a - phi_b) / abs(phi_b),
+            "grad": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb))}
+
+
+def eval_sweep(configs, precs, reps=20, warmup=3):
+    """M1 per configuration and precision: median time of one Phi + grad Phi
+    evaluation (forward, chi^2, adjoint, entropy, combine) at the P3 image,
+    timed with events on the context's stream."""
+    import numpy as np
+    import torch
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+    rows = []
+    for c in configs:
+        ds = synth.make_config(c)
+        img_np = synth.eval_images(ds, "P3")
+        for prec in precs:
+            if prec == "fp64" and ds.n > 512:
+                continue
+            ctx = Context.from_dataset(ds, prec)
+            img = torch.tensor(img_np, dtype=ctx.dtype, device=ctx.device)
+            scal, grad = ctx.scalars(), torch.empty_like(img)
+            for _ in range(warmup):
+                ctx.phi_and_grad(img, grad, scal)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(ctx.stream)
+                ctx.phi_and_grad(img, grad, scal)
+                e1.record(ctx.stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ctx.check()
+            ms = float(np.median(ts))
+            rows.append({"config": f"c{c}", "precision": prec, "ms_per_eval": ms,
+                         "vis_pixel_evals_per_s": ds.pairs / (ms / 1e3),
+                         "algorithmic_tflops": 8.0 * ds.pairs / (ms / 1e3) / 1e12,
+                         "frac_of_peak": 8.0 * ds.pairs / (ms / 1e3) / 1e12 / PEAK[prec]})
+            print(json.dumps(rows[-1]), flush=True)
+            ctx.close()
+    return rows
+
+
+def cg_compare(c, precs, iters=None):
+    """M2: T graph-replayed projected-CG iterations from I = M in each
+    precision; iterations/s, and the relative error of Phi_T and of the final
+    image against the FP64 trajectory (the FP64 path is held to 1e-12 of the
+    oracle by the parity tests)."""
+    import numpy as np
+    import torch
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+    ds = synth.make_config(c)
+    T = iters or ds.cg_iters
+    res = {}
+    ref = None
+    for prec in ["fp64"] + [p for p in precs if p != "fp64"]:
+        ctx = Context.from_dataset(ds, prec)
+        I = ctx.image()
+        ctx.cg_init(I, init_to_floor=True)
+        ctx.cg_run(I, 1, graph=True)          # capture (and one iteration)
+        ctx.cg_init(I, init_to_floor=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        hist = ctx.cg_run(I, T, graph=True)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = e0.elapsed_time(e1)
+        phi = hist[-1, :, 0].double().sum().item()
+        img = I.double().cpu().numpy()
+        row = {"config": f"c{c}", "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
+               "vis_pixel_evals_per_s": ds.pairs * T / (ms / 1e3), "phi_T": phi}
+        if prec == "fp64":
+            ref = (phi, img)
+        else:
+            row["rel_err_phi_T_vs_fp64"] = abs(phi - ref[0]) / abs(ref[0])
+            row["rel_err_image_T_vs_fp64"] = float(np.linalg.norm(img - ref[1]) / np.linalg.norm(ref[1]))
+        res[prec] = row
+        print(json.dumps(row), flush=True)
+        ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload configuration (1..5)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
     ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision companion runs")
+    ap.add_argument("--eval-sweep", default="", metavar="CONFIGS",
+                    help="only time single Phi + grad evaluations on these configurations (e.g. 1,2,3,4,5)")
+    ap.add_argument("--cg-compare", type=int, default=0, metavar="CONFIG",
+                    help="only run the configuration's CG iterations in every precision vs FP64")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.eval_sweep:
+        eval_sweep([int(x) for x in args.eval_sweep.split(",")], ["fp64", "fp32", "bf16x3", "fp16x3"])
+        return
+    if args.cg_compare:
+        cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"])
+        return
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
+        return
 
     from paper_1703_02920_amd import synth
     from paper_1703_02920_amd.uvmem import Context
@@ -112,46 +272,11 @@ def main():
     torch.cuda.set_device(0)
     ds = synth.make_config(args.config)
     ctx = Context.from_dataset(ds, args.precision)
-    I = ctx.image()
-    scal = ctx.scalars()
-    ctx.cg_init(I, init_to_floor=True)
-    for _ in range(args.warmup):
-        ctx.cg_step(I, scal)
-    if args.graph:
-        ctx.cg_run(I, 1, graph=True)
-    torch.cuda.synchronize()
-    print(f"bench: warmup done ({ds.description})", file=sys.stderr, flush=True)
-
-    ctx.timing(True)
-    ctx.timing_read(0, reset=True)
-    ctx.timing_read(1, reset=True)
-    stream = ctx.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    if args.graph:
-        ctx.timing(False)
-        ctx.cg_run(I, args.steps, graph=True)
-    else:
-        for _ in range(args.steps):
-            ctx.cg_step(I, scal)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1)
-    fwd_ms, fwd_n = ctx.timing_read(0)
-    adj_ms, adj_n = ctx.timing_read(1)
-    ctx.check()
+    print(f"bench: {ds.description}", file=sys.stderr, flush=True)
+    ms, t_wall, kern = run_steps(ctx, args.steps, args.warmup, args.graph)
     pairs = ds.pairs
     value = pairs * args.steps / (ms / 1e3)
     flops_per_launch = 4.0 * pairs          # complex twiddle x real pixel (fwd) / Re(complex x complex) (adj)
-    kern = {}
-    if fwd_n:
-        kern["forward"] = fwd_ms / fwd_n
-    if adj_n:
-        kern["adjoint"] = adj_ms / adj_n
     roof = None
     if kern:
         dom = max(kern, key=kern.get)
@@ -162,6 +287,20 @@ def main():
                 "traffic": traffic_from_profiles("k_adjoint" if dom == "adjoint" else "k_forward", workload),
                 "kernel": dom, "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
                 "other_kernel_ms": {k: v for k, v in kern.items() if k != dom}}
+    mixed = None
+    if args.precision == "fp32" and not args.no_mixed:
+        mixed = {}
+        for mp in ("bf16x3", "fp16x3"):
+            print(f"bench: split-precision ({mp}) run", file=sys.stderr, flush=True)
+            mctx = Context.from_dataset(ds, mp)
+            mms, _, mkern = run_steps(mctx, args.steps, args.warmup, args.graph)
+            mixed[mp] = {"value": pairs * args.steps / (mms / 1e3),
+                         "ms_per_step": mms / args.steps, "cg_iters_per_s": args.steps / (mms / 1e3),
+                         "kernel_ms": mkern,
+                         "mfma_frac_16bit_algorithmic": {k: flops_per_launch / (v / 1e3) / 1e12 / PEAK[mp]
+                                                         for k, v in mkern.items()},
+                         "rel_err_vs_fp32_at_P3": eval_error(ds, mctx, ctx)}
+            mctx.close()
     cpu = None
     if not args.no_cpu:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -177,7 +316,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[args.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3", "fp16x3": "fp16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": ds.description + "; one projected-CG iteration per step",
                    "n": ds.n, "channels": ds.n_chan, "visibilities": ds.total_vis,
@@ -187,6 +326,7 @@ def main():
         "wall_s": t_wall,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     print(json.dumps(out), flush=True)
 

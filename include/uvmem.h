@@ -159,8 +159,13 @@ int uvmem_check(uvmem_ctx *ctx);
 int uvmem_timing_enable(uvmem_ctx *ctx, int enable);
 int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *count, int reset);
 
-/* Introspection: padded side, channel offsets into the visibility arrays,
- * split-K depth chosen for the adjoint. */
+/* Introspection.  uvmem_info writes up to nout of, in order: N, padded side
+ * Np, channels, precision, total visibilities, forward image blocks, adjoint
+ * tile side, adjoint split-K slots, forward items, adjoint items, visibility
+ * items, device bytes held, pixel blocks per channel, pixels per pixel block,
+ * visibilities per visibility item, forward workgroups.  uvmem_chan_range
+ * gives a channel's offset into the concatenated visibility arrays and its
+ * count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);
 int uvmem_chan_range(const uvmem_ctx *ctx, int chan, int64_t *offset, int64_t *nvis);
 

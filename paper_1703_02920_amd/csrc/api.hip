@@ -67,7 +67,7 @@ hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
 }
 
 void free_all(uvmem_ctx *c) {
-    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwd, c->d_adj, c->d_vis,
+    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwd, c->d_fwdp, c->d_adj, c->d_vis,
                     c->d_slot_base, c->d_vis_base, c->d_R, c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr};
@@ -129,32 +129,34 @@ int check_ready(uvmem_ctx *c) {
 int build_layout(uvmem_ctx *c) {
     const int C = c->nchan;
     c->np = ((c->n + 63) / 64) * 64;
-    if (c->prec == UVMEM_BF16X3) {
-        int ib = 128;
-        if (const char *env = std::getenv("UVMEM_FWD_IB")) ib = std::atoi(env);
-        if (ib != 64 && ib != 128 && ib != 256) ib = 128;
-        while (c->np % ib) ib /= 2;
-        c->ib_rows = ib;
-    } else {
-        int ib = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
-        if (c->prec == UVMEM_FP32)
-            if (const char *env = std::getenv("UVMEM_FWD_IB")) ib = std::atoi(env) == 64 ? 64 : ib;
-        c->ib_rows = ib;
-    }
+    // persistent forward: image blocks resident in LDS, 128 x 256 where the
+    // size allows (FP32 and bf16 also sum at most 256 columns in one FP32
+    // accumulator; the blocks are combined in FP64), 64 x 64 in FP64
+    if (c->prec == UVMEM_FP64) { c->ib_rows = 64; c->jb_cols = 64; }
+    else if (c->np % 256 == 0) { c->ib_rows = 128; c->jb_cols = 256; }
+    else if (c->np % 128 == 0) { c->ib_rows = 128; c->jb_cols = 128; }
+    else { c->ib_rows = 64; c->jb_cols = 64; }
     c->n_ib = c->np / c->ib_rows;
-    // FP32 sums at most 256 image columns in one FP32 accumulator; the
-    // column blocks are combined in FP64 with the row blocks
-    c->jb_cols = (c->prec == UVMEM_FP32) ? std::min(c->np, 256) : c->np;
     c->n_jb = c->np / c->jb_cols;
     c->n_fparts = c->n_ib * c->n_jb;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     c->adj_nt = c->np / c->adj_tt;
-    c->n_pb = (int)(((int64_t)c->n * c->n + PIX_BLK - 1) / PIX_BLK);
     c->ls_steps = LS_STEPS;
     if (const char *env = std::getenv("UVMEM_LS_STEPS")) c->ls_steps = std::max(1, std::min(64, std::atoi(env)));
     c->off.assign(C + 1, 0);
     for (int ch = 0; ch < C; ++ch) c->off[ch + 1] = c->off[ch] + c->nvis[ch];
     c->ztot = c->off[C];
+    // pixel and visibility kernels: about PIX_WGS / VIS_WGS workgroups in
+    // all (enough to spread the streaming over the CUs; few enough that the
+    // per-channel partial sums each workgroup recomputes stay short)
+    auto roundup = [](int64_t x, int64_t m) { return ((x + m - 1) / m) * m; };
+    int64_t pix_wgs = PIX_WGS, vis_wgs = VIS_WGS;
+    if (const char *env = std::getenv("UVMEM_PIX_WGS")) pix_wgs = std::max(1L, std::atol(env));
+    if (const char *env = std::getenv("UVMEM_VIS_WGS")) vis_wgs = std::max(1L, std::atol(env));
+    const int64_t npix = (int64_t)c->n * c->n;
+    c->pix_blk = (int)std::max<int64_t>(NTHR, roundup((npix * C + pix_wgs - 1) / pix_wgs, NTHR));
+    c->n_pb = (int)((npix + c->pix_blk - 1) / c->pix_blk);
+    c->vis_blk = (int)std::max<int64_t>(2 * NTHR, roundup((c->ztot + vis_wgs - 1) / vis_wgs, 2 * NTHR));
     return UVMEM_OK;
 }
 
@@ -182,7 +184,7 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     if (n < 2 || n > 8192 || (n % 2) != 0) return UVMEM_EINVAL;
     if (n_chan < 1 || n_chan > 65536) return UVMEM_EINVAL;
     if (mode != UVMEM_CUBE) return UVMEM_EINVAL;
-    if (precision != UVMEM_FP64 && precision != UVMEM_FP32 && precision != UVMEM_BF16X3) return UVMEM_EINVAL;
+    if (precision < UVMEM_FP64 || precision > UVMEM_FP16X3) return UVMEM_EINVAL;
     uvmem_ctx *c = new (std::nothrow) uvmem_ctx();
     if (!c) return UVMEM_ENOMEM;
     c->n = n;
@@ -350,12 +352,13 @@ int uvmem_finalize(uvmem_ctx *c) {
     // over, chunks of equal length across channels (uneven channels balance)
     // adjoint workgroups per launch: one round on 256 CUs (FP32/FP64 kernels
     // hold one workgroup per CU; the split kernel holds two)
-    int64_t target = c->prec == UVMEM_BF16X3 ? 512 : 256;
+    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
+    int64_t target = split ? 512 : 256;
     if (const char *env = std::getenv("UVMEM_ADJ_WGS")) target = std::max(1L, std::atol(env));
     int64_t klen = (c->ztot * tiles + target - 1) / target;
     klen = std::max<int64_t>(klen, ADJ_KMIN);
     // the split-precision adjoint accumulates a chunk in FP32 only: bound it
-    if (c->prec == UVMEM_BF16X3) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
+    if (split) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
     klen = ((klen + 15) / 16) * 16;
     int slot = 0;
     for (int ch = 0; ch < C; ++ch) {
@@ -363,8 +366,8 @@ int uvmem_finalize(uvmem_ctx *c) {
         for (int64_t k = b; k < e; k += FWD_KV)
             fwd.push_back(FwdItem{ch, (int)std::min<int64_t>(FWD_KV, e - k), (long long)k});
         c->h_vis_base[ch] = (int)vis.size();
-        for (int64_t k = b; k < e; k += VIS_BLK)
-            vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + VIS_BLK, e)});
+        for (int64_t k = b; k < e; k += c->vis_blk)
+            vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + c->vis_blk, e)});
         c->h_slot_base[ch] = slot;
         for (int64_t k = b; k < e; k += klen, ++slot)
             for (int ti = 0; ti < c->adj_nt; ++ti)
@@ -372,6 +375,27 @@ int uvmem_finalize(uvmem_ctx *c) {
                     adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k, (long long)std::min<int64_t>(k + klen, e)});
     }
     c->h_slot_base[C] = slot;
+    // persistent forward: workgroups spread over the image
+    // blocks in proportion to their channel's visibility count
+    std::vector<FwdPItem> fwdp;
+    if (c->ztot > 0) {
+        int64_t wgs = 256;
+        if (const char *env = std::getenv("UVMEM_FWD_WGS")) wgs = std::max(1L, std::atol(env));
+        const int nblk = c->n_ib * c->n_jb;
+        for (int ch = 0; ch < C; ++ch) {
+            const int64_t nv = c->nvis[ch];
+            if (nv == 0) continue;
+            const int64_t tiles = (nv + 15) / 16;
+            int64_t g = (int64_t)std::llround((double)wgs * (double)nv / (double)c->ztot / nblk);
+            g = std::max<int64_t>(1, std::min<int64_t>(g, (tiles + 7) / 8));
+            for (int ib = 0; ib < c->n_ib; ++ib)
+                for (int jb = 0; jb < c->n_jb; ++jb)
+                    for (int64_t x = 0; x < g; ++x)
+                        fwdp.push_back(FwdPItem{ch, ib, jb, ib * c->n_jb + jb, (int)x, (int)g,
+                                                (long long)c->off[ch], (long long)c->off[ch + 1]});
+        }
+    }
+    c->n_fwdp = (int)fwdp.size();
     c->h_vis_base[C] = (int)vis.size();
     c->n_slots = slot;
     c->n_fwd = (int)fwd.size();
@@ -416,6 +440,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_w, c->ztot));
     ok(dalloc(c, (char **)&c->d_beam, C * npix * rs));
     ok(dalloc(c, &c->d_fwd, fwd.size()));
+    ok(dalloc(c, &c->d_fwdp, fwdp.size()));
     ok(dalloc(c, &c->d_adj, adj.size()));
     ok(dalloc(c, &c->d_vis, vis.size()));
     ok(dalloc(c, &c->d_slot_base, C + 1));
@@ -452,6 +477,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_w, w.data(), w.size() * 4);
     up(c->d_beam, beam.data(), beam.size());
     up(c->d_fwd, fwd.data(), fwd.size() * sizeof(FwdItem));
+    up(c->d_fwdp, fwdp.data(), fwdp.size() * sizeof(FwdPItem));
     up(c->d_adj, adj.data(), adj.size() * sizeof(AdjItem));
     up(c->d_vis, vis.data(), vis.size() * sizeof(VisItem));
     up(c->d_slot_base, c->h_slot_base.data(), (C + 1) * sizeof(int));
@@ -497,6 +523,7 @@ int uvmem_adjoint(uvmem_ctx *c, const void *coef, void *img) {
     int s = check_ready(c);
     if (s) return s;
     if ((!coef && c->ztot) || !img) return fail(c, UVMEM_EINVAL, "null coefficients or output");
+    HIPCHK(c, launch_coef_max(c, (const double2 *)coef, c->stream));
     HIPCHK(c, timed_dft(c, 1, nullptr, (const double2 *)coef, nullptr));
     HIPCHK(c, launch_grad(c, nullptr, img, 0, c->stream));
     return UVMEM_OK;
@@ -690,7 +717,8 @@ int uvmem_timing_read(uvmem_ctx *c, int which, double *total_ms, int64_t *count,
 int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     if (!c || !out) return UVMEM_EINVAL;
     const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
-                            c->n_fwd, c->n_adj, c->n_visit, (int64_t)c->bytes_device};
+                            c->n_fwd, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
+                            c->vis_blk, c->n_fwdp};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
     return UVMEM_OK;

@@ -14,10 +14,13 @@ namespace uvm {
 
 // Visibilities per forward workgroup (4 waves x 16 MFMA rows).
 constexpr int FWD_KV = 64;
-// Visibilities per visibility-reduction workgroup item.
-constexpr int VIS_BLK = 2048;
-// Pixels per pixel-kernel workgroup (256 threads x 4).
-constexpr int PIX_BLK = 1024;
+// Threads per workgroup of the pixel, visibility and scalar kernels.
+constexpr int NTHR = 256;
+// Target workgroup counts of the visibility kernels and of the pixel kernels
+// (over all channels); a visibility item is a multiple of 2 NTHR
+// visibilities, a pixel block a multiple of NTHR pixels.
+constexpr int VIS_WGS = 1024;
+constexpr int PIX_WGS = 1024;
 // Minimum visibilities per adjoint split-K chunk (multiple of 16).
 constexpr int ADJ_KMIN = 256;
 // Maximum visibilities per split-K chunk of the split-precision adjoint,
@@ -38,6 +41,20 @@ struct FwdItem {
     int chan;
     int nvalid;
     long long k0;
+};
+
+// One workgroup of the persistent split-precision forward model: image block
+// (ib, jb) of a channel resident in LDS; the workgroup is number `wg` of the
+// `nwg` sharing that block's visibility tiles.
+struct FwdPItem {
+    int chan;
+    int ib;
+    int jb;
+    int part;
+    int wg;
+    int nwg;
+    long long kbeg;
+    long long kend;
 };
 
 // One adjoint workgroup: a square pixel tile (ti, tj) of a channel and a
@@ -115,6 +132,8 @@ struct uvmem_ctx {
     int adj_tt = 0, adj_nt = 0;        // adjoint tile side, tiles per side
     int n_slots = 0;
     int n_pb = 0;                      // pixel blocks per channel
+    int pix_blk = 0;                   // pixels per pixel block (multiple of NTHR)
+    int vis_blk = 0;                   // visibilities per visibility item (multiple of 2 NTHR)
     int ls_steps = 8;                  // line-search passes per CG step
     std::vector<int> h_slot_base;      // nchan+1
     std::vector<int> h_vis_base;       // nchan+1
@@ -126,6 +145,8 @@ struct uvmem_ctx {
     float *d_w = nullptr;
     void *d_beam = nullptr;                     // real [C][n][n]
     uvm::FwdItem *d_fwd = nullptr;
+    uvm::FwdPItem *d_fwdp = nullptr;
+    int n_fwdp = 0;
     uvm::AdjItem *d_adj = nullptr;
     uvm::VisItem *d_vis = nullptr;
     int *d_slot_base = nullptr, *d_vis_base = nullptr;
@@ -172,6 +193,9 @@ hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st);
 hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st);
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st);
+// Per-item max |coef| (slot 2 of the visibility partials) for the scaled
+// fp16 adjoint; no-op for the other precisions.
+hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t st);
 hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st);
 hipError_t launch_chan_phi(const uvmem_ctx *c, double *user_scal, hipStream_t st);
 hipError_t launch_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st);

@@ -15,8 +15,6 @@
 namespace uvm {
 namespace {
 
-constexpr int NTHR = 256;
-
 // ---------------------------------------------------------------- reductions
 // Sum K doubles over the workgroup; every thread receives the totals.
 template <int K>
@@ -69,22 +67,6 @@ __device__ __forceinline__ double min_partials(const double *base, int n_items, 
     return block_min(m);
 }
 
-// ---------------------------------------------------------------- operand store
-// The DFT operand image: plain (SPLIT = 0, element type R) or split into
-// bf16 hi and lo halves (SPLIT = 1; lo at element offset lo_off).
-template <typename R, int SPLIT>
-__device__ __forceinline__ void store_op(void *bop, size_t idx, size_t lo_off, R v) {
-    if constexpr (SPLIT == 0) {
-        reinterpret_cast<R *>(bop)[idx] = v;
-    } else {
-        __bf16 *h = reinterpret_cast<__bf16 *>(bop);
-        const float x = (float)v;
-        const __bf16 hh = (__bf16)x;
-        h[idx] = hh;
-        h[lo_off + idx] = (__bf16)(x - (float)hh);
-    }
-}
-
 // ---------------------------------------------------------------- fill
 template <typename R>
 __global__ void k_fill(R *__restrict__ x, R value, long long count) {
@@ -96,11 +78,11 @@ __global__ void k_fill(R *__restrict__ x, R value, long long count) {
 // ---------------------------------------------------------------- prologue
 // B = A o I written into the padded operand image; optional entropy partial
 // S = sum I ln(I/M) and the domain flag (I <= 0 or NaN).
-template <typename R, int SPLIT>
+template <typename R>
 __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, const R *__restrict__ beam,
-                                                   void *__restrict__ bop, size_t lo_off,
+                                                   R *__restrict__ bop,
                                                    double *__restrict__ ppart,
-                                                   int *__restrict__ flag, int n, int np, int n_pb,
+                                                   int *__restrict__ flag, int n, int np, int n_pb, int pb_len,
                                                    double M, int with_entropy) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
@@ -109,12 +91,12 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
     const size_t cb = (size_t)c * np * np;
     double s[1] = {0.0};
     int bad = 0;
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const int i = (int)(p / n), j = (int)(p % n);
         const R x = Ic[p];
-        store_op<R, SPLIT>(bop, cb + (size_t)i * np + j, lo_off, Ac[p] * x);
+        bop[cb + (size_t)i * np + j] = Ac[p] * x;
         if (with_entropy) {
             const double xd = (double)x;
             if (!(xd > 0.0)) bad = 1;
@@ -133,64 +115,78 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
 // mode 1: R_k = V_k - Vo_k -> R; partial[0] = sum w |R|^2
 // mode 2: Vd_k = V_k -> Vd; partial[0] = sum w |Vd|^2, partial[1] = sum w Re(conj(R) Vd)
 // mode 3: R_k += alpha_c Vd_k; partial[0] = sum w |R|^2
+// mode 4: R is a caller's coefficient vector, only read (w may be null)
+// with_max (modes 1, 3, 4): partial[2] = max over the item of w max(|Re R|, |Im R|)
 __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
                                               const double2 *__restrict__ vpart, int n_parts, long long ztot,
                                               const float2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
-                                              double *__restrict__ vispart, int mode) {
+                                              double *__restrict__ vispart, int mode, int with_max) {
     const VisItem it = items[blockIdx.x];
     double acc[2] = {0.0, 0.0};
+    double cmax = 0.0;   // max |Re|, |Im| of the adjoint's coefficients w R (mode 4: R alone)
     const double alpha = mode == 3 ? scal[(size_t)it.chan * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
-    constexpr int U = VIS_BLK / NTHR;   // visibilities per thread, loads issued together
-    double2 v[U];
+    constexpr int U = 2;   // visibilities per thread and round, loads issued together
+    for (long long k0 = it.kbeg; k0 < it.kend; k0 += U * NTHR) {
+        double2 v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = make_double2(0.0, 0.0);
-    if (mode != 3) {
-        for (int ib = 0; ib < n_parts; ++ib) {
+        for (int u = 0; u < U; ++u) v[u] = make_double2(0.0, 0.0);
+        if (mode < 3) {
+            for (int ib = 0; ib < n_parts; ++ib) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const long long k = it.kbeg + threadIdx.x + (long long)u * NTHR;
-                if (k < it.kend) {
-                    const double2 p = vpart[(size_t)ib * ztot + k];
-                    v[u].x += p.x;
-                    v[u].y += p.y;
+                for (int u = 0; u < U; ++u) {
+                    const long long k = k0 + threadIdx.x + (long long)u * NTHR;
+                    if (k < it.kend) {
+                        const double2 p = vpart[(size_t)ib * ztot + k];
+                        v[u].x += p.x;
+                        v[u].y += p.y;
+                    }
                 }
             }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const long long k = it.kbeg + threadIdx.x + (long long)u * NTHR;
-        if (k >= it.kend) continue;
-        const double ww = (double)w[k];
-        if (mode == 0) {
-            out[k] = v[u];
-        } else if (mode == 1) {
-            const float2 o = vo[k];
-            const double2 r = make_double2(v[u].x - (double)o.x, v[u].y - (double)o.y);
-            R[k] = r;
-            acc[0] += ww * (r.x * r.x + r.y * r.y);
-        } else if (mode == 2) {
-            Vd[k] = v[u];
-            const double2 r = R[k];
-            acc[0] += ww * (v[u].x * v[u].x + v[u].y * v[u].y);
-            acc[1] += ww * (r.x * v[u].x + r.y * v[u].y);
-        } else {
-            const double2 d = Vd[k];
-            double2 r = R[k];
-            r.x += alpha * d.x;
-            r.y += alpha * d.y;
-            R[k] = r;
-            acc[0] += ww * (r.x * r.x + r.y * r.y);
+        for (int u = 0; u < U; ++u) {
+            const long long k = k0 + threadIdx.x + (long long)u * NTHR;
+            if (k >= it.kend) continue;
+            const double ww = w ? (double)w[k] : 1.0;
+            if (mode == 0) {
+                out[k] = v[u];
+            } else if (mode == 1) {
+                const float2 o = vo[k];
+                const double2 r = make_double2(v[u].x - (double)o.x, v[u].y - (double)o.y);
+                R[k] = r;
+                acc[0] += ww * (r.x * r.x + r.y * r.y);
+                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+            } else if (mode == 2) {
+                Vd[k] = v[u];
+                const double2 r = R[k];
+                acc[0] += ww * (v[u].x * v[u].x + v[u].y * v[u].y);
+                acc[1] += ww * (r.x * v[u].x + r.y * v[u].y);
+            } else if (mode == 3) {
+                const double2 d = Vd[k];
+                double2 r = R[k];
+                r.x += alpha * d.x;
+                r.y += alpha * d.y;
+                R[k] = r;
+                acc[0] += ww * (r.x * r.x + r.y * r.y);
+                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+            } else {
+                const double2 r = R[k];
+                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+            }
         }
     }
-    if (mode != 0) {
+    if (mode != 0 && mode != 4) {
         block_sum<2>(acc);
         if (threadIdx.x == 0) {
             vispart[(size_t)blockIdx.x * NPART + 0] = acc[0];
             vispart[(size_t)blockIdx.x * NPART + 1] = acc[1];
         }
+    }
+    if (with_max && mode != 0 && mode != 2) {
+        cmax = -block_min(-cmax);
+        if (threadIdx.x == 0) vispart[(size_t)blockIdx.x * NPART + 2] = cmax;
     }
 }
 
@@ -200,69 +196,70 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
 // mode 1: out = A o G + lambda (ln(I/M) + 1)            (grad Phi)
 // mode 2: as 1 into g; gt = g with zeros on the active set; partials
 //         [0] = gt_new . gt_new, [1] = gt_new . gt_old; gt updated in place.
-template <typename R>
+template <typename R, int RP>
 __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart, const int *__restrict__ slot_base,
                                                const R *__restrict__ beam, const R *__restrict__ I,
                                                R *__restrict__ out, R *__restrict__ gt,
-                                               double *__restrict__ ppart, int n, int np, int n_pb,
+                                               double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
                                                double M, double Mb, double lam, int mode) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const int s0 = slot_base[c], s1 = slot_base[c + 1];
     const size_t np2 = (size_t)np * np;
-    constexpr int RP = PIX_BLK / NTHR;
-    // fixed-order sum over the slots for the thread's RP pixels, 8 slots x RP
-    // pixels of independent loads in flight
-    size_t off[RP];
-    bool okp[RP];
-#pragma unroll
-    for (int r = 0; r < RP; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
-        okp[r] = p < npix;
-        const long long pc = okp[r] ? p : 0;
-        off[r] = (size_t)(pc / n) * np + (size_t)(pc % n);
-    }
-    double Gs[RP];
-#pragma unroll
-    for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
-    int s = s0;
-    for (; s + 8 <= s1; s += 8) {
-        double v[RP][8];
-#pragma unroll
-        for (int r = 0; r < RP; ++r)
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[r][u] = gpart[(size_t)(s + u) * np2 + off[r]];
-#pragma unroll
-        for (int r = 0; r < RP; ++r)
-#pragma unroll
-            for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
-    }
-    for (; s < s1; ++s) {
-#pragma unroll
-        for (int r = 0; r < RP; ++r) Gs[r] += gpart[(size_t)s * np2 + off[r]];
-    }
     double acc[2] = {0.0, 0.0};
+    // groups of RP pixels per thread; fixed-order sum over the slots with
+    // 8 slots x RP pixels of independent loads in flight
+    for (int g0 = 0; g0 < pb_len; g0 += RP * NTHR) {
+        size_t off[RP];
+        bool okp[RP];
 #pragma unroll
-    for (int r = 0; r < RP; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
-        if (!okp[r]) break;
-        const double G = Gs[r];
-        const size_t q = (size_t)c * npix + p;
-        double gv = (double)beam[q] * G;
-        if (mode >= 1) {
-            const double x = (double)I[q];
-            gv += lam * (log(x / M) + 1.0);
+        for (int r = 0; r < RP; ++r) {
+            const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
+            okp[r] = g0 + r * NTHR < pb_len && p < npix;
+            const long long pc = okp[r] ? p : 0;
+            off[r] = (size_t)(pc / n) * np + (size_t)(pc % n);
         }
-        const R gr = (R)gv;
-        out[q] = gr;
-        if (mode == 2) {
-            const double x = (double)I[q];
-            const bool act = (x <= Mb * (1.0 + BOUND_TOL)) && ((double)gr > 0.0);
-            const double gnew = act ? 0.0 : (double)gr;
-            const double gold = (double)gt[q];
-            gt[q] = (R)gnew;
-            acc[0] += gnew * gnew;
-            acc[1] += gnew * gold;
+        double Gs[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
+        int s = s0;
+        for (; s + 8 <= s1; s += 8) {
+            double v[RP][8];
+#pragma unroll
+            for (int r = 0; r < RP; ++r)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[r][u] = gpart[(size_t)(s + u) * np2 + off[r]];
+#pragma unroll
+            for (int r = 0; r < RP; ++r)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
+        }
+        for (; s < s1; ++s) {
+#pragma unroll
+            for (int r = 0; r < RP; ++r) Gs[r] += gpart[(size_t)s * np2 + off[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            if (!okp[r]) continue;
+            const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
+            const double G = Gs[r];
+            const size_t q = (size_t)c * npix + p;
+            double gv = (double)beam[q] * G;
+            if (mode >= 1) {
+                const double x = (double)I[q];
+                gv += lam * (log(x / M) + 1.0);
+            }
+            const R gr = (R)gv;
+            out[q] = gr;
+            if (mode == 2) {
+                const double x = (double)I[q];
+                const bool act = (x <= Mb * (1.0 + BOUND_TOL)) && ((double)gr > 0.0);
+                const double gnew = act ? 0.0 : (double)gr;
+                const double gold = (double)gt[q];
+                gt[q] = (R)gnew;
+                acc[0] += gnew * gnew;
+                acc[1] += gnew * gold;
+            }
         }
     }
     if (mode == 2) {
@@ -302,12 +299,12 @@ __global__ __launch_bounds__(NTHR) void k_chan_phi(const double *__restrict__ vi
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const R *__restrict__ g,
                                                   R *__restrict__ gt, R *__restrict__ dir,
-                                                  double *__restrict__ ppart, int n, int n_pb, double Mb) {
+                                                  double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     double acc[1] = {0.0};
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double x = (double)I[q], gv = (double)g[q];
@@ -348,14 +345,14 @@ template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const R *__restrict__ g,
                                                  const R *__restrict__ gt, R *__restrict__ dir,
                                                  const double *__restrict__ scal, const double *__restrict__ chan,
-                                                 double *__restrict__ ppart, int n, int n_pb, double Mb) {
+                                                 double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const double beta = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_BETA];
     const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
     double acc[1] = {0.0};
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double x = (double)I[q], gv = (double)g[q], gtv = (double)gt[q];
@@ -374,14 +371,14 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
 
 // Step 3: apply the restart, stage B = A o d for the forward model, and the
 // partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts).
-template <typename R, int SPLIT>
+template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
                                                   R *__restrict__ dir, const R *__restrict__ beam,
-                                                  void *__restrict__ bop, size_t lo_off,
+                                                  R *__restrict__ bop,
                                                   const double *__restrict__ pp_gtd,
                                                   const double *__restrict__ scal,
                                                   double *__restrict__ chan,
-                                                  double *__restrict__ ppart, int n, int np, int n_pb,
+                                                  double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
                                                   double M, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
@@ -403,8 +400,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
     const size_t cb = (size_t)c * np * np;
     double amax = INFINITY;
     double acc[2] = {0.0, 0.0};
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         double d = (double)dir[q];
@@ -414,7 +411,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         d = (double)dr;
         dir[q] = dr;
         const int i = (int)(p / n), j = (int)(p % n);
-        store_op<R, SPLIT>(bop, cb + (size_t)i * np + j, lo_off, beam[q] * dr);
+        bop[cb + (size_t)i * np + j] = beam[q] * dr;
         const double x = (double)I[q];
         if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
@@ -574,7 +571,7 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
                                                   const double *__restrict__ pp_prev, double *__restrict__ pp_next,
                                                   const double *__restrict__ vispart, const int *__restrict__ vis_base,
                                                   const double *__restrict__ chan,
-                                                  int n, int n_pb, double M, double lam, int first) {
+                                                  int n, int n_pb, int pb_len, double M, double lam, int first) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
@@ -606,8 +603,8 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
     double acc[2 * LS_K];
 #pragma unroll
     for (int m = 0; m < 2 * LS_K; ++m) acc[m] = 0.0;
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double d = (double)dir[q];
@@ -634,7 +631,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
                                                     const double *__restrict__ ls_prev, const double *__restrict__ pp_prev,
                                                     double *__restrict__ pp_out, double *__restrict__ scal,
                                                     double *__restrict__ chan, int *__restrict__ flag,
-                                                    int n, int n_pb, double M, double Mb, double lam) {
+                                                    int n, int n_pb, int pb_len, double M, double Mb, double lam) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
@@ -658,8 +655,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
     }
     double acc[1] = {0.0};
     int bad = 0;
-    for (int r = 0; r < PIX_BLK / NTHR; ++r) {
-        const long long p = (long long)pb * PIX_BLK + r * NTHR + threadIdx.x;
+    for (int r = 0; r < pb_len / NTHR; ++r) {
+        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         double x = (double)I[q];
@@ -726,35 +723,48 @@ inline int pix_grid(const uvmem_ctx *c) { return c->nchan * c->n_pb; }
 inline double *pp(const uvmem_ctx *c, int buf) {
     return c->d_ppart + (size_t)buf * c->nchan * c->n_pb * NPART;
 }
+// The fp16 split adjoint scales its coefficients by the channel's max |w R|,
+// which the visibility pass leaves in slot 2 of its partial records.
+inline int adj_scaled(const uvmem_ctx *c) { return c->prec == UVMEM_FP16X3 ? 1 : 0; }
 inline double *lsb(const uvmem_ctx *c, int buf) { return c->d_ls + (size_t)buf * c->nchan * LSS_N; }
 
-inline size_t lo_off(const uvmem_ctx *c) { return (size_t)c->nchan * c->np * c->np; }
-
-template <typename R, int SPLIT>
+template <typename R>
 hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
-    hipLaunchKernelGGL((k_prologue<R, SPLIT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_beam),
-                       c->d_bop, lo_off(c), pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->M, with_entropy);
+    hipLaunchKernelGGL(k_prologue<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_beam),
+                       P<R>(c->d_bop), pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->pix_blk, c->M, with_entropy);
     return hipGetLastError();
+}
+
+// k_grad with 4 pixels per thread and round when the pixel blocks are long
+// enough, else 1 (more workgroups, fewer loads in flight per thread)
+template <typename R>
+void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+    if (c->pix_blk >= 4 * NTHR)
+        hipLaunchKernelGGL((k_grad<R, 4>), dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
+                           CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
+                           c->pix_blk, c->M, c->Mb, c->lam, mode);
+    else
+        hipLaunchKernelGGL((k_grad<R, 1>), dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
+                           CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
+                           c->pix_blk, c->M, c->Mb, c->lam, mode);
 }
 
 template <typename R>
 hipError_t t_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
-                       CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), pp(c, 1), c->n, c->np, c->n_pb,
-                       c->M, c->Mb, c->lam, mode);
+    grad_launch<R>(c, I, out, pp(c, 1), mode, st);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t t_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_g),
-                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->Mb);
+                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
     hipLaunchKernelGGL(k_chan_cg_init, dim3(c->nchan), dim3(NTHR), 0, st, pp(c, 0), c->n_pb, c->d_scal,
                        c->d_chan);
     return hipGetLastError();
 }
 
-template <typename R, int SPLIT>
+template <typename R>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st);
 
 }  // namespace
@@ -770,15 +780,23 @@ hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t 
 }
 
 hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
-    if (c->prec == UVMEM_FP64) return t_prologue<double, 0>(c, I, with_entropy, st);
-    if (c->prec == UVMEM_BF16X3) return t_prologue<float, 1>(c, I, with_entropy, st);
-    return t_prologue<float, 0>(c, I, with_entropy, st);
+    return c->prec == UVMEM_FP64 ? t_prologue<double>(c, I, with_entropy, st)
+                                 : t_prologue<float>(c, I, with_entropy, st);
 }
 
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st) {
     if (c->n_visit == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
-                       (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart, mode);
+                       (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart, mode,
+                       adj_scaled(c));
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t st) {
+    if (c->n_visit == 0 || !adj_scaled(c)) return hipSuccess;
+    hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
+                       (long long)c->ztot, c->d_vo, (const float *)nullptr, const_cast<double2 *>(coef), c->d_Vd,
+                       (double2 *)nullptr, c->d_scal, c->d_vispart, 4, 1);
     return hipGetLastError();
 }
 
@@ -803,17 +821,17 @@ hipError_t launch_copy_scal(const uvmem_ctx *c, double *, long long *ctr, hipStr
 }
 
 namespace {
-template <typename R, int SPLIT>
+template <typename R>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
     hipError_t e;
     const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
     // 1. direction update and projection; partial gt.d
     hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->Mb);
+                       c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
     // 2-3. restart test, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
-    hipLaunchKernelGGL((k_cg_dir2<R, SPLIT>), gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       CP<R>(c->d_beam), c->d_bop, lo_off(c), pp(c, 0), c->d_scal, c->d_chan, pp(c, 1), c->n,
-                       c->np, c->n_pb, c->M, c->Mb);
+    hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
+                       CP<R>(c->d_beam), P<R>(c->d_bop), pp(c, 0), c->d_scal, c->d_chan, pp(c, 1), c->n,
+                       c->np, c->n_pb, c->pix_blk, c->M, c->Mb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. Vd = F(d)
     return hipSuccess;
@@ -835,16 +853,16 @@ hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t
 }
 
 namespace {
-template <typename R, int SPLIT>
+template <typename R>
 hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
     const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
-    if (phase == 0) return t_cg_step<R, SPLIT>(c, I, user, st);
+    if (phase == 0) return t_cg_step<R>(c, I, user, st);
     if (phase == 1) {
         // 5. Vd and the quadratic coefficients a, b of chi^2 along d
         if (c->n_visit)
             hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, 2);
+                               c->d_scal, c->d_vispart, 2, 0);
         // 6-7. line search: pass 0 initialises the state (from the visibility
         // partials and the direction pass's partials in pp[1]); pass t > 0
         // advances S^t-1 (ls[t%2]) with P^t-1 (pp[(t+1)%2]); every pass
@@ -853,24 +871,23 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         for (int t = 0; t < L; ++t) {
             hipLaunchKernelGGL(k_ls_step<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_dir), lsb(c, t % 2),
                                lsb(c, (t + 1) % 2), pp(c, (t + 1) % 2), pp(c, t % 2), c->d_vispart,
-                               c->d_vis_base, c->d_chan, c->n, c->n_pb, c->M, c->lam, t == 0 ? 1 : 0);
+                               c->d_vis_base, c->d_chan, c->n, c->n_pb, c->pix_blk, c->M, c->lam, t == 0 ? 1 : 0);
         }
         const int last = (L - 1) % 2;   // pp buffer holding the last partials
         // 8. final update of the step, I <- max(I + alpha d, M), entropy partial
         hipLaunchKernelGGL(k_cg_update<R>, gp, blk, 0, st, P<R>(I), CP<R>(c->d_dir), lsb(c, 1 - last),
-                           pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->M,
+                           pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->pix_blk, c->M,
                            c->Mb, c->lam);
         // 9. R <- R + alpha Vd, chi^2 partials
         if (c->n_visit)
             hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, 3);
+                               c->d_scal, c->d_vispart, 3, adj_scaled(c));
         return hipGetLastError();
     }
     // 11. gradient at the new point, projected gradient, PR partials
     const int last = (c->ls_steps - 1) % 2;
-    hipLaunchKernelGGL(k_grad<R>, gp, blk, 0, st, c->d_gpart, c->d_slot_base, CP<R>(c->d_beam), CP<R>(I),
-                       P<R>(c->d_g), P<R>(c->d_gt), pp(c, last), c->n, c->np, c->n_pb, c->M, c->Mb, c->lam, 2);
+    grad_launch<R>(c, I, c->d_g, pp(c, last), 2, st);
     // 12. beta and scalars
     hipLaunchKernelGGL(k_chan_beta, gc, blk, 0, st, c->d_vispart, c->d_vis_base, pp(c, 1 - last), pp(c, last),
                        c->n_pb, c->lam, c->d_scal, c->d_chan, user);
@@ -879,9 +896,8 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
 }  // namespace
 
 hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
-    if (c->prec == UVMEM_FP64) return t_cg_phase<double, 0>(c, I, user, phase, st);
-    if (c->prec == UVMEM_BF16X3) return t_cg_phase<float, 1>(c, I, user, phase, st);
-    return t_cg_phase<float, 0>(c, I, user, phase, st);
+    return c->prec == UVMEM_FP64 ? t_cg_phase<double>(c, I, user, phase, st)
+                                 : t_cg_phase<float>(c, I, user, phase, st);
 }
 
 }  // namespace uvm

@@ -189,6 +189,119 @@ __global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ ite
     }
 }
 
+// Forward, FP32 / FP64, persistent.  As k_forward_bf16p: a workgroup of eight
+// waves keeps the image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams
+// 16-visibility tiles through its waves.  Twiddles are correctly rounded
+// (sincospi of FP64-reduced phases): E_u[k][j0 + 16 m + 4 g + s] =
+// E(j0 + 16 m - N/2) E(4 g + s); the row dot uses E_v = E(i0 + q - N/2) E(16 t)
+// with the second factors in a per-wave LDS table, accumulated in FP64.
+template <typename T, int IB, int JB>
+__global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict__ items,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ b,
+                                                      const T *__restrict__ bop, double2 *__restrict__ vpart,
+                                                      int n, int np, long long ztot) {
+    typedef typename Mfma<T>::acc acc_t;
+    typedef typename Vec4<T>::type T4;
+    typedef typename C2T<T>::type C2;
+    constexpr int NT = IB / 16;
+    constexpr int PADC = 4;
+    __shared__ __attribute__((aligned(16))) T sB[IB][JB + PADC];
+    __shared__ C2 sCo[8][16][NT];
+
+    const FwdPItem it = items[blockIdx.x];
+    const int i0 = it.ib * IB, j0 = it.jb * JB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int half = n / 2;
+    {
+        const T *B = bop + (size_t)it.chan * np * np;
+        constexpr int VROW = JB / 4;
+        for (int x = tid; x < IB * VROW; x += 512) {
+            const int row = x / VROW, c4 = x % VROW;
+            *reinterpret_cast<T4 *>(&sB[row][4 * c4]) =
+                *reinterpret_cast<const T4 *>(B + (size_t)(i0 + row) * np + j0 + 4 * c4);
+        }
+    }
+    __syncthreads();
+    const long long nk = it.kend - it.kbeg;
+    const long long ntiles = (nk + 15) / 16;
+    const long long stride = 8LL * it.nwg;
+    for (long long tile = (long long)it.wg * 8 + wave; tile < ntiles; tile += stride) {
+        const long long k0 = it.kbeg + 16 * tile;
+        const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
+        const double ak = q < nvalid ? a[k0 + q] : 0.0;
+        T fc[4], fs[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
+        acc_t accR[NT], accI[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            accR[t] = Mfma<T>::zero();
+            accI[t] = Mfma<T>::zero();
+        }
+#pragma unroll 2
+        for (int js = 0; js < JB; js += 16) {
+            T cc, sc;
+            cis2pi((T)phase(ak, j0 + js - half), cc, sc);
+            T cr[4], ci[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                cr[s] = cc * fc[s] - sc * fs[s];
+                ci[s] = -(sc * fc[s] + cc * fs[s]);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const T4 bv = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
+                accR[t] = Mfma<T>::mma(cr[0], bv.x, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[0], bv.x, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[1], bv.y, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[1], bv.y, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[2], bv.z, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[2], bv.z, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[3], bv.w, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[3], bv.w, accI[t]);
+            }
+        }
+        // per-wave coarse factors E(16 b_k t) of the tile's 16 rows
+        for (int e = lane; e < 16 * NT; e += 64) {
+            const int kk = e / NT, t = e % NT;
+            const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
+            T c, sn;
+            cis2pi((T)phase(bk, 16 * t), c, sn);
+            sCo[wave][kk][t] = C2{c, sn};
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kk = Mfma<T>::drow(g, r);
+            const bool ok = kk < nvalid;
+            const double bk = ok ? b[k0 + kk] : 0.0;
+            T fcq, fsq;
+            cis2pi((T)phase(bk, i0 + q - half), fcq, fsq);
+            double vr = 0.0, vi = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const C2 co = sCo[wave][kk][t];
+                const double cd = (double)(fcq * co.x - fsq * co.y);
+                const double sd = (double)(fsq * co.x + fcq * co.y);
+                const double tr = (double)accR[t][r], ti = (double)accI[t][r];
+                vr += cd * tr + sd * ti;
+                vi += cd * ti - sd * tr;
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                vr += __shfl_xor(vr, o, 64);
+                vi += __shfl_xor(vi, o, 64);
+            }
+            if (q == 0 && ok) vpart[(size_t)it.part * ztot + k0 + kk] = make_double2(vr, vi);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Adjoint.  Workgroup tile TT x TT pixels (TT = 2 WT), 2 x 2 waves of WT x WT.
 // Per 16-visibility super-step the workgroup writes to LDS, for k in the step,
@@ -369,22 +482,46 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
 
 
 // ----------------------------------------------------------------------------
-// Split precision (bf16 hi + lo, three products per real product):
-//   x y ~= x_h y_h + x_h y_l + x_l y_h,  x_h = RN_bf16(x), x_l = RN_bf16(x - x_h),
-// on v_mfma_f32_16x16x32_bf16 (lane l supplies A[l%16][8 (l/16) + e] and
+// Split precision (16-bit hi + lo, three products per real product):
+//   x y ~= x_h y_h + x_h y_l + x_l y_h,  x_h = RN_16(x), x_l = RN_16(x - x_h),
+// on v_mfma_f32_16x16x32_{bf16,f16} (lane l supplies A[l%16][8 (l/16) + e] and
 // B[8 (l/16) + e][l%16], e = 0..7; it holds D[4 (l/16) + r][l%16]) with FP32
 // accumulation, folded into FP64 periodically.  The dropped x_l y_l term and
 // the representation error leave ~2^-16 relative error per product.
 // ----------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ floatx4 mma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+// 16-bit operand formats of the split path.  bf16 keeps the FP32 exponent
+// range (no scaling); fp16 has 11-bit halves (hi + lo ~ 22 bits) but a narrow
+// range, so its operands are scaled by powers of two to a magnitude <= 1
+// (v_mfma_f32_16x16x32_f16 has the same lane layout as the bf16 form).
+template <typename H> struct Half16;
+template <> struct Half16<__bf16> {
+    typedef bf16x8 h8;
+    static constexpr bool scaled = false;
+    static __device__ __forceinline__ floatx4 mma(h8 a, h8 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Half16<_Float16> {
+    typedef f16x8 h8;
+    static constexpr bool scaled = true;
+    static __device__ __forceinline__ floatx4 mma(h8 a, h8 b, floatx4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename H>
+__device__ __forceinline__ void split16(float x, H &h, H &l) {
+    h = (H)x;
+    l = (H)(x - (float)h);
 }
 
-__device__ __forceinline__ void split_bf16(float x, __bf16 &h, __bf16 &l) {
-    h = (__bf16)x;
-    l = (__bf16)(x - (float)h);
+// 2^-e with e chosen so that m 2^-e < 1 (1 for m = 0 or not finite).
+__device__ __forceinline__ float pow2_scale(float m) {
+    if (!(m > 0.f) || !isfinite(m)) return 1.f;
+    return ldexpf(1.f, -(ilogbf(m) + 1));
 }
 
 // Hardware sine/cosine of 2 pi f for f in revolutions (|f| <= 1/2).
@@ -393,137 +530,138 @@ __device__ __forceinline__ void cis2pi_hw(float f, float &c, float &s) {
     c = __builtin_amdgcn_cosf(f);
 }
 
-// Forward, split precision.  Same decomposition as k_forward; each lane's
-// eight consecutive columns j0 + e (e = 0..7) get E_u = E(j0) E(e) with the
-// fine factors E(e) computed once per lane.  The row dot uses
-// E_v[k][i0 + 16 t + q] = fine(k, q) coarse(k, t) with the coarse factors
-// shared through LDS.
-template <int IB>
-__global__ __launch_bounds__(256) void k_forward_bf16(const FwdItem *__restrict__ items,
-                                                      const double *__restrict__ a,
-                                                      const double *__restrict__ b,
-                                                      const __bf16 *__restrict__ bh,
-                                                      const __bf16 *__restrict__ bl,
-                                                      double2 *__restrict__ vpart, int n, int np, long long ztot) {
+// Forward, split precision, persistent.  A workgroup of eight waves holds the
+// image block rows [i0, i0 + IB) x columns [j0, j0 + JB) in LDS for its
+// whole life (16-bit hi and lo halves, fp16 scaled by a power of
+// two to the block's maximum) and streams 16-visibility tiles through its waves:
+// tile t of the block goes to workgroup-wave (t mod 8 nwg).  For a tile the
+// wave forms the E_u operand of each 32-column step from a coarse factor and
+// eight fine factors (hardware sin/cos of FP64-reduced phases), contracts the
+// block on matrix cores, then does the row dot with E_v and writes the
+// block's partial V_k.
+template <typename H, int IB, int JB>
+__global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const float *__restrict__ bop,
+                                                         double2 *__restrict__ vpart, int n, int np,
+                                                         long long ztot) {
+    typedef typename Half16<H>::h8 h8;
     constexpr int NT = IB / 16;
-    constexpr int JC = 64;
-    constexpr int PAD = 8;
-    __shared__ __attribute__((aligned(16))) __bf16 sH[IB][JC + PAD];
-    __shared__ __attribute__((aligned(16))) __bf16 sL[IB][JC + PAD];
-    __shared__ float2 sCo[64][NT];
+    constexpr int KSTEPS = JB / 32;
+    constexpr int PADC = 8;
+    __shared__ __attribute__((aligned(16))) H sH[IB][JB + PADC];
+    __shared__ __attribute__((aligned(16))) H sL[IB][JB + PADC];
+    __shared__ float sMax[8];
 
-    const FwdItem it = items[blockIdx.x];
-    const int ib = blockIdx.y;
-    const int i0 = ib * IB;
+    const FwdPItem it = items[blockIdx.x];
+    const int i0 = it.ib * IB, j0 = it.jb * JB;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int q = lane & 15, g = lane >> 4;
-    const size_t coff = (size_t)it.chan * np * np;
-    const __bf16 *Bh = bh + coff;
-    const __bf16 *Bl = bl + coff;
     const int half = n / 2;
-
-    const int krow = wave * 16 + q;
-    const double ak = krow < it.nvalid ? a[it.k0 + krow] : 0.0;
-    float fc[8], fs[8];
+    // stage the block: (scale,) split into hi and lo halves
+    const float *Bc = bop + (size_t)it.chan * np * np;
+    constexpr int VROW = JB / 4;
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        float m = 0.f;
+        for (int x = tid; x < IB * VROW; x += 512) {
+            const int row = x / VROW, c4 = x % VROW;
+            const float4 v = *reinterpret_cast<const float4 *>(Bc + (size_t)(i0 + row) * np + j0 + 4 * c4);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
-
-    floatx4 accR[NT], accI[NT];
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sMax[wave] = m;
+        __syncthreads();
+        m = sMax[0];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        accI[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int x = 1; x < 8; ++x) m = fmaxf(m, sMax[x]);
+        scale = pow2_scale(m);
     }
-    constexpr int VROW = JC / 8;
-    constexpr int NLD = IB * VROW / 256;
-    // software pipeline: the next chunk travels global -> registers while the
-    // current one is contracted from LDS
-    uint4 ph[NLD], pl[NLD];
-    auto load_chunk = [&](int jc) {
+    for (int x = tid; x < IB * VROW; x += 512) {
+        const int row = x / VROW, c4 = x % VROW;
+        const float4 v = *reinterpret_cast<const float4 *>(Bc + (size_t)(i0 + row) * np + j0 + 4 * c4);
+        const float vv[4] = {v.x * scale, v.y * scale, v.z * scale, v.w * scale};
 #pragma unroll
-        for (int r = 0; r < NLD; ++r) {
-            const int idx = tid + 256 * r;
-            const int row = idx / VROW, c8 = idx % VROW;
-            const size_t go = (size_t)(i0 + row) * np + jc + 8 * c8;
-            ph[r] = *reinterpret_cast<const uint4 *>(Bh + go);
-            pl[r] = *reinterpret_cast<const uint4 *>(Bl + go);
+        for (int e = 0; e < 4; ++e) split16(vv[e], sH[row][4 * c4 + e], sL[row][4 * c4 + e]);
+    }
+    __syncthreads();
+    const float unscale = 1.f / scale;
+    const long long nk = it.kend - it.kbeg;
+    const long long ntiles = (nk + 15) / 16;
+    const long long stride = 8LL * it.nwg;
+    for (long long tile = (long long)it.wg * 8 + wave; tile < ntiles; tile += stride) {
+        const long long k0 = it.kbeg + 16 * tile;
+        const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
+        const double ak = q < nvalid ? a[k0 + q] : 0.0;
+        float fc[8], fs[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
+        floatx4 accR[NT], accI[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            accI[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    };
-    load_chunk(0);
-    for (int jc = 0; jc < np; jc += JC) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < NLD; ++r) {
-            const int idx = tid + 256 * r;
-            const int row = idx / VROW, c8 = idx % VROW;
-            *reinterpret_cast<uint4 *>(&sH[row][8 * c8]) = ph[r];
-            *reinterpret_cast<uint4 *>(&sL[row][8 * c8]) = pl[r];
-        }
-        __syncthreads();
-        if (jc + JC < np) load_chunk(jc + JC);
-#pragma unroll
-        for (int js = 0; js < JC; js += 32) {
+#pragma unroll 2
+        for (int ks = 0; ks < KSTEPS; ++ks) {
             float cc, sc;
-            cis2pi_hw((float)phase(ak, jc + js + 8 * g - half), cc, sc);
-            bf16x8 rh, rl, ih, il;
+            cis2pi_hw((float)phase(ak, j0 + 32 * ks + 8 * g - half), cc, sc);
+            h8 rh, rl, ih, il;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float c = cc * fc[e] - sc * fs[e];
                 const float sn = sc * fc[e] + cc * fs[e];
-                __bf16 h, l;
-                split_bf16(c, h, l);
+                H h, l;
+                split16(c, h, l);
                 rh[e] = h;
                 rl[e] = l;
-                split_bf16(-sn, h, l);
+                split16(-sn, h, l);
                 ih[e] = h;
                 il[e] = l;
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const bf16x8 bhv = *reinterpret_cast<const bf16x8 *>(&sH[16 * t + q][js + 8 * g]);
-                const bf16x8 blv = *reinterpret_cast<const bf16x8 *>(&sL[16 * t + q][js + 8 * g]);
-                accR[t] = mma_bf16(rh, bhv, accR[t]);
-                accI[t] = mma_bf16(ih, bhv, accI[t]);
-                accR[t] = mma_bf16(rh, blv, accR[t]);
-                accI[t] = mma_bf16(ih, blv, accI[t]);
-                accR[t] = mma_bf16(rl, bhv, accR[t]);
-                accI[t] = mma_bf16(il, bhv, accI[t]);
+                const h8 bhv = *reinterpret_cast<const h8 *>(&sH[16 * t + q][32 * ks + 8 * g]);
+                const h8 blv = *reinterpret_cast<const h8 *>(&sL[16 * t + q][32 * ks + 8 * g]);
+                accR[t] = Half16<H>::mma(rh, bhv, accR[t]);
+                accI[t] = Half16<H>::mma(ih, bhv, accI[t]);
+                accR[t] = Half16<H>::mma(rh, blv, accR[t]);
+                accI[t] = Half16<H>::mma(ih, blv, accI[t]);
+                accR[t] = Half16<H>::mma(rl, bhv, accR[t]);
+                accI[t] = Half16<H>::mma(il, bhv, accI[t]);
             }
         }
-    }
-    // coarse row-dot factors exp(-2 pi i b_k 16 t) for the workgroup's 64 rows
-    for (int x = tid; x < 64 * NT; x += 256) {
-        const int kk = x / NT, t = x % NT;
-        const double bk = kk < it.nvalid ? b[it.k0 + kk] : 0.0;
-        float c, sn;
-        cis2pi_hw((float)phase(bk, 16 * t), c, sn);
-        sCo[kk][t] = make_float2(c, sn);
-    }
-    __syncthreads();
+        // row dot: E_v[k][i0 + 16 t + q] = E(b_k (i0 + q - N/2)) E(16 b_k)^t
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int kk = wave * 16 + 4 * g + r;
-        const bool ok = kk < it.nvalid;
-        const double bk = ok ? b[it.k0 + kk] : 0.0;
-        float fcq, fsq;
-        cis2pi_hw((float)phase(bk, i0 + q - half), fcq, fsq);
-        float vr = 0.f, vi = 0.f;
+        for (int r = 0; r < 4; ++r) {
+            const int kk = 4 * g + r;
+            const bool ok = kk < nvalid;
+            const double bk = ok ? b[k0 + kk] : 0.0;
+            float ec, es, sc16, ss16;
+            cis2pi_hw((float)phase(bk, i0 + q - half), ec, es);
+            cis2pi_hw((float)phase(bk, 16), sc16, ss16);
+            float vr = 0.f, vi = 0.f;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float2 co = sCo[kk][t];
-            const float c = fcq * co.x - fsq * co.y;
-            const float sn = fsq * co.x + fcq * co.y;
-            const float tr = accR[t][r], ti = accI[t][r];
-            vr += c * tr + sn * ti;
-            vi += c * ti - sn * tr;
+            for (int t = 0; t < NT; ++t) {
+                const float tr = accR[t][r], ti = accI[t][r];
+                vr += ec * tr + es * ti;
+                vi += ec * ti - es * tr;
+                const float nc = ec * sc16 - es * ss16;
+                es = es * sc16 + ec * ss16;
+                ec = nc;
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                vr += __shfl_xor(vr, o, 64);
+                vi += __shfl_xor(vi, o, 64);
+            }
+            if (q == 0 && ok)
+                vpart[(size_t)it.part * ztot + k0 + kk] =
+                    make_double2((double)vr * (double)unscale, (double)vi * (double)unscale);
         }
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            vr += __shfl_xor(vr, o, 64);
-            vi += __shfl_xor(vi, o, 64);
-        }
-        if (q == 0 && ok) vpart[(size_t)ib * ztot + it.k0 + kk] = make_double2((double)vr, (double)vi);
     }
 }
 
@@ -535,13 +673,16 @@ __global__ __launch_bounds__(256) void k_forward_bf16(const FwdItem *__restrict_
 // E[j][k] = Fu Gu (cos, sin) in LDS (one thread per operand row), and the
 // waves contract them on matrix cores.  The visibility data of the next
 // step are loaded into registers while the current step computes.
-template <int WT>
-__global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restrict__ items,
-                                                         const double *__restrict__ a,
-                                                         const double *__restrict__ b,
-                                                         const double2 *__restrict__ coef,
-                                                         const float *__restrict__ w,
-                                                         double *__restrict__ gpart, int n, int np) {
+template <typename H, int WT>
+__global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restrict__ items,
+                                                        const double *__restrict__ a,
+                                                        const double *__restrict__ b,
+                                                        const double2 *__restrict__ coef,
+                                                        const float *__restrict__ w,
+                                                        const double *__restrict__ vispart,
+                                                        const int *__restrict__ vis_base,
+                                                        double *__restrict__ gpart, int n, int np) {
+    typedef typename Half16<H>::h8 h8;
     constexpr int TT = 2 * WT;
     constexpr int NT = WT / 16;
     constexpr int NC = TT / 16;
@@ -549,8 +690,9 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
     constexpr int KT = KS + 2;     // padded table rows (float2)
     constexpr int KP = KS;         // operand rows: 4 groups of 8, XOR-swizzled (see swz)
     __shared__ __attribute__((aligned(16))) float2 sHv[16][KT], sFu[16][KT], sGv[NC][KT], sGu[NC][KT];
-    __shared__ __attribute__((aligned(16))) __bf16 sP[4][TT][KP];   // re_h, re_l, -im_h, -im_l
-    __shared__ __attribute__((aligned(16))) __bf16 sE[4][TT][KP];   // cos_h, cos_l, sin_h, sin_l
+    __shared__ __attribute__((aligned(16))) H sP[4][TT][KP];   // re_h, re_l, -im_h, -im_l
+    __shared__ __attribute__((aligned(16))) H sE[4][TT][KP];   // cos_h, cos_l, sin_h, sin_l
+    __shared__ double sRed[4];
     // group kg of row r is stored at group kg ^ ((r >> 1) & 3): eight
     // consecutive rows then hit distinct LDS banks for 16-byte accesses
     auto swz = [](int r, int kg) { return 8 * (kg ^ ((r >> 1) & 3)); };
@@ -562,6 +704,20 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
     const int q = lane & 15, g = lane >> 4;
     const int wi = (wave >> 1) * WT, wj = (wave & 1) * WT;
     const int half = n / 2;
+    // fp16: coefficients scaled by 2^-e so that max |w c| of the channel
+    // (slot 2 of its visibility partials) is below one
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        double m = 0.0;
+        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 256)
+            m = fmax(m, vispart[(size_t)x * NPART + 2]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sRed[wave] = m;
+        __syncthreads();
+        m = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+        scale = pow2_scale((float)m);
+    }
 
     // table tasks of this thread: fine (k = tid>>4 and tid>>4 + 16, q = tid&15),
     // coarse (k = tid / NC8, t = tid % NC8 for both axes when tid < KS*NC)
@@ -598,13 +754,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
         {
             float c, s;
             cis2pi_hw((float)phase(cur.b0, i0 + fq - half), c, s);
-            float cr = (float)((double)cur.w0 * cur.c0.x), ci = (float)((double)cur.w0 * cur.c0.y);
+            float cr = scale * (float)((double)cur.w0 * cur.c0.x), ci = scale * (float)((double)cur.w0 * cur.c0.y);
             sHv[fq][fk0] = make_float2(cr * c - ci * s, cr * s + ci * c);
             cis2pi_hw((float)phase(cur.a0, j0 + fq - half), c, s);
             sFu[fq][fk0] = make_float2(c, s);
             cis2pi_hw((float)phase(cur.b1, i0 + fq - half), c, s);
-            cr = (float)((double)cur.w1 * cur.c1.x);
-            ci = (float)((double)cur.w1 * cur.c1.y);
+            cr = scale * (float)((double)cur.w1 * cur.c1.x);
+            ci = scale * (float)((double)cur.w1 * cur.c1.y);
             sHv[fq][fk0 + 16] = make_float2(cr * c - ci * s, cr * s + ci * c);
             cis2pi_hw((float)phase(cur.a1, j0 + fq - half), c, s);
             sFu[fq][fk0 + 16] = make_float2(c, s);
@@ -622,58 +778,58 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
             const int qq = row & 15, t = row >> 4;
             const float2 *f = dim == 0 ? sHv[qq] : sFu[qq];
             const float2 *gc = dim == 0 ? sGv[t] : sGu[t];
-            __bf16 (*dst)[TT][KP] = dim == 0 ? sP : sE;
+            H (*dst)[TT][KP] = dim == 0 ? sP : sE;
 #pragma unroll
             for (int kg = 0; kg < KS / 8; ++kg) {
-                bf16x8 v0, v1, v2, v3;
+                h8 v0, v1, v2, v3;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const float2 fv = f[8 * kg + e], gv = gc[8 * kg + e];
                     const float re = fv.x * gv.x - fv.y * gv.y;
                     const float im = fv.x * gv.y + fv.y * gv.x;
-                    __bf16 h, l;
-                    split_bf16(re, h, l);
+                    H h, l;
+                    split16(re, h, l);
                     v0[e] = h;
                     v1[e] = l;
-                    split_bf16(dim == 0 ? -im : im, h, l);
+                    split16(dim == 0 ? -im : im, h, l);
                     v2[e] = h;
                     v3[e] = l;
                 }
                 const int o = swz(row, kg);
-                *reinterpret_cast<bf16x8 *>(&dst[0][row][o]) = v0;
-                *reinterpret_cast<bf16x8 *>(&dst[1][row][o]) = v1;
-                *reinterpret_cast<bf16x8 *>(&dst[2][row][o]) = v2;
-                *reinterpret_cast<bf16x8 *>(&dst[3][row][o]) = v3;
+                *reinterpret_cast<h8 *>(&dst[0][row][o]) = v0;
+                *reinterpret_cast<h8 *>(&dst[1][row][o]) = v1;
+                *reinterpret_cast<h8 *>(&dst[2][row][o]) = v2;
+                *reinterpret_cast<h8 *>(&dst[3][row][o]) = v3;
             }
         }
         __syncthreads();
         // ---- contract on matrix cores
-        bf16x8 ech[NT], ecl[NT], esh[NT], esl[NT];
+        h8 ech[NT], ecl[NT], esh[NT], esl[NT];
 #pragma unroll
         for (int y = 0; y < NT; ++y) {
             const int r = wj + 16 * y + q;
             const int o = swz(r, g);
-            ech[y] = *reinterpret_cast<const bf16x8 *>(&sE[0][r][o]);
-            ecl[y] = *reinterpret_cast<const bf16x8 *>(&sE[1][r][o]);
-            esh[y] = *reinterpret_cast<const bf16x8 *>(&sE[2][r][o]);
-            esl[y] = *reinterpret_cast<const bf16x8 *>(&sE[3][r][o]);
+            ech[y] = *reinterpret_cast<const h8 *>(&sE[0][r][o]);
+            ecl[y] = *reinterpret_cast<const h8 *>(&sE[1][r][o]);
+            esh[y] = *reinterpret_cast<const h8 *>(&sE[2][r][o]);
+            esl[y] = *reinterpret_cast<const h8 *>(&sE[3][r][o]);
         }
 #pragma unroll
         for (int x = 0; x < NT; ++x) {
             const int r = wi + 16 * x + q;
             const int o = swz(r, g);
-            const bf16x8 prh = *reinterpret_cast<const bf16x8 *>(&sP[0][r][o]);
-            const bf16x8 prl = *reinterpret_cast<const bf16x8 *>(&sP[1][r][o]);
-            const bf16x8 pih = *reinterpret_cast<const bf16x8 *>(&sP[2][r][o]);
-            const bf16x8 pil = *reinterpret_cast<const bf16x8 *>(&sP[3][r][o]);
+            const h8 prh = *reinterpret_cast<const h8 *>(&sP[0][r][o]);
+            const h8 prl = *reinterpret_cast<const h8 *>(&sP[1][r][o]);
+            const h8 pih = *reinterpret_cast<const h8 *>(&sP[2][r][o]);
+            const h8 pil = *reinterpret_cast<const h8 *>(&sP[3][r][o]);
 #pragma unroll
             for (int y = 0; y < NT; ++y) {
-                acc[x][y] = mma_bf16(prh, ech[y], acc[x][y]);
-                acc[x][y] = mma_bf16(pih, esh[y], acc[x][y]);
-                acc[x][y] = mma_bf16(prh, ecl[y], acc[x][y]);
-                acc[x][y] = mma_bf16(pih, esl[y], acc[x][y]);
-                acc[x][y] = mma_bf16(prl, ech[y], acc[x][y]);
-                acc[x][y] = mma_bf16(pil, esh[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(prh, ech[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(pih, esh[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(prh, ecl[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(pih, esl[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(prl, ech[y], acc[x][y]);
+                acc[x][y] = Half16<H>::mma(pil, esh[y], acc[x][y]);
             }
         }
         __syncthreads();
@@ -688,12 +844,30 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_bf16(const AdjItem *__restri
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * x + 4 * g + r;
                 const int j = j0 + wj + 16 * y + q;
-                out[(size_t)i * np + j] = (double)acc[x][y][r];
+                out[(size_t)i * np + j] = (double)acc[x][y][r] / (double)scale;
             }
 }
 
 template <typename T>
 hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->n_fwdp > 0) {
+        const dim3 grid(c->n_fwdp), blk(512);
+        if constexpr (sizeof(T) == 4) {
+            if (c->ib_rows == 128 && c->jb_cols == 256) {
+                hipLaunchKernelGGL((k_forward_p<T, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+                                   (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+                return hipGetLastError();
+            }
+            if (c->ib_rows == 128 && c->jb_cols == 128) {
+                hipLaunchKernelGGL((k_forward_p<T, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+                                   (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+        return hipGetLastError();
+    }
     if (c->n_fwd == 0) return hipSuccess;
     dim3 grid(c->n_fwd, c->n_fparts);
     if (c->ib_rows == 128)
@@ -717,31 +891,32 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
     return hipGetLastError();
 }
 
-hipError_t fwd_bf16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
-    if (c->n_fwd == 0) return hipSuccess;
-    const __bf16 *bh = reinterpret_cast<const __bf16 *>(bop);
-    const __bf16 *bl = bh + (size_t)c->nchan * c->np * c->np;
-    dim3 grid(c->n_fwd, c->n_ib);
-    if (c->ib_rows == 256)
-        hipLaunchKernelGGL(k_forward_bf16<256>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+template <typename H>
+hipError_t fwd_h16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->n_fwdp == 0) return hipSuccess;
+    const float *B = reinterpret_cast<const float *>(bop);
+    const dim3 grid(c->n_fwdp), blk(512);
+    if (c->ib_rows == 128 && c->jb_cols == 256)
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
-    else if (c->ib_rows == 128)
-        hipLaunchKernelGGL(k_forward_bf16<128>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+    else if (c->ib_rows == 128 && c->jb_cols == 128)
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     else
-        hipLaunchKernelGGL(k_forward_bf16<64>, grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b, bh, bl,
+        hipLaunchKernelGGL((k_forward_h16p<H, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     return hipGetLastError();
 }
 
-hipError_t adj_bf16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+template <typename H>
+hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
     if (c->n_adj == 0) return hipSuccess;
     if (c->adj_tt == 128)
-        hipLaunchKernelGGL(k_adjoint_bf16<64>, dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
-                           coef, w, c->d_gpart, c->n, c->np);
+        hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
     else
-        hipLaunchKernelGGL(k_adjoint_bf16<32>, dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
-                           coef, w, c->d_gpart, c->n, c->np);
+        hipLaunchKernelGGL((k_adjoint_h16<H, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
     return hipGetLastError();
 }
 
@@ -749,13 +924,15 @@ hipError_t adj_bf16(const uvmem_ctx *c, const double2 *coef, const float *w, hip
 
 hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
     if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st);
-    if (c->prec == UVMEM_BF16X3) return fwd_bf16(c, bop, st);
+    if (c->prec == UVMEM_BF16X3) return fwd_h16<__bf16>(c, bop, st);
+    if (c->prec == UVMEM_FP16X3) return fwd_h16<_Float16>(c, bop, st);
     return fwd_dispatch<float>(c, bop, st);
 }
 
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
     if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st);
-    if (c->prec == UVMEM_BF16X3) return adj_bf16(c, coef, w, st);
+    if (c->prec == UVMEM_BF16X3) return adj_h16<__bf16>(c, coef, w, st);
+    if (c->prec == UVMEM_FP16X3) return adj_h16<_Float16>(c, coef, w, st);
     return adj_dispatch<float>(c, coef, w, st);
 }
 

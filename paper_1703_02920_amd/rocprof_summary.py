@@ -1,0 +1,144 @@
+"""Summaries of rocprofv3 output for the profiles folder.
+
+    python -m paper_1703_02920_amd.rocprof_summary stats DIR OUT.md --cmd "..." [--note "..."]
+        kernel statistics (``--kernel-trace --stats --output-format csv``) as a
+        markdown table, with the command that produced them.
+    python -m paper_1703_02920_amd.rocprof_summary traffic --workload W --fetch DIR --write DIR \\
+            --copy-fetch DIR --copy-write DIR --copy-bytes B --kernels k_forward k_adjoint --out OUT.md
+        HBM traffic per launch from two counter runs (FETCH_SIZE, then
+        WRITE_SIZE, KiB per dispatch), each scaled by the same counter's
+        reading for a plain device-to-device copy of B bytes; the result is
+        merged into profiles/traffic.json under W with the hash of the DFT
+        kernel source (the benchmark reports it only while the hash matches).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import re
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _short(name: str) -> str:
+    s = name.replace("(anonymous namespace)::", "")
+    s = re.sub(r"\(.*", "", s)
+    return s.strip()
+
+
+def _one(dirpath: str, pattern: str) -> str:
+    hits = sorted(glob.glob(os.path.join(dirpath, "**", pattern), recursive=True))
+    if not hits:
+        sys.exit(f"no {pattern} under {dirpath}")
+    return hits[0]
+
+
+def stats(args):
+    path = _one(args.dir, "*kernel_stats.csv")
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    lines = [f"# {args.title}", "", "Command (repository root, one MI355X):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp && cd -", args.cmd, "```", ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += [f"Source: `{os.path.basename(path)}`.", "",
+              "| kernel | calls | total ms | avg us | min us | max us | % |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{_short(r['Name'])[:70]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}")
+
+
+def _counter(dirpath: str, counter: str):
+    """{short kernel name: [values per dispatch]} for one counter."""
+    path = _one(dirpath, "*counter_collection.csv")
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _match(d, key):
+    vals = [v for k, vs in d.items() if key in k for v in vs]
+    if not vals:
+        sys.exit(f"no dispatch of {key}")
+    return statistics.median(vals), len(vals)
+
+
+def traffic(args):
+    sys.path.insert(0, ROOT)
+    from bench import kernel_hash
+
+    f_k, w_k = _counter(args.fetch, "FETCH_SIZE"), _counter(args.write, "WRITE_SIZE")
+    f_c, w_c = _counter(args.copy_fetch, "FETCH_SIZE"), _counter(args.copy_write, "WRITE_SIZE")
+    cf, _ = _match(f_c, args.copy_kernel)
+    cw, _ = _match(w_c, args.copy_kernel)
+    fscale = args.copy_bytes / (cf * 1024.0)
+    wscale = args.copy_bytes / (cw * 1024.0)
+    rec_path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(rec_path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    ent = rec.setdefault(args.workload, {})
+    lines = [f"# HBM traffic per launch, {args.workload}", "", "Commands (repository root, one MI355X):", "",
+             "```", "cd /tmp && export TMPDIR=/tmp && cd -"] + args.cmd + ["```", "",
+             f"Copy calibration: `{args.copy_kernel}` moving {args.copy_bytes} bytes reads "
+             f"FETCH_SIZE {cf:.0f} KiB and WRITE_SIZE {cw:.0f} KiB per dispatch; scale factors "
+             f"{fscale:.4f} (fetch) and {wscale:.4f} (write).", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes per launch |",
+             "|---|---:|---:|---:|---:|"]
+    h = kernel_hash()
+    for k in args.kernels:
+        fv, nf = _match(f_k, k)
+        wv, _ = _match(w_k, k)
+        b = fv * 1024.0 * fscale + wv * 1024.0 * wscale
+        ent[k] = {"bytes_per_launch": b, "fetch_kib": fv, "write_kib": wv, "fetch_scale": fscale,
+                  "write_scale": wscale, "kernel_hash": h}
+        lines.append(f"| `{k}` | {nf} | {fv:.0f} | {wv:.0f} | {b:.4g} |")
+    with open(rec_path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out} and {rec_path}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("out")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--title", default="Kernel statistics")
+    s.add_argument("--note", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--workload", required=True)
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--copy-kernel", default="copy")
+    t.add_argument("--kernels", nargs="+", required=True)
+    t.add_argument("--cmd", nargs="+", required=True)
+    t.add_argument("--out", required=True)
+    args = ap.parse_args()
+    stats(args) if args.what == "stats" else traffic(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -33,10 +33,11 @@ def _oracle_cg(prob, c, iters, I0):
 # to the whole run and final image loosely.
 CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7, "first": 1e-12},
           "fp32": {"phi": 1e-5, "img": 1e-3, "first": 1e-6},
-          "bf16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4}}
+          "bf16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4},
+          "fp16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4}}
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_cg_trajectory_c1(prec):
     _cuda()
     ds = synth.make_config(1)
@@ -125,7 +126,7 @@ def test_phi_grad_deterministic():
     assert torch.equal(s1, s2) and torch.equal(g1, g2)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_channel_batching_uneven_and_empty(prec):
     """Several channels of different sizes and one empty channel in one set
     of launches: each channel equals its own oracle evaluation; the empty one

@@ -43,7 +43,7 @@ def _oracle_c2_P3():
     return img, prob.oracle_phi_grad(0, img)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_c2_full_phi_grad(prec):
     """Every visibility and pixel of the 256^2 x 99,840 workload at P3."""
     _cuda()
@@ -134,21 +134,21 @@ def _point_source_property(ds, prob, ctx, prec):
     assert worst_x2 < TOL[prec] and worst_g < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_c3_sampled_and_point_source(prec):
     flush(f"c3 512^2 x 999,600 sampled parity {prec}")
     ds, prob, ctx = _sampled(prec, 3)
     _point_source_property(ds, prob, ctx, prec)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_c4_batched_sampled_and_point_source(prec):
     flush(f"c4 64 x 256^2 batched sampled parity {prec}")
     ds, prob, ctx = _sampled(prec, 4, n_vis=48, n_pix=32, channels=[0, 17, 40, 63])
     _point_source_property(ds, prob, ctx, prec)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_c5_sampled_and_point_source(prec):
     flush(f"c5 1024^2 x 5,000,250 sampled parity {prec}")
     ds, prob, ctx = _sampled(prec, 5, n_vis=48, n_pix=48)

@@ -15,7 +15,7 @@ def _cuda():
         pytest.skip("no GPU")
 
 
-PRECS = ["fp64", "fp32", "bf16x3"]
+PRECS = ["fp64", "fp32", "bf16x3", "fp16x3"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
