@@ -26,15 +26,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "vis·pixel evals/sec (fwd+adjoint ∇Φ); CG iters/sec, mixed vs FP32 at stated err"
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "fp16x3": 2500.0}   # TFLOP/s, dense MFMA
-KERNEL_SRC = ["paper_1703_02920_amd/csrc/k_dft.hip"]
+KERNEL_SRC = "paper_1703_02920_amd/csrc/k_dft.hip"
+# DFT kernel functions per precision: (forward, adjoint)
+KERNELS = {"fp32": ("k_forward_p", "k_adjoint"), "fp64": ("k_forward_p", "k_adjoint"),
+           "bf16x3": ("k_forward_h16p", "k_adjoint_h16"), "fp16x3": ("k_forward_h16p", "k_adjoint_h16")}
 
 
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SRC:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def kernel_hash(kernel: str) -> str:
+    """Hash of the DFT source with every other kernel's definition removed:
+    it changes when this kernel, a shared helper or the launch code changes."""
+    import re
+    with open(os.path.join(ROOT, KERNEL_SRC)) as f:
+        src = f.read()
+    # a kernel definition runs from its template line to the closing brace at
+    # column 0
+    pat = re.compile(r"^template <[^\n]*>\n__global__ [^\n]*? void (k_\w+)\(.*?^}\n", re.S | re.M)
+    if kernel not in {m.group(1) for m in pat.finditer(src)}:
+        raise ValueError(f"no kernel {kernel} in {KERNEL_SRC}")
+    kept = pat.sub(lambda m: m.group(0) if m.group(1) == kernel else "", src)
+    return hashlib.sha256(kept.encode()).hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel: str, workload: str):
@@ -47,7 +57,7 @@ def traffic_from_profiles(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("kernel_hash") != kernel_hash():
+    if not ent or ent.get("kernel_hash") != kernel_hash(kernel):
         return None
     return ent.get("bytes_per_launch")
 
@@ -284,7 +294,8 @@ def main():
         workload = f"c{args.config}-{args.precision}"
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision], "unit": "TFLOP/s",
                 "frac": achieved / PEAK[args.precision],
-                "traffic": traffic_from_profiles("k_adjoint" if dom == "adjoint" else "k_forward", workload),
+                "traffic": traffic_from_profiles(KERNELS[args.precision][0 if dom == "forward" else 1],
+                                                 workload),
                 "kernel": dom, "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
                 "other_kernel_ms": {k: v for k, v in kern.items() if k != dom}}
     mixed = None

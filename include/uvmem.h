@@ -161,9 +161,9 @@ int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *coun
 
 /* Introspection.  uvmem_info writes up to nout of, in order: N, padded side
  * Np, channels, precision, total visibilities, forward image blocks, adjoint
- * tile side, adjoint split-K slots, forward items, adjoint items, visibility
- * items, device bytes held, pixel blocks per channel, pixels per pixel block,
- * visibilities per visibility item, forward workgroups.  uvmem_chan_range
+ * tile side, adjoint split-K slots, forward workgroups, adjoint workgroups,
+ * visibility items, device bytes held, pixel blocks per channel, pixels per
+ * pixel block, visibilities per visibility item.  uvmem_chan_range
  * gives a channel's offset into the concatenated visibility arrays and its
  * count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);

@@ -8,6 +8,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <functional>
+#include <queue>
+#include <vector>
 
 #include "internal.h"
 
@@ -67,7 +70,7 @@ hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
 }
 
 void free_all(uvmem_ctx *c) {
-    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwd, c->d_fwdp, c->d_adj, c->d_vis,
+    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwdp, c->d_adj, c->d_vis,
                     c->d_slot_base, c->d_vis_base, c->d_R, c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr};
@@ -126,6 +129,40 @@ int check_ready(uvmem_ctx *c) {
     return UVMEM_OK;
 }
 
+// Completion time of work items with the given costs, dispatched in order
+// onto `slots` identical resident-workgroup slots (each item starts on the
+// slot that frees first).
+double makespan(const std::vector<double> &costs, int slots) {
+    std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+    for (int i = 0; i < slots; ++i) q.push(0.0);
+    double end = 0.0;
+    for (double w : costs) {
+        const double t = q.top() + w;
+        q.pop();
+        q.push(t);
+        end = std::max(end, t);
+    }
+    return end;
+}
+
+// Schedule choice for the DFT launches.  Candidate workgroup counts are
+// multiples of the resident-slot count; each candidate's per-channel splits
+// are simulated (longest items first) and the cheapest makespan wins, ties
+// going to fewer workgroups (fewer split-K partial planes to sum, fewer
+// image-block stagings).  `cost(m)` returns the items' costs for candidate m.
+int pick_schedule(int slots, const std::function<std::vector<double>(int)> &cost) {
+    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    int best = 1;
+    double best_t = 0.0;
+    for (int m : cand) {
+        std::vector<double> w = cost(m);
+        std::sort(w.begin(), w.end(), std::greater<double>());
+        const double t = makespan(w, slots);
+        if (m == 1 || t < 0.97 * best_t) { best = m; best_t = t; }
+    }
+    return best;
+}
+
 int build_layout(uvmem_ctx *c) {
     const int C = c->nchan;
     c->np = ((c->n + 63) / 64) * 64;
@@ -139,7 +176,16 @@ int build_layout(uvmem_ctx *c) {
     c->n_ib = c->np / c->ib_rows;
     c->n_jb = c->np / c->jb_cols;
     c->n_fparts = c->n_ib * c->n_jb;
+    // adjoint pixel tile: 256 x 256 for the split kernel where the padded
+    // side allows (halves its table work per product), else 128 x 128
+    // (FP32, split), 64 x 64 (FP64)
+    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    if (split && c->np % 256 == 0) c->adj_tt = 256;
+    if (const char *env = std::getenv("UVMEM_ADJ_TILE")) {
+        const int t = std::atoi(env);
+        if ((t == 64 || (t == 128 && c->prec != UVMEM_FP64) || (t == 256 && split)) && c->np % t == 0) c->adj_tt = t;
+    }
     c->adj_nt = c->np / c->adj_tt;
     c->ls_steps = LS_STEPS;
     if (const char *env = std::getenv("UVMEM_LS_STEPS")) c->ls_steps = std::max(1, std::min(64, std::atoi(env)));
@@ -342,63 +388,107 @@ int uvmem_finalize(uvmem_ctx *c) {
     const size_t rs = real_size(c);
 
     // ---- work tables
-    std::vector<FwdItem> fwd;
     std::vector<VisItem> vis;
     std::vector<AdjItem> adj;
     c->h_slot_base.assign(C + 1, 0);
     c->h_vis_base.assign(C + 1, 0);
     const int tiles = c->adj_nt * c->adj_nt;
-    // split-K chunk length: enough workgroups to fill the GPU several times
-    // over, chunks of equal length across channels (uneven channels balance)
-    // adjoint workgroups per launch: one round on 256 CUs (FP32/FP64 kernels
-    // hold one workgroup per CU; the split kernel holds two)
+    // ---- adjoint: split-K chunks.  Resident slots: 256 CUs x (1 workgroup,
+    // or 2 for the split kernel on 128 x 128 tiles).  A channel of Z_c
+    // visibilities is cut into ceil(Z_c / klen) equal chunks (multiples of 16)
+    // and every chunk covers all pixel tiles; the split kernel's chunks are
+    // also bounded because it sums a chunk in FP32 only.
     const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
-    int64_t target = split ? 512 : 256;
-    if (const char *env = std::getenv("UVMEM_ADJ_WGS")) target = std::max(1L, std::atol(env));
-    int64_t klen = (c->ztot * tiles + target - 1) / target;
-    klen = std::max<int64_t>(klen, ADJ_KMIN);
-    // the split-precision adjoint accumulates a chunk in FP32 only: bound it
-    if (split) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
-    klen = ((klen + 15) / 16) * 16;
+    const int adj_slots = (split && c->adj_tt == 128) ? 512 : 256;
+    auto adj_klen = [&](int64_t target) {
+        int64_t klen = (c->ztot * tiles + target - 1) / target;
+        klen = std::max<int64_t>(klen, ADJ_KMIN);
+        if (split) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
+        return ((klen + 15) / 16) * 16;
+    };
+    auto chunks_of = [&](int64_t nv, int64_t klen, int64_t &len) {
+        const int64_t nch = (nv + klen - 1) / klen;
+        len = nch ? ((nv + nch - 1) / nch + 15) / 16 * 16 : 0;
+        return nch;
+    };
+    constexpr double ADJ_OVERHEAD = 64.0;   // per-workgroup set-up and tile store, in visibilities
+    int adj_m = pick_schedule(adj_slots, [&](int m) {
+        std::vector<double> w;
+        const int64_t klen = adj_klen((int64_t)adj_slots * m);
+        for (int ch = 0; ch < C; ++ch) {
+            int64_t len;
+            const int64_t nch = chunks_of(c->nvis[ch], klen, len);
+            for (int64_t x = 0; x < nch; ++x) {
+                const double z = (double)std::min<int64_t>(len, c->nvis[ch] - x * len);
+                for (int t = 0; t < tiles; ++t) w.push_back(z + ADJ_OVERHEAD);
+            }
+        }
+        return w;
+    });
+    int64_t klen = adj_klen((int64_t)adj_slots * adj_m);
+    if (const char *env = std::getenv("UVMEM_ADJ_WGS")) klen = adj_klen(std::max(1L, std::atol(env)));
     int slot = 0;
     for (int ch = 0; ch < C; ++ch) {
         const int64_t b = c->off[ch], e = c->off[ch + 1];
-        for (int64_t k = b; k < e; k += FWD_KV)
-            fwd.push_back(FwdItem{ch, (int)std::min<int64_t>(FWD_KV, e - k), (long long)k});
         c->h_vis_base[ch] = (int)vis.size();
         for (int64_t k = b; k < e; k += c->vis_blk)
             vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + c->vis_blk, e)});
         c->h_slot_base[ch] = slot;
-        for (int64_t k = b; k < e; k += klen, ++slot)
+        int64_t len;
+        chunks_of(e - b, klen, len);
+        for (int64_t k = b; k < e; k += len, ++slot)
             for (int ti = 0; ti < c->adj_nt; ++ti)
                 for (int tj = 0; tj < c->adj_nt; ++tj)
-                    adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k, (long long)std::min<int64_t>(k + klen, e)});
+                    adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k, (long long)std::min<int64_t>(k + len, e)});
     }
     c->h_slot_base[C] = slot;
-    // persistent forward: workgroups spread over the image
-    // blocks in proportion to their channel's visibility count
+    // longest chunks first (the slot of an item fixes its place in the
+    // split-K sum, so the order of the items is free)
+    std::stable_sort(adj.begin(), adj.end(), [](const AdjItem &x, const AdjItem &y) {
+        return x.kend - x.kbeg > y.kend - y.kbeg;
+    });
+    // ---- persistent forward: one resident workgroup per CU; the
+    // (channel, image block) pairs are shared by g_c workgroups each, with
+    // g_c = ceil(Z_c / L) for the per-workgroup visibility count L chosen by
+    // the same simulation
     std::vector<FwdPItem> fwdp;
     if (c->ztot > 0) {
-        int64_t wgs = 256;
-        if (const char *env = std::getenv("UVMEM_FWD_WGS")) wgs = std::max(1L, std::atol(env));
         const int nblk = c->n_ib * c->n_jb;
-        for (int ch = 0; ch < C; ++ch) {
+        constexpr double FWD_OVERHEAD = 256.0;   // image-block staging, in visibilities
+        auto shares = [&](int64_t wgs, int ch) {
             const int64_t nv = c->nvis[ch];
-            if (nv == 0) continue;
-            const int64_t tiles = (nv + 15) / 16;
-            int64_t g = (int64_t)std::llround((double)wgs * (double)nv / (double)c->ztot / nblk);
-            g = std::max<int64_t>(1, std::min<int64_t>(g, (tiles + 7) / 8));
+            const int64_t L = std::max<int64_t>(16, (c->ztot * nblk + wgs - 1) / wgs);
+            const int64_t tl = (nv + 15) / 16;
+            return std::max<int64_t>(1, std::min<int64_t>((nv + L - 1) / L, (tl + 7) / 8));
+        };
+        int fwd_m = pick_schedule(256, [&](int m) {
+            std::vector<double> w;
+            for (int ch = 0; ch < C; ++ch) {
+                if (c->nvis[ch] == 0) continue;
+                const int64_t g = shares(256LL * m, ch);
+                for (int b = 0; b < nblk; ++b)
+                    for (int64_t x = 0; x < g; ++x) w.push_back((double)c->nvis[ch] / (double)g + FWD_OVERHEAD);
+            }
+            return w;
+        });
+        int64_t wgs = 256LL * fwd_m;
+        if (const char *env = std::getenv("UVMEM_FWD_WGS")) wgs = std::max(1L, std::atol(env));
+        for (int ch = 0; ch < C; ++ch) {
+            if (c->nvis[ch] == 0) continue;
+            const int64_t g = shares(wgs, ch);
             for (int ib = 0; ib < c->n_ib; ++ib)
                 for (int jb = 0; jb < c->n_jb; ++jb)
                     for (int64_t x = 0; x < g; ++x)
                         fwdp.push_back(FwdPItem{ch, ib, jb, ib * c->n_jb + jb, (int)x, (int)g,
                                                 (long long)c->off[ch], (long long)c->off[ch + 1]});
         }
+        std::stable_sort(fwdp.begin(), fwdp.end(), [&](const FwdPItem &x, const FwdPItem &y) {
+            return (double)c->nvis[x.chan] / x.nwg > (double)c->nvis[y.chan] / y.nwg;
+        });
     }
     c->n_fwdp = (int)fwdp.size();
     c->h_vis_base[C] = (int)vis.size();
     c->n_slots = slot;
-    c->n_fwd = (int)fwd.size();
     c->n_adj = (int)adj.size();
     c->n_visit = (int)vis.size();
 
@@ -439,7 +529,6 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_vo, c->ztot));
     ok(dalloc(c, &c->d_w, c->ztot));
     ok(dalloc(c, (char **)&c->d_beam, C * npix * rs));
-    ok(dalloc(c, &c->d_fwd, fwd.size()));
     ok(dalloc(c, &c->d_fwdp, fwdp.size()));
     ok(dalloc(c, &c->d_adj, adj.size()));
     ok(dalloc(c, &c->d_vis, vis.size()));
@@ -476,7 +565,6 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_vo, vo.data(), vo.size() * 4);
     up(c->d_w, w.data(), w.size() * 4);
     up(c->d_beam, beam.data(), beam.size());
-    up(c->d_fwd, fwd.data(), fwd.size() * sizeof(FwdItem));
     up(c->d_fwdp, fwdp.data(), fwdp.size() * sizeof(FwdPItem));
     up(c->d_adj, adj.data(), adj.size() * sizeof(AdjItem));
     up(c->d_vis, vis.data(), vis.size() * sizeof(VisItem));
@@ -717,8 +805,8 @@ int uvmem_timing_read(uvmem_ctx *c, int which, double *total_ms, int64_t *count,
 int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     if (!c || !out) return UVMEM_EINVAL;
     const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
-                            c->n_fwd, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
-                            c->vis_blk, c->n_fwdp};
+                            c->n_fwdp, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
+                            c->vis_blk};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
     return UVMEM_OK;

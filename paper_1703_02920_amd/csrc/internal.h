@@ -12,8 +12,6 @@
 
 namespace uvm {
 
-// Visibilities per forward workgroup (4 waves x 16 MFMA rows).
-constexpr int FWD_KV = 64;
 // Threads per workgroup of the pixel, visibility and scalar kernels.
 constexpr int NTHR = 256;
 // Target workgroup counts of the visibility kernels and of the pixel kernels
@@ -35,13 +33,6 @@ constexpr double BOUND_TOL = 1e-12;
 // Default number of line-search passes per CG step; a channel whose search
 // has converged skips the remaining passes.
 constexpr int LS_STEPS = 4;
-
-// One forward workgroup: FWD_KV visibilities [k0, k0 + nvalid) of a channel.
-struct FwdItem {
-    int chan;
-    int nvalid;
-    long long k0;
-};
 
 // One workgroup of the persistent split-precision forward model: image block
 // (ib, jb) of a channel resident in LDS; the workgroup is number `wg` of the
@@ -137,14 +128,13 @@ struct uvmem_ctx {
     int ls_steps = 8;                  // line-search passes per CG step
     std::vector<int> h_slot_base;      // nchan+1
     std::vector<int> h_vis_base;       // nchan+1
-    int n_fwd = 0, n_adj = 0, n_visit = 0;
+    int n_adj = 0, n_visit = 0;
 
     // device buffers
     double *d_a = nullptr, *d_b = nullptr;      // u cell, v cell
     float2 *d_vo = nullptr;
     float *d_w = nullptr;
     void *d_beam = nullptr;                     // real [C][n][n]
-    uvm::FwdItem *d_fwd = nullptr;
     uvm::FwdPItem *d_fwdp = nullptr;
     int n_fwdp = 0;
     uvm::AdjItem *d_adj = nullptr;

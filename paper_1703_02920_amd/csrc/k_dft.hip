@@ -66,131 +66,9 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
+
 // ----------------------------------------------------------------------------
-// Forward.  Workgroup = 4 waves; wave w owns the 16 visibilities
-// k0 + 16 w + (0..15) as MFMA rows and all IB image rows of i-block blockIdx.y
-// as MFMA columns; the image block is staged through LDS in 32-column chunks.
-// Within a 16-column super-step, MFMA #s (s = 0..3) of lane group g = l/16
-// contracts column j = jbase + 4 g + s, so each lane reads 4 consecutive
-// image values with one vector load.
-// ----------------------------------------------------------------------------
-constexpr int JPAD = 4;
-
-template <typename T, int IB>
-__global__ __launch_bounds__(256) void k_forward(const FwdItem *__restrict__ items,
-                                                 const double *__restrict__ a,
-                                                 const double *__restrict__ b,
-                                                 const T *__restrict__ bop, double2 *__restrict__ vpart,
-                                                 int n, int np, long long ztot, int jb_cols, int n_jb) {
-    typedef typename Mfma<T>::acc acc_t;
-    typedef typename Vec4<T>::type T4;
-    typedef typename C2T<T>::type C2;
-    constexpr int NT = IB / 16;
-    constexpr int JCF = 32;                           // image columns per staged chunk
-    __shared__ __attribute__((aligned(16))) T sB[IB][JCF + JPAD];
-    __shared__ C2 sCo[64][NT + 1];
-
-    const FwdItem it = items[blockIdx.x];
-    const int part = blockIdx.y;            // (row block, column block)
-    const int ib = part / n_jb, jb = part % n_jb;
-    const int i0 = ib * IB;
-    const int j_beg = jb * jb_cols, j_end = j_beg + jb_cols;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int q = lane & 15, g = lane >> 4;
-    const T *B = bop + (size_t)it.chan * np * np;
-    const int half = n / 2;
-
-    const int krow = wave * 16 + q;
-    const double ak = krow < it.nvalid ? a[it.k0 + krow] : 0.0;
-    // E_u[k][j0 + 4 g + s] = E(j0 - N/2) E(4 g + s): per-lane fine factors
-    T fc[4], fs[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
-
-    acc_t accR[NT], accI[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        accR[t] = Mfma<T>::zero();
-        accI[t] = Mfma<T>::zero();
-    }
-
-    constexpr int V_PER_ROW = JCF / 4;                // 4-wide vectors per staged row
-    constexpr int NLOAD = IB * V_PER_ROW / 256;       // vectors per thread
-    for (int jc = j_beg; jc < j_end; jc += JCF) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < NLOAD; ++r) {
-            const int idx = tid + 256 * r;
-            const int row = idx / V_PER_ROW, c4 = idx % V_PER_ROW;
-            *reinterpret_cast<T4 *>(&sB[row][4 * c4]) =
-                *reinterpret_cast<const T4 *>(B + (size_t)(i0 + row) * np + jc + 4 * c4);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int js = 0; js < JCF; js += 16) {
-            T cc, sc;
-            cis2pi((T)phase(ak, jc + js - half), cc, sc);
-            T cr[4], ci[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                cr[s] = cc * fc[s] - sc * fs[s];
-                ci[s] = -(sc * fc[s] + cc * fs[s]);
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                T4 bv = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
-                accR[t] = Mfma<T>::mma(cr[0], bv.x, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[0], bv.x, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[1], bv.y, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[1], bv.y, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[2], bv.z, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[2], bv.z, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[3], bv.w, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[3], bv.w, accI[t]);
-            }
-        }
-    }
-
-    // Row dot with E_v, accumulated in FP64: lane holds T[k][i] for
-    // k = 16 w + drow(g, r), i = i0 + 16 t + q.  E_v[k][i0 + 16 t + q] =
-    // E(b_k (i0 + q - N/2)) E(16 b_k t), the second factor shared via LDS.
-    for (int x = tid; x < 64 * NT; x += 256) {
-        const int kk = x / NT, t = x % NT;
-        const double bk = kk < it.nvalid ? b[it.k0 + kk] : 0.0;
-        T c, sn;
-        cis2pi((T)phase(bk, 16 * t), c, sn);
-        sCo[kk][t] = C2{c, sn};
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int kk = wave * 16 + Mfma<T>::drow(g, r);
-        const bool ok = kk < it.nvalid;
-        const double bk = ok ? b[it.k0 + kk] : 0.0;
-        T fcq, fsq;
-        cis2pi((T)phase(bk, i0 + q - half), fcq, fsq);
-        double vr = 0.0, vi = 0.0;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const C2 co = sCo[kk][t];
-            const double cd = (double)(fcq * co.x - fsq * co.y);
-            const double sd = (double)(fsq * co.x + fcq * co.y);
-            const double tr = (double)accR[t][r], ti = (double)accI[t][r];
-            vr += cd * tr + sd * ti;
-            vi += cd * ti - sd * tr;
-        }
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            vr += __shfl_xor(vr, o, 64);
-            vi += __shfl_xor(vi, o, 64);
-        }
-        if (q == 0 && ok) vpart[(size_t)part * ztot + it.k0 + kk] = make_double2(vr, vi);
-    }
-}
-
-// Forward, FP32 / FP64, persistent.  As k_forward_bf16p: a workgroup of eight
-// waves keeps the image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams
+// Forward, FP32 / FP64, persistent.  A workgroup of eight waves keeps the image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams
 // 16-visibility tiles through its waves.  Twiddles are correctly rounded
 // (sincospi of FP64-reduced phases): E_u[k][j0 + 16 m + 4 g + s] =
 // E(j0 + 16 m - N/2) E(4 g + s); the row dot uses E_v = E(i0 + q - N/2) E(16 t)
@@ -518,6 +396,27 @@ __device__ __forceinline__ void split16(float x, H &h, H &l) {
     l = (H)(x - (float)h);
 }
 
+// Split eight floats into hi and lo vectors, two values per conversion
+// instruction (v_cvt_pk_{bf16,f16}_f32).
+typedef float float2v __attribute__((ext_vector_type(2)));
+template <typename H>
+__device__ __forceinline__ void split8(const float (&x)[8], typename Half16<H>::h8 &hi,
+                                       typename Half16<H>::h8 &lo) {
+    typedef H h2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const float2v v = {x[2 * m], x[2 * m + 1]};
+        const h2 hh = __builtin_convertvector(v, h2);
+        const float2v back = __builtin_convertvector(hh, float2v);
+        const float2v d = {v.x - back.x, v.y - back.y};
+        const h2 ll = __builtin_convertvector(d, h2);
+        hi[2 * m] = hh.x;
+        hi[2 * m + 1] = hh.y;
+        lo[2 * m] = ll.x;
+        lo[2 * m + 1] = ll.y;
+    }
+}
+
 // 2^-e with e chosen so that m 2^-e < 1 (1 for m = 0 or not finite).
 __device__ __forceinline__ float pow2_scale(float m) {
     if (!(m > 0.f) || !isfinite(m)) return 1.f;
@@ -610,18 +509,14 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
             float cc, sc;
             cis2pi_hw((float)phase(ak, j0 + 32 * ks + 8 * g - half), cc, sc);
             h8 rh, rl, ih, il;
+            float cv[8], nsv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float c = cc * fc[e] - sc * fs[e];
-                const float sn = sc * fc[e] + cc * fs[e];
-                H h, l;
-                split16(c, h, l);
-                rh[e] = h;
-                rl[e] = l;
-                split16(-sn, h, l);
-                ih[e] = h;
-                il[e] = l;
+                cv[e] = cc * fc[e] - sc * fs[e];
+                nsv[e] = -(sc * fc[e] + cc * fs[e]);
             }
+            split8<H>(cv, rh, rl);
+            split8<H>(nsv, ih, il);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const h8 bhv = *reinterpret_cast<const h8 *>(&sH[16 * t + q][32 * ks + 8 * g]);
@@ -667,10 +562,11 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
 
 // Adjoint, split precision.  Per 32-visibility step the workgroup builds
 // fine/coarse twiddle tables (hardware sin/cos of FP64-reduced phases):
-//   Hv[q][k] = w_k c_k exp(+2 pi i b_k (i0 + q - N/2)),  Gv[t][k] = exp(+2 pi i b_k 16 t)
-//   Fu[q][k] = exp(+2 pi i a_k (j0 + q - N/2)),          Gu[t][k] = exp(+2 pi i a_k 16 t)
-// then the pre-split operand tiles P[i][k] = Hv Gv (re, -im) and
-// E[j][k] = Fu Gu (cos, sin) in LDS (one thread per operand row), and the
+//   Hv[q][k] = conj(w_k c_k exp(+2 pi i b_k (i0 + q - N/2))),  Gv[t][k] = exp(-2 pi i b_k 16 t)
+//   Fu[q][k] = exp(+2 pi i a_k (j0 + q - N/2)),                Gu[t][k] = exp(+2 pi i a_k 16 t)
+// (the P side conjugated, so that Hv Gv = (Re P, -Im P) directly), then the
+// pre-split operand tiles P[i][k] = Hv Gv and E[j][k] = Fu Gu (cos, sin) in
+// LDS (one thread per operand row), and the
 // waves contract them on matrix cores.  The visibility data of the next
 // step are loaded into registers while the current step computes.
 template <typename H, int WT>
@@ -755,18 +651,18 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
             float c, s;
             cis2pi_hw((float)phase(cur.b0, i0 + fq - half), c, s);
             float cr = scale * (float)((double)cur.w0 * cur.c0.x), ci = scale * (float)((double)cur.w0 * cur.c0.y);
-            sHv[fq][fk0] = make_float2(cr * c - ci * s, cr * s + ci * c);
+            sHv[fq][fk0] = make_float2(cr * c - ci * s, -(cr * s + ci * c));
             cis2pi_hw((float)phase(cur.a0, j0 + fq - half), c, s);
             sFu[fq][fk0] = make_float2(c, s);
             cis2pi_hw((float)phase(cur.b1, i0 + fq - half), c, s);
             cr = scale * (float)((double)cur.w1 * cur.c1.x);
             ci = scale * (float)((double)cur.w1 * cur.c1.y);
-            sHv[fq][fk0 + 16] = make_float2(cr * c - ci * s, cr * s + ci * c);
+            sHv[fq][fk0 + 16] = make_float2(cr * c - ci * s, -(cr * s + ci * c));
             cis2pi_hw((float)phase(cur.a1, j0 + fq - half), c, s);
             sFu[fq][fk0 + 16] = make_float2(c, s);
             if (has_c) {
                 cis2pi_hw((float)phase(cur.bc, 16 * ct), c, s);
-                sGv[ct][ck] = make_float2(c, s);
+                sGv[ct][ck] = make_float2(c, -s);
                 cis2pi_hw((float)phase(cur.ac, 16 * ct), c, s);
                 sGu[ct][ck] = make_float2(c, s);
             }
@@ -782,19 +678,15 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
 #pragma unroll
             for (int kg = 0; kg < KS / 8; ++kg) {
                 h8 v0, v1, v2, v3;
+                float re[8], im[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const float2 fv = f[8 * kg + e], gv = gc[8 * kg + e];
-                    const float re = fv.x * gv.x - fv.y * gv.y;
-                    const float im = fv.x * gv.y + fv.y * gv.x;
-                    H h, l;
-                    split16(re, h, l);
-                    v0[e] = h;
-                    v1[e] = l;
-                    split16(dim == 0 ? -im : im, h, l);
-                    v2[e] = h;
-                    v3[e] = l;
+                    re[e] = fv.x * gv.x - fv.y * gv.y;
+                    im[e] = fv.x * gv.y + fv.y * gv.x;
                 }
+                split8<H>(re, v0, v1);
+                split8<H>(im, v2, v3);
                 const int o = swz(row, kg);
                 *reinterpret_cast<h8 *>(&dst[0][row][o]) = v0;
                 *reinterpret_cast<h8 *>(&dst[1][row][o]) = v1;
@@ -848,34 +740,199 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
             }
 }
 
+// Adjoint, split precision, 256 x 256 pixel tile, eight waves (2 x 4 waves
+// of 128 x 64 pixels).  The operand tables grow with the tile side while the
+// matrix-core work grows with its area, so the larger tile halves the table
+// and splitting work per product.  Per 32-visibility step:
+//   1. every thread forms one fine and one coarse entry of each axis
+//      (k = tid / 16, index tid % 16), hardware sin/cos of FP64-reduced phases:
+//        Hv[q][k] = conj(s w_k c_k E(b_k (i0 + q - N/2))),  Gv[t][k] = conj E(16 b_k t)
+//        Fu[q][k] = E(a_k (j0 + q - N/2)),                  Gu[t][k] = E(16 a_k t)
+//      (s: the fp16 power-of-two scale; E(x) = exp(2 pi i x));
+//   2. every thread forms one operand row, P[i][k] = Hv Gv (waves 0-3) or
+//      E[j][k] = Fu Gu (waves 4-7), split into hi and lo halves;
+//   3. each wave keeps its four E column blocks in registers and streams its
+//      eight P row blocks: 6 MFMAs per 16 x 16 block pair.
+// Chunk sums are FP32; the partial tile is stored in FP64.
+template <typename H>
+__global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const double2 *__restrict__ coef,
+                                                         const float *__restrict__ w,
+                                                         const double *__restrict__ vispart,
+                                                         const int *__restrict__ vis_base,
+                                                         double *__restrict__ gpart, int n, int np) {
+    typedef typename Half16<H>::h8 h8;
+    constexpr int TT = 256;
+    constexpr int KS = 32;
+    constexpr int KT = KS + 2;     // padded table rows (float2)
+    constexpr int NR = 8;          // 16-row blocks per wave (128 rows)
+    constexpr int NCB = 4;         // 16-column blocks per wave (64 columns)
+    __shared__ __attribute__((aligned(16))) float2 sHv[16][KT], sFu[16][KT], sGv[16][KT], sGu[16][KT];
+    __shared__ __attribute__((aligned(16))) H sP[4][TT][KS];   // re_h, re_l, -im_h, -im_l
+    __shared__ __attribute__((aligned(16))) H sE[4][TT][KS];   // cos_h, cos_l, sin_h, sin_l
+    __shared__ double sRed[8];
+    // group kg of row r is stored at group kg ^ ((r >> 1) & 3): eight
+    // consecutive rows then hit distinct LDS banks for 16-byte accesses
+    auto swz = [](int r, int kg) { return 8 * (kg ^ ((r >> 1) & 3)); };
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int wi = (wave >> 2) * 128, wj = (wave & 3) * 64;
+    const int half = n / 2;
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        double m = 0.0;
+        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 512)
+            m = fmax(m, vispart[(size_t)x * NPART + 2]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sRed[wave] = m;
+        __syncthreads();
+        m = sRed[0];
+#pragma unroll
+        for (int x = 1; x < 8; ++x) m = fmax(m, sRed[x]);
+        scale = pow2_scale((float)m);
+    }
+
+    // table task of this thread: visibility k = tid / 16 of the step, index tid % 16
+    const int tk = tid >> 4, tq = tid & 15;
+    struct Pre {
+        double a, b;
+        double2 c;
+        float w;
+    };
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k = kb + tk;
+        p.a = p.b = 0.0;
+        p.c = make_double2(0.0, 0.0);
+        p.w = 0.f;
+        if (k < it.kend) { p.a = a[k]; p.b = b[k]; p.c = coef[k]; p.w = w ? w[k] : 1.f; }
+    };
+
+    floatx4 acc[NR][NCB];
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+        for (int y = 0; y < NCB; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    // operand row of this thread in the split stage
+    const int dim = tid >> 8, row = tid & 255;
+    const float2 *f_row = dim == 0 ? sHv[row & 15] : sFu[row & 15];
+    const float2 *g_row = dim == 0 ? sGv[row >> 4] : sGu[row >> 4];
+    H (*dst)[TT][KS] = dim == 0 ? sP : sE;
+
+    Pre cur, nxt;
+    fetch(it.kbeg, cur);
+    for (long long kb = it.kbeg; kb < it.kend; kb += KS) {
+        if (kb + KS < it.kend) fetch(kb + KS, nxt);
+        // ---- 1. twiddle tables (zero coefficients / unit factors past the end)
+        {
+            float c, s;
+            cis2pi_hw((float)phase(cur.b, i0 + tq - half), c, s);
+            const float cr = scale * (float)((double)cur.w * cur.c.x);
+            const float ci = scale * (float)((double)cur.w * cur.c.y);
+            sHv[tq][tk] = make_float2(cr * c - ci * s, -(cr * s + ci * c));
+            cis2pi_hw((float)phase(cur.a, j0 + tq - half), c, s);
+            sFu[tq][tk] = make_float2(c, s);
+            cis2pi_hw((float)phase(cur.b, 16 * tq), c, s);
+            sGv[tq][tk] = make_float2(c, -s);
+            cis2pi_hw((float)phase(cur.a, 16 * tq), c, s);
+            sGu[tq][tk] = make_float2(c, s);
+        }
+        __syncthreads();
+        // ---- 2. pre-split operand rows
+#pragma unroll
+        for (int kg = 0; kg < KS / 8; ++kg) {
+            float re[8], im[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float2 fv = f_row[8 * kg + e], gv = g_row[8 * kg + e];
+                re[e] = fv.x * gv.x - fv.y * gv.y;
+                im[e] = fv.x * gv.y + fv.y * gv.x;
+            }
+            h8 v0, v1, v2, v3;
+            split8<H>(re, v0, v1);
+            split8<H>(im, v2, v3);
+            const int o = swz(row, kg);
+            *reinterpret_cast<h8 *>(&dst[0][row][o]) = v0;
+            *reinterpret_cast<h8 *>(&dst[1][row][o]) = v1;
+            *reinterpret_cast<h8 *>(&dst[2][row][o]) = v2;
+            *reinterpret_cast<h8 *>(&dst[3][row][o]) = v3;
+        }
+        __syncthreads();
+        // ---- 3. contract on matrix cores
+        h8 ech[NCB], ecl[NCB], esh[NCB], esl[NCB];
+#pragma unroll
+        for (int y = 0; y < NCB; ++y) {
+            const int r = wj + 16 * y + q;
+            const int o = swz(r, g);
+            ech[y] = *reinterpret_cast<const h8 *>(&sE[0][r][o]);
+            ecl[y] = *reinterpret_cast<const h8 *>(&sE[1][r][o]);
+            esh[y] = *reinterpret_cast<const h8 *>(&sE[2][r][o]);
+            esl[y] = *reinterpret_cast<const h8 *>(&sE[3][r][o]);
+        }
+#pragma unroll
+        for (int x = 0; x < NR; ++x) {
+            const int r = wi + 16 * x + q;
+            const int o = swz(r, g);
+            const h8 prh = *reinterpret_cast<const h8 *>(&sP[0][r][o]);
+            const h8 prl = *reinterpret_cast<const h8 *>(&sP[1][r][o]);
+            const h8 pih = *reinterpret_cast<const h8 *>(&sP[2][r][o]);
+            const h8 pil = *reinterpret_cast<const h8 *>(&sP[3][r][o]);
+            // product-major order: four independent accumulators between
+            // dependent matrix-core instructions
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prh, ech[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pih, esh[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prh, ecl[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pih, esl[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prl, ech[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pil, esh[y], acc[x][y]);
+        }
+        cur = nxt;
+    }
+    double *out = gpart + (size_t)it.slot * np * np;
+    const double inv = 1.0 / (double)scale;
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+        for (int y = 0; y < NCB; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * x + 4 * g + r;
+                const int j = j0 + wj + 16 * y + q;
+                out[(size_t)i * np + j] = (double)acc[x][y][r] * inv;
+            }
+}
+
 template <typename T>
 hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
-    if (c->n_fwdp > 0) {
-        const dim3 grid(c->n_fwdp), blk(512);
-        if constexpr (sizeof(T) == 4) {
-            if (c->ib_rows == 128 && c->jb_cols == 256) {
-                hipLaunchKernelGGL((k_forward_p<T, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
-                                   (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
-                return hipGetLastError();
-            }
-            if (c->ib_rows == 128 && c->jb_cols == 128) {
-                hipLaunchKernelGGL((k_forward_p<T, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
-                                   (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
-                return hipGetLastError();
-            }
+    if (c->n_fwdp == 0) return hipSuccess;
+    const dim3 grid(c->n_fwdp), blk(512);
+    if constexpr (sizeof(T) == 4) {
+        if (c->ib_rows == 128 && c->jb_cols == 256) {
+            hipLaunchKernelGGL((k_forward_p<T, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+                               (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+            return hipGetLastError();
         }
-        hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
-                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
-        return hipGetLastError();
+        if (c->ib_rows == 128 && c->jb_cols == 128) {
+            hipLaunchKernelGGL((k_forward_p<T, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+                               (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+            return hipGetLastError();
+        }
     }
-    if (c->n_fwd == 0) return hipSuccess;
-    dim3 grid(c->n_fwd, c->n_fparts);
-    if (c->ib_rows == 128)
-        hipLaunchKernelGGL((k_forward<T, 128>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
-                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot, c->jb_cols, c->n_jb);
-    else
-        hipLaunchKernelGGL((k_forward<T, 64>), grid, dim3(256), 0, st, c->d_fwd, c->d_a, c->d_b,
-                           (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot, c->jb_cols, c->n_jb);
+    hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, (const T *)bop,
+                       c->d_vpart, c->n, c->np, (long long)c->ztot);
     return hipGetLastError();
 }
 
@@ -911,7 +968,10 @@ hipError_t fwd_h16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
 template <typename H>
 hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
     if (c->n_adj == 0) return hipSuccess;
-    if (c->adj_tt == 128)
+    if (c->adj_tt == 256)
+        hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(c->n_adj), dim3(512), 0, st, c->d_adj, c->d_a, c->d_b,
+                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
+    else if (c->adj_tt == 128)
         hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
     else

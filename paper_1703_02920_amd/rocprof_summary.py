@@ -25,8 +25,38 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def _demangle(name: str) -> str:
+    """Readable form of this library's mangled kernel names (the system
+    demangler does not know the 16-bit float types): function name and
+    template arguments."""
+    m = re.match(r"_ZN(?:\d+\w+?)*?12_GLOBAL__N_1(\d+)", name)
+    if not m:
+        return name
+    start = m.end()
+    fn = name[start:start + int(m.group(1))]
+    rest = name[start + int(m.group(1)):]
+    args = []
+    if rest.startswith("I"):
+        rest = rest[1:]
+        tok = {"DF16b": "__bf16", "DF16_": "_Float16", "f": "float", "d": "double"}
+        while rest and not rest.startswith("E"):
+            t = re.match(r"Li(\d+)E", rest)
+            if t:
+                args.append(t.group(1))
+                rest = rest[t.end():]
+                continue
+            for k, v in tok.items():
+                if rest.startswith(k):
+                    args.append(v)
+                    rest = rest[len(k):]
+                    break
+            else:
+                break
+    return f"uvm::{fn}<{', '.join(args)}>" if args else f"uvm::{fn}"
+
+
 def _short(name: str) -> str:
-    s = name.replace("(anonymous namespace)::", "")
+    s = _demangle(name).replace("(anonymous namespace)::", "")
     s = re.sub(r"\(.*", "", s)
     return s.strip()
 
@@ -70,8 +100,19 @@ def _counter(dirpath: str, counter: str):
     return out
 
 
+def _fname(name: str) -> str:
+    """Function name of a kernel name, demangled (uvm::k_adjoint_h16<...>) or
+    mangled (_ZN3uvm12_GLOBAL__N_113k_adjoint_h16I...): k_adjoint_h16."""
+    m = re.match(r"_ZN(?:\d+\w+?)*?12_GLOBAL__N_1(\d+)", name)
+    if m:
+        start = m.end()
+        return name[start:start + int(m.group(1))]
+    m = re.search(r"(\w+)\s*(<|$)", name)
+    return m.group(1) if m else name
+
+
 def _match(d, key):
-    vals = [v for k, vs in d.items() if key in k for v in vs]
+    vals = [v for k, vs in d.items() if _fname(k) == key for v in vs]
     if not vals:
         sys.exit(f"no dispatch of {key}")
     return statistics.median(vals), len(vals)
@@ -101,8 +142,8 @@ def traffic(args):
              f"{fscale:.4f} (fetch) and {wscale:.4f} (write).", "",
              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes per launch |",
              "|---|---:|---:|---:|---:|"]
-    h = kernel_hash()
     for k in args.kernels:
+        h = kernel_hash(k)
         fv, nf = _match(f_k, k)
         wv, _ = _match(w_k, k)
         b = fv * 1024.0 * fscale + wv * 1024.0 * wscale
@@ -132,7 +173,7 @@ def main():
     t.add_argument("--copy-fetch", required=True)
     t.add_argument("--copy-write", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
-    t.add_argument("--copy-kernel", default="copy")
+    t.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer")
     t.add_argument("--kernels", nargs="+", required=True)
     t.add_argument("--cmd", nargs="+", required=True)
     t.add_argument("--out", required=True)

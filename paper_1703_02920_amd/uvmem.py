@@ -183,9 +183,8 @@ class Context:
         return ctx.finalize()
 
     def info(self) -> dict:
-        keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_items",
-                "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block",
-                "n_fwd_wgs"]
+        keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_wgs",
+                "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block"]
         out = (ctypes.c_int64 * len(keys))()
         self._call("uvmem_info", out, len(keys))
         return dict(zip(keys, [int(x) for x in out]))
