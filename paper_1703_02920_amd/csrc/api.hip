@@ -537,7 +537,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_R, c->ztot));
     ok(dalloc(c, &c->d_Vd, c->ztot));
     ok(dalloc(c, &c->d_vpart, (size_t)c->n_fparts * c->ztot));
-    ok(dalloc(c, &c->d_gpart, (size_t)c->n_slots * np * np));
+    ok(dalloc(c, (char **)&c->d_gpart, (size_t)c->n_slots * np * np * (split ? sizeof(float) : sizeof(double))));
     ok(dalloc(c, (char **)&c->d_bop, (size_t)C * np * np * rs));
     ok(dalloc(c, (char **)&c->d_g, C * npix * rs));
     ok(dalloc(c, (char **)&c->d_gt, C * npix * rs));

@@ -141,7 +141,7 @@ struct uvmem_ctx {
     uvm::VisItem *d_vis = nullptr;
     int *d_slot_base = nullptr, *d_vis_base = nullptr;
     double2 *d_R = nullptr, *d_Vd = nullptr, *d_vpart = nullptr;
-    double *d_gpart = nullptr;
+    void *d_gpart = nullptr;                    // split-K adjoint partials [slots][Np][Np]: FP64, FP32 (split)
     void *d_bop = nullptr;                      // operand image [C][np][np]
     void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [C][n][n]
     double *d_scal = nullptr;                   // [C][NSCAL]

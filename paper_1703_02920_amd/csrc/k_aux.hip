@@ -196,8 +196,8 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
 // mode 1: out = A o G + lambda (ln(I/M) + 1)            (grad Phi)
 // mode 2: as 1 into g; gt = g with zeros on the active set; partials
 //         [0] = gt_new . gt_new, [1] = gt_new . gt_old; gt updated in place.
-template <typename R, int RP>
-__global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart, const int *__restrict__ slot_base,
+template <typename R, int RP, typename PT>
+__global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, const int *__restrict__ slot_base,
                                                const R *__restrict__ beam, const R *__restrict__ I,
                                                R *__restrict__ out, R *__restrict__ gt,
                                                double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
 #pragma unroll
             for (int r = 0; r < RP; ++r)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[r][u] = gpart[(size_t)(s + u) * np2 + off[r]];
+                for (int u = 0; u < 8; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
 #pragma unroll
             for (int r = 0; r < RP; ++r)
 #pragma unroll
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NTHR) void k_grad(const double *__restrict__ gpart,
         }
         for (; s < s1; ++s) {
 #pragma unroll
-            for (int r = 0; r < RP; ++r) Gs[r] += gpart[(size_t)s * np2 + off[r]];
+            for (int r = 0; r < RP; ++r) Gs[r] += (double)gpart[(size_t)s * np2 + off[r]];
         }
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
@@ -736,17 +736,27 @@ hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipSt
 }
 
 // k_grad with 4 pixels per thread and round when the pixel blocks are long
-// enough, else 1 (more workgroups, fewer loads in flight per thread)
-template <typename R>
-void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+// enough, else 1 (more workgroups, fewer loads in flight per thread); the
+// split-K partials are FP32 for the split precisions, else FP64
+template <typename R, typename PT>
+void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+    const PT *gp = static_cast<const PT *>(c->d_gpart);
     if (c->pix_blk >= 4 * NTHR)
-        hipLaunchKernelGGL((k_grad<R, 4>), dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
+        hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
                            CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
                            c->pix_blk, c->M, c->Mb, c->lam, mode);
     else
-        hipLaunchKernelGGL((k_grad<R, 1>), dim3(pix_grid(c)), dim3(NTHR), 0, st, c->d_gpart, c->d_slot_base,
+        hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
                            CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
                            c->pix_blk, c->M, c->Mb, c->lam, mode);
+}
+
+template <typename R>
+void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+    if (c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3)
+        grad_launch_t<R, float>(c, I, out, ppart, mode, st);
+    else
+        grad_launch_t<R, double>(c, I, out, ppart, mode, st);
 }
 
 template <typename R>

@@ -119,28 +119,36 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             accR[t] = Mfma<T>::zero();
             accI[t] = Mfma<T>::zero();
         }
+        // coarse factors E(a_k (j0 + js - N/2)) of four 16-column steps: lane
+        // group g computes step 4 u + g, the others read it by lane exchange
+        for (int js0 = 0; js0 < JB; js0 += 64) {
+        T cc4, sc4;
+        cis2pi((T)phase(ak, j0 + js0 + 16 * g - half), cc4, sc4);
 #pragma unroll 2
-        for (int js = 0; js < JB; js += 16) {
-            T cc, sc;
-            cis2pi((T)phase(ak, j0 + js - half), cc, sc);
+        for (int m = 0; m < 4; ++m) {
+            const int js = js0 + 16 * m;
+            const T cc = __shfl(cc4, q + 16 * m, 64), sc = __shfl(sc4, q + 16 * m, 64);
             T cr[4], ci[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 cr[s] = cc * fc[s] - sc * fs[s];
                 ci[s] = -(sc * fc[s] + cc * fs[s]);
             }
+            T4 bv[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const T4 bv = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
-                accR[t] = Mfma<T>::mma(cr[0], bv.x, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[0], bv.x, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[1], bv.y, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[1], bv.y, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[2], bv.z, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[2], bv.z, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[3], bv.w, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[3], bv.w, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[0], bv[t].x, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[0], bv[t].x, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[1], bv[t].y, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[1], bv[t].y, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[2], bv[t].z, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[2], bv[t].z, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[3], bv[t].w, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[3], bv[t].w, accI[t]);
             }
+        }
         }
         // per-wave coarse factors E(16 b_k t) of the tile's 16 rows
         for (int e = lane; e < 16 * NT; e += 64) {
@@ -504,30 +512,43 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
             accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
             accI[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-#pragma unroll 2
-        for (int ks = 0; ks < KSTEPS; ++ks) {
+        // E_u operand of 32-column step ks: E(a_k (j0 + 32 ks + 8 g - N/2)) E(a_k e)
+        auto twiddle = [&](int ks, h8 &th, h8 &tl, h8 &uh, h8 &ul) {
             float cc, sc;
             cis2pi_hw((float)phase(ak, j0 + 32 * ks + 8 * g - half), cc, sc);
-            h8 rh, rl, ih, il;
             float cv[8], nsv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 cv[e] = cc * fc[e] - sc * fs[e];
                 nsv[e] = -(sc * fc[e] + cc * fs[e]);
             }
-            split8<H>(cv, rh, rl);
-            split8<H>(nsv, ih, il);
+            split8<H>(cv, th, tl);
+            split8<H>(nsv, uh, ul);
+        };
+        auto contract = [&](int ks, const h8 &rh, const h8 &rl, const h8 &ih, const h8 &il) {
+            // all image fragments of the step first (one LDS wait), then the
+            // matrix-core instructions
+            h8 bhv[NT], blv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const h8 bhv = *reinterpret_cast<const h8 *>(&sH[16 * t + q][32 * ks + 8 * g]);
-                const h8 blv = *reinterpret_cast<const h8 *>(&sL[16 * t + q][32 * ks + 8 * g]);
-                accR[t] = Half16<H>::mma(rh, bhv, accR[t]);
-                accI[t] = Half16<H>::mma(ih, bhv, accI[t]);
-                accR[t] = Half16<H>::mma(rh, blv, accR[t]);
-                accI[t] = Half16<H>::mma(ih, blv, accI[t]);
-                accR[t] = Half16<H>::mma(rl, bhv, accR[t]);
-                accI[t] = Half16<H>::mma(il, bhv, accI[t]);
+                bhv[t] = *reinterpret_cast<const h8 *>(&sH[16 * t + q][32 * ks + 8 * g]);
+                blv[t] = *reinterpret_cast<const h8 *>(&sL[16 * t + q][32 * ks + 8 * g]);
             }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                accR[t] = Half16<H>::mma(rh, bhv[t], accR[t]);
+                accI[t] = Half16<H>::mma(ih, bhv[t], accI[t]);
+                accR[t] = Half16<H>::mma(rh, blv[t], accR[t]);
+                accI[t] = Half16<H>::mma(ih, blv[t], accI[t]);
+                accR[t] = Half16<H>::mma(rl, bhv[t], accR[t]);
+                accI[t] = Half16<H>::mma(il, bhv[t], accI[t]);
+            }
+        };
+#pragma unroll 2
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            h8 rh, rl, ih, il;
+            twiddle(ks, rh, rl, ih, il);
+            contract(ks, rh, rl, ih, il);
         }
         // row dot: E_v[k][i0 + 16 t + q] = E(b_k (i0 + q - N/2)) E(16 b_k)^t
 #pragma unroll
@@ -577,7 +598,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
                                                         const float *__restrict__ w,
                                                         const double *__restrict__ vispart,
                                                         const int *__restrict__ vis_base,
-                                                        double *__restrict__ gpart, int n, int np) {
+                                                        float *__restrict__ gpart, int n, int np) {
     typedef typename Half16<H>::h8 h8;
     constexpr int TT = 2 * WT;
     constexpr int NT = WT / 16;
@@ -727,7 +748,8 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
         __syncthreads();
         cur = nxt;
     }
-    double *out = gpart + (size_t)it.slot * np * np;
+    float *out = gpart + (size_t)it.slot * np * np;
+    const float inv = 1.f / scale;   // a power of two: exact
 #pragma unroll
     for (int x = 0; x < NT; ++x)
 #pragma unroll
@@ -736,7 +758,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * x + 4 * g + r;
                 const int j = j0 + wj + 16 * y + q;
-                out[(size_t)i * np + j] = (double)acc[x][y][r] / (double)scale;
+                out[(size_t)i * np + j] = acc[x][y][r] * inv;
             }
 }
 
@@ -753,7 +775,7 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
 //      E[j][k] = Fu Gu (waves 4-7), split into hi and lo halves;
 //   3. each wave keeps its four E column blocks in registers and streams its
 //      eight P row blocks: 6 MFMAs per 16 x 16 block pair.
-// Chunk sums are FP32; the partial tile is stored in FP64.
+// Chunk sums are FP32 and the partial tile is stored in FP32.
 template <typename H>
 __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restrict__ items,
                                                          const double *__restrict__ a,
@@ -762,7 +784,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
                                                          const float *__restrict__ w,
                                                          const double *__restrict__ vispart,
                                                          const int *__restrict__ vis_base,
-                                                         double *__restrict__ gpart, int n, int np) {
+                                                         float *__restrict__ gpart, int n, int np) {
     typedef typename Half16<H>::h8 h8;
     constexpr int TT = 256;
     constexpr int KS = 32;
@@ -901,8 +923,8 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
         }
         cur = nxt;
     }
-    double *out = gpart + (size_t)it.slot * np * np;
-    const double inv = 1.0 / (double)scale;
+    float *out = gpart + (size_t)it.slot * np * np;
+    const float inv = 1.f / scale;   // a power of two: exact
 #pragma unroll
     for (int x = 0; x < NR; ++x)
 #pragma unroll
@@ -911,7 +933,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + 16 * x + 4 * g + r;
                 const int j = j0 + wj + 16 * y + q;
-                out[(size_t)i * np + j] = (double)acc[x][y][r] * inv;
+                out[(size_t)i * np + j] = acc[x][y][r] * inv;
             }
 }
 
@@ -941,10 +963,10 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
     if (c->n_adj == 0) return hipSuccess;
     if (c->adj_tt == 128)
         hipLaunchKernelGGL((k_adjoint<T, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
-                           c->d_b, coef, w, c->d_gpart, c->n, c->np);
+                           c->d_b, coef, w, (double *)c->d_gpart, c->n, c->np);
     else
         hipLaunchKernelGGL((k_adjoint<T, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
-                           c->d_b, coef, w, c->d_gpart, c->n, c->np);
+                           c->d_b, coef, w, (double *)c->d_gpart, c->n, c->np);
     return hipGetLastError();
 }
 
@@ -970,13 +992,13 @@ hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipS
     if (c->n_adj == 0) return hipSuccess;
     if (c->adj_tt == 256)
         hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(c->n_adj), dim3(512), 0, st, c->d_adj, c->d_a, c->d_b,
-                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
+                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else if (c->adj_tt == 128)
         hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
-                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
+                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else
         hipLaunchKernelGGL((k_adjoint_h16<H, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
-                           coef, w, c->d_vispart, c->d_vis_base, c->d_gpart, c->n, c->np);
+                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     return hipGetLastError();
 }
 
