@@ -456,9 +456,13 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
     typedef typename Half16<H>::h8 h8;
     constexpr int NT = IB / 16;
     constexpr int KSTEPS = JB / 32;
-    constexpr int PADC = 8;
-    __shared__ __attribute__((aligned(16))) H sH[IB][JB + PADC];
-    __shared__ __attribute__((aligned(16))) H sL[IB][JB + PADC];
+    // 8-element column group cg of row r is stored at group cg ^ (r & SWM):
+    // the 16 rows read by one matrix-core operand load then fall into
+    // distinct LDS banks
+    constexpr int NCG = JB / 8;
+    constexpr int SWM = NCG >= 16 ? 15 : NCG - 1;
+    __shared__ __attribute__((aligned(16))) H sH[IB][JB];
+    __shared__ __attribute__((aligned(16))) H sL[IB][JB];
     __shared__ float sMax[8];
 
     const FwdPItem it = items[blockIdx.x];
@@ -487,12 +491,18 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
         for (int x = 1; x < 8; ++x) m = fmaxf(m, sMax[x]);
         scale = pow2_scale(m);
     }
-    for (int x = tid; x < IB * VROW; x += 512) {
-        const int row = x / VROW, c4 = x % VROW;
-        const float4 v = *reinterpret_cast<const float4 *>(Bc + (size_t)(i0 + row) * np + j0 + 4 * c4);
-        const float vv[4] = {v.x * scale, v.y * scale, v.z * scale, v.w * scale};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) split16(vv[e], sH[row][4 * c4 + e], sL[row][4 * c4 + e]);
+    for (int x = tid; x < IB * NCG; x += 512) {
+        const int row = x / NCG, cg = x % NCG;
+        const float *src = Bc + (size_t)(i0 + row) * np + j0 + 8 * cg;
+        const float4 v0 = *reinterpret_cast<const float4 *>(src);
+        const float4 v1 = *reinterpret_cast<const float4 *>(src + 4);
+        const float vv[8] = {v0.x * scale, v0.y * scale, v0.z * scale, v0.w * scale,
+                             v1.x * scale, v1.y * scale, v1.z * scale, v1.w * scale};
+        h8 hv, lv;
+        split8<H>(vv, hv, lv);
+        const int o = 8 * (cg ^ (row & SWM));
+        *reinterpret_cast<h8 *>(&sH[row][o]) = hv;
+        *reinterpret_cast<h8 *>(&sL[row][o]) = lv;
     }
     __syncthreads();
     const float unscale = 1.f / scale;
@@ -531,8 +541,9 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
             h8 bhv[NT], blv[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                bhv[t] = *reinterpret_cast<const h8 *>(&sH[16 * t + q][32 * ks + 8 * g]);
-                blv[t] = *reinterpret_cast<const h8 *>(&sL[16 * t + q][32 * ks + 8 * g]);
+                const int o = 8 * ((4 * ks + g) ^ (q & SWM));
+                bhv[t] = *reinterpret_cast<const h8 *>(&sH[16 * t + q][o]);
+                blv[t] = *reinterpret_cast<const h8 *>(&sL[16 * t + q][o]);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
