@@ -458,7 +458,7 @@ int uvmem_finalize(uvmem_ctx *c) {
         auto shares = [&](int64_t wgs, int ch) {
             const int64_t nv = c->nvis[ch];
             const int64_t L = std::max<int64_t>(16, (c->ztot * nblk + wgs - 1) / wgs);
-            const int64_t tl = (nv + 15) / 16;
+            const int64_t tl = (nv + 15) / 16;   // 16-visibility wave tiles
             return std::max<int64_t>(1, std::min<int64_t>((nv + L - 1) / L, (tl + 7) / 8));
         };
         int fwd_m = pick_schedule(256, [&](int m) {

@@ -117,16 +117,14 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
 // mode 3: R_k += alpha_c Vd_k; partial[0] = sum w |R|^2
 // mode 4: R is a caller's coefficient vector, only read (w may be null)
 // with_max (modes 1, 3, 4): partial[2] = max over the item of w max(|Re R|, |Im R|)
-__global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
-                                              const double2 *__restrict__ vpart, int n_parts, long long ztot,
-                                              const float2 *__restrict__ vo, const float *__restrict__ w,
-                                              double2 *__restrict__ R, double2 *__restrict__ Vd,
-                                              double2 *__restrict__ out, const double *__restrict__ scal,
-                                              double *__restrict__ vispart, int mode, int with_max) {
-    const VisItem it = items[blockIdx.x];
+// One visibility item (index `item`); `alpha` is the step length of mode 3.
+__device__ __forceinline__ void vis_item(const VisItem it, int item, const double2 *__restrict__ vpart,
+                                         int n_parts, long long ztot, const float2 *__restrict__ vo,
+                                         const float *__restrict__ w, double2 *__restrict__ R,
+                                         double2 *__restrict__ Vd, double2 *__restrict__ out,
+                                         double *__restrict__ vispart, int mode, int with_max, double alpha) {
     double acc[2] = {0.0, 0.0};
     double cmax = 0.0;   // max |Re|, |Im| of the adjoint's coefficients w R (mode 4: R alone)
-    const double alpha = mode == 3 ? scal[(size_t)it.chan * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
     constexpr int U = 2;   // visibilities per thread and round, loads issued together
     for (long long k0 = it.kbeg; k0 < it.kend; k0 += U * NTHR) {
         double2 v[U];
@@ -180,14 +178,25 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
     if (mode != 0 && mode != 4) {
         block_sum<2>(acc);
         if (threadIdx.x == 0) {
-            vispart[(size_t)blockIdx.x * NPART + 0] = acc[0];
-            vispart[(size_t)blockIdx.x * NPART + 1] = acc[1];
+            vispart[(size_t)item * NPART + 0] = acc[0];
+            vispart[(size_t)item * NPART + 1] = acc[1];
         }
     }
     if (with_max && mode != 0 && mode != 2) {
         cmax = -block_min(-cmax);
-        if (threadIdx.x == 0) vispart[(size_t)blockIdx.x * NPART + 2] = cmax;
+        if (threadIdx.x == 0) vispart[(size_t)item * NPART + 2] = cmax;
     }
+}
+
+__global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
+                                              const double2 *__restrict__ vpart, int n_parts, long long ztot,
+                                              const float2 *__restrict__ vo, const float *__restrict__ w,
+                                              double2 *__restrict__ R, double2 *__restrict__ Vd,
+                                              double2 *__restrict__ out, const double *__restrict__ scal,
+                                              double *__restrict__ vispart, int mode, int with_max) {
+    const VisItem it = items[blockIdx.x];
+    const double alpha = mode == 3 ? scal[(size_t)it.chan * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
+    vis_item(it, blockIdx.x, vpart, n_parts, ztot, vo, w, R, Vd, out, vispart, mode, with_max, alpha);
 }
 
 // ---------------------------------------------------------------- gradient
@@ -631,8 +640,17 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
                                                     const double *__restrict__ ls_prev, const double *__restrict__ pp_prev,
                                                     double *__restrict__ pp_out, double *__restrict__ scal,
                                                     double *__restrict__ chan, int *__restrict__ flag,
-                                                    int n, int n_pb, int pb_len, double M, double Mb, double lam) {
-    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
+                                                    int n, int n_pb, int pb_len, double M, double Mb, double lam,
+                                                    const VisItem *__restrict__ vitems, const float *__restrict__ w,
+                                                    double2 *__restrict__ Rv, const double2 *__restrict__ Vd,
+                                                    double *__restrict__ vispart, int n_pixwg, int with_max) {
+    // workgroups past the pixel grid update the residuals of one visibility
+    // item each (step 9); every workgroup derives the channel's final alpha
+    // from the line-search state itself
+    const bool visw = (int)blockIdx.x >= n_pixwg;
+    const int vi = (int)blockIdx.x - n_pixwg;
+    const VisItem vit = visw ? vitems[vi] : VisItem{};
+    const int c = visw ? vit.chan : (int)blockIdx.x / n_pb, pb = visw ? -1 : (int)blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
     if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
@@ -647,6 +665,10 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
     }
     __syncthreads();
     const double al = st[LSS_ALPHA];
+    if (visw) {
+        vis_item(vit, vi, nullptr, 0, 0, nullptr, w, Rv, const_cast<double2 *>(Vd), nullptr, vispart, 3, with_max, al);
+        return;
+    }
     if (pb == 0 && threadIdx.x == 0) {
         double *sc = scal + (size_t)c * UVMEM_NSCAL;
         sc[UVMEM_S_ALPHA] = al;
@@ -884,15 +906,13 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
                                c->d_vis_base, c->d_chan, c->n, c->n_pb, c->pix_blk, c->M, c->lam, t == 0 ? 1 : 0);
         }
         const int last = (L - 1) % 2;   // pp buffer holding the last partials
-        // 8. final update of the step, I <- max(I + alpha d, M), entropy partial
-        hipLaunchKernelGGL(k_cg_update<R>, gp, blk, 0, st, P<R>(I), CP<R>(c->d_dir), lsb(c, 1 - last),
-                           pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->pix_blk, c->M,
-                           c->Mb, c->lam);
-        // 9. R <- R + alpha Vd, chi^2 partials
-        if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
-                               (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, 3, adj_scaled(c));
+        // 8-9. one launch: the final update of the step, I <- max(I + alpha d, M)
+        // and its entropy partial (pixel workgroups); R <- R + alpha Vd and the
+        // chi^2 partials (visibility workgroups)
+        hipLaunchKernelGGL(k_cg_update<R>, dim3(pix_grid(c) + c->n_visit), blk, 0, st, P<R>(I), CP<R>(c->d_dir),
+                           lsb(c, 1 - last), pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n,
+                           c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, c->d_vis, c->d_w, c->d_R, c->d_Vd,
+                           c->d_vispart, pix_grid(c), adj_scaled(c));
         return hipGetLastError();
     }
     // 11. gradient at the new point, projected gradient, PR partials

@@ -446,7 +446,7 @@ __device__ __forceinline__ void cis2pi_hw(float f, float &c, float &s) {
 // eight fine factors (hardware sin/cos of FP64-reduced phases), contracts the
 // block on matrix cores, then does the row dot with E_v and writes the
 // block's partial V_k.
-template <typename H, int IB, int JB>
+template <typename H, int IB, int JB, int NV>
 __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restrict__ items,
                                                          const double *__restrict__ a,
                                                          const double *__restrict__ b,
@@ -506,89 +506,101 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
     }
     __syncthreads();
     const float unscale = 1.f / scale;
+    // a wave's tile: NV groups of 16 visibilities that share every image
+    // fragment read from LDS
+    constexpr int TV = 16 * NV;
     const long long nk = it.kend - it.kbeg;
-    const long long ntiles = (nk + 15) / 16;
+    const long long ntiles = (nk + TV - 1) / TV;
     const long long stride = 8LL * it.nwg;
     for (long long tile = (long long)it.wg * 8 + wave; tile < ntiles; tile += stride) {
-        const long long k0 = it.kbeg + 16 * tile;
-        const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
-        const double ak = q < nvalid ? a[k0 + q] : 0.0;
-        float fc[8], fs[8];
+        const long long k0 = it.kbeg + TV * tile;
+        const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
+        double ak[NV];
+        float fc[NV][8], fs[NV][8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
-        floatx4 accR[NT], accI[NT];
+        for (int v = 0; v < NV; ++v) {
+            ak[v] = 16 * v + q < nvalid ? a[k0 + 16 * v + q] : 0.0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-            accI[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak[v], e), fc[v][e], fs[v][e]);
         }
-        // E_u operand of 32-column step ks: E(a_k (j0 + 32 ks + 8 g - N/2)) E(a_k e)
-        auto twiddle = [&](int ks, h8 &th, h8 &tl, h8 &uh, h8 &ul) {
+        floatx4 accR[NV][NT], accI[NV][NT];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                accR[v][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+                accI[v][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+        // E_u operand of group v, 32-column step ks: E(a_k (j0 + 32 ks + 8 g - N/2)) E(a_k e)
+        auto twiddle = [&](int ks, int v, h8 &th, h8 &tl, h8 &uh, h8 &ul) {
             float cc, sc;
-            cis2pi_hw((float)phase(ak, j0 + 32 * ks + 8 * g - half), cc, sc);
+            cis2pi_hw((float)phase(ak[v], j0 + 32 * ks + 8 * g - half), cc, sc);
             float cv[8], nsv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                cv[e] = cc * fc[e] - sc * fs[e];
-                nsv[e] = -(sc * fc[e] + cc * fs[e]);
+                cv[e] = cc * fc[v][e] - sc * fs[v][e];
+                nsv[e] = -(sc * fc[v][e] + cc * fs[v][e]);
             }
             split8<H>(cv, th, tl);
             split8<H>(nsv, uh, ul);
         };
-        auto contract = [&](int ks, const h8 &rh, const h8 &rl, const h8 &ih, const h8 &il) {
-            // all image fragments of the step first (one LDS wait), then the
-            // matrix-core instructions
-            h8 bhv[NT], blv[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int o = 8 * ((4 * ks + g) ^ (q & SWM));
-                bhv[t] = *reinterpret_cast<const h8 *>(&sH[16 * t + q][o]);
-                blv[t] = *reinterpret_cast<const h8 *>(&sL[16 * t + q][o]);
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                accR[t] = Half16<H>::mma(rh, bhv[t], accR[t]);
-                accI[t] = Half16<H>::mma(ih, bhv[t], accI[t]);
-                accR[t] = Half16<H>::mma(rh, blv[t], accR[t]);
-                accI[t] = Half16<H>::mma(ih, blv[t], accI[t]);
-                accR[t] = Half16<H>::mma(rl, bhv[t], accR[t]);
-                accI[t] = Half16<H>::mma(il, bhv[t], accI[t]);
-            }
-        };
 #pragma unroll 2
         for (int ks = 0; ks < KSTEPS; ++ks) {
-            h8 rh, rl, ih, il;
-            twiddle(ks, rh, rl, ih, il);
-            contract(ks, rh, rl, ih, il);
+            h8 rh[NV], rl[NV], ih[NV], il[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) twiddle(ks, v, rh[v], rl[v], ih[v], il[v]);
+            const int o = 8 * ((4 * ks + g) ^ (q & SWM));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const h8 bhv = *reinterpret_cast<const h8 *>(&sH[16 * t + q][o]);
+                const h8 blv = *reinterpret_cast<const h8 *>(&sL[16 * t + q][o]);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    accR[v][t] = Half16<H>::mma(rh[v], bhv, accR[v][t]);
+                    accI[v][t] = Half16<H>::mma(ih[v], bhv, accI[v][t]);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    accR[v][t] = Half16<H>::mma(rh[v], blv, accR[v][t]);
+                    accI[v][t] = Half16<H>::mma(ih[v], blv, accI[v][t]);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    accR[v][t] = Half16<H>::mma(rl[v], bhv, accR[v][t]);
+                    accI[v][t] = Half16<H>::mma(il[v], bhv, accI[v][t]);
+                }
+            }
         }
         // row dot: E_v[k][i0 + 16 t + q] = E(b_k (i0 + q - N/2)) E(16 b_k)^t
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int kk = 4 * g + r;
-            const bool ok = kk < nvalid;
-            const double bk = ok ? b[k0 + kk] : 0.0;
-            float ec, es, sc16, ss16;
-            cis2pi_hw((float)phase(bk, i0 + q - half), ec, es);
-            cis2pi_hw((float)phase(bk, 16), sc16, ss16);
-            float vr = 0.f, vi = 0.f;
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float tr = accR[t][r], ti = accI[t][r];
-                vr += ec * tr + es * ti;
-                vi += ec * ti - es * tr;
-                const float nc = ec * sc16 - es * ss16;
-                es = es * sc16 + ec * ss16;
-                ec = nc;
-            }
+            for (int r = 0; r < 4; ++r) {
+                const int kk = 16 * v + 4 * g + r;
+                const bool ok = kk < nvalid;
+                const double bk = ok ? b[k0 + kk] : 0.0;
+                float ec, es, sc16, ss16;
+                cis2pi_hw((float)phase(bk, i0 + q - half), ec, es);
+                cis2pi_hw((float)phase(bk, 16), sc16, ss16);
+                float vr = 0.f, vi = 0.f;
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                vr += __shfl_xor(vr, o, 64);
-                vi += __shfl_xor(vi, o, 64);
+                for (int t = 0; t < NT; ++t) {
+                    const float tr = accR[v][t][r], ti = accI[v][t][r];
+                    vr += ec * tr + es * ti;
+                    vi += ec * ti - es * tr;
+                    const float nc = ec * sc16 - es * ss16;
+                    es = es * sc16 + ec * ss16;
+                    ec = nc;
+                }
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) {
+                    vr += __shfl_xor(vr, o, 64);
+                    vi += __shfl_xor(vi, o, 64);
+                }
+                if (q == 0 && ok)
+                    vpart[(size_t)it.part * ztot + k0 + kk] =
+                        make_double2((double)vr * (double)unscale, (double)vi * (double)unscale);
             }
-            if (q == 0 && ok)
-                vpart[(size_t)it.part * ztot + k0 + kk] =
-                    make_double2((double)vr * (double)unscale, (double)vi * (double)unscale);
-        }
     }
 }
 
@@ -909,14 +921,21 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
             esh[y] = *reinterpret_cast<const h8 *>(&sE[2][r][o]);
             esl[y] = *reinterpret_cast<const h8 *>(&sE[3][r][o]);
         }
-#pragma unroll
-        for (int x = 0; x < NR; ++x) {
+        // P fragments of row block x + 1 are loaded while block x contracts
+        h8 nph, npl, nqh, nql;
+        auto load_p = [&](int x, h8 &ph, h8 &pl, h8 &qh, h8 &ql) {
             const int r = wi + 16 * x + q;
             const int o = swz(r, g);
-            const h8 prh = *reinterpret_cast<const h8 *>(&sP[0][r][o]);
-            const h8 prl = *reinterpret_cast<const h8 *>(&sP[1][r][o]);
-            const h8 pih = *reinterpret_cast<const h8 *>(&sP[2][r][o]);
-            const h8 pil = *reinterpret_cast<const h8 *>(&sP[3][r][o]);
+            ph = *reinterpret_cast<const h8 *>(&sP[0][r][o]);
+            pl = *reinterpret_cast<const h8 *>(&sP[1][r][o]);
+            qh = *reinterpret_cast<const h8 *>(&sP[2][r][o]);
+            ql = *reinterpret_cast<const h8 *>(&sP[3][r][o]);
+        };
+        load_p(0, nph, npl, nqh, nql);
+#pragma unroll
+        for (int x = 0; x < NR; ++x) {
+            const h8 prh = nph, prl = npl, pih = nqh, pil = nql;
+            if (x + 1 < NR) load_p(x + 1, nph, npl, nqh, nql);
             // product-major order: four independent accumulators between
             // dependent matrix-core instructions
 #pragma unroll
@@ -981,21 +1000,27 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
     return hipGetLastError();
 }
 
+template <typename H, int NV>
+hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st) {
+    const dim3 grid(c->n_fwdp), blk(512);
+    if (c->ib_rows == 128 && c->jb_cols == 256)
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    else if (c->ib_rows == 128 && c->jb_cols == 128)
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    else
+        hipLaunchKernelGGL((k_forward_h16p<H, 64, 64, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+    return hipGetLastError();
+}
+
+// One 16-visibility group per wave tile: two groups (one LDS image read for
+// twice the matrix-core work) measured slower on 256^2 (register pressure).
 template <typename H>
 hipError_t fwd_h16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
     if (c->n_fwdp == 0) return hipSuccess;
-    const float *B = reinterpret_cast<const float *>(bop);
-    const dim3 grid(c->n_fwdp), blk(512);
-    if (c->ib_rows == 128 && c->jb_cols == 256)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
-                           c->d_vpart, c->n, c->np, (long long)c->ztot);
-    else if (c->ib_rows == 128 && c->jb_cols == 128)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
-                           c->d_vpart, c->n, c->np, (long long)c->ztot);
-    else
-        hipLaunchKernelGGL((k_forward_h16p<H, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
-                           c->d_vpart, c->n, c->np, (long long)c->ztot);
-    return hipGetLastError();
+    return fwd_h16_t<H, 1>(c, reinterpret_cast<const float *>(bop), st);
 }
 
 template <typename H>
