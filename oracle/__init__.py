@@ -12,11 +12,12 @@ marshals numpy arrays and composes the objective of Eq. phi2/phi3:
     grad Phi = A o Re F^H (w o R) + lambda (ln(I/M) + 1)   (Eq. chi2gradient,
              with the beam factor of the exact derivative).
 
-Readings where the paper is ambiguous are listed in the design doc; the ones this
-file depends on: the 1/2 in chi^2 (Eq. phi2), S written with M in place of G
-and without the 1/G prefactor (so that Eq. Sgradient is its exact gradient),
-the sign Phi = chi^2 + lambda S (the paper's S carries the opposite sign), and
-the beam factor A_ij kept in the chi^2 gradient.
+Readings taken where the paper is ambiguous, on which this file depends:
+the 1/2 in chi^2 (Eq. phi2), S written with M in place of G and without the
+1/G prefactor (so that Eq. Sgradient is its exact gradient), the sign
+Phi = chi^2 + lambda S (the paper's S carries the opposite sign), the beam
+factor A_ij kept in the chi^2 gradient, and, for one image fitted to several
+channels, the entropy term counted once (Eq. chi2-multi sums only chi^2).
 """
 from __future__ import annotations
 
@@ -167,3 +168,30 @@ def phi_grad(n, cell, u, v, A, I, Vo, w, M, lam):
     gchi = adjoint(n, cell, u, v, A, _f64(w) * R)
     grad = gchi + lam * gS
     return dict(phi=x2 + lam * S, chi2=x2, S=S, grad=grad, gchi2=gchi, V=V, R=R)
+
+
+def phi_grad_shared(n, cell, chans, I, M, lam):
+    """Phi and grad Phi of ONE image seen by several channels (Eq. chi2-multi).
+
+    chi^2 is the sum over the channels of Eq. phi2, each channel with its own
+    (u, v), weights and attenuation image A_c (Sec. 2.4 item 1: one
+    attenuation matrix per channel); grad chi^2 is the sum of the channels'
+    gradients of Eq. chi2gradient (the per-channel gradients that the
+    multi-channel gradient function of Sec. 2.7 adds into one image); S and
+    its gradient are counted once.  `chans` is a sequence of dicts with keys
+    u, v, A, vis, w."""
+    I = _f64(I)
+    x2 = 0.0
+    gchi = np.zeros((n, n))
+    Vs, Rs = [], []
+    for ch in chans:
+        V = forward(n, cell, ch["u"], ch["v"], ch["A"], I)
+        x, R = chi2(V, ch["vis"], ch["w"])
+        gchi += adjoint(n, cell, ch["u"], ch["v"], ch["A"], _f64(ch["w"]) * R)
+        x2 += x
+        Vs.append(V)
+        Rs.append(R)
+    S, gS = entropy(I, M)
+    return dict(phi=x2 + lam * S, chi2=x2, S=S, grad=gchi + lam * gS, gchi2=gchi,
+                V=np.concatenate(Vs) if Vs else np.zeros(0, np.complex128),
+                R=np.concatenate(Rs) if Rs else np.zeros(0, np.complex128))

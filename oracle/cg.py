@@ -70,6 +70,37 @@ class Problem:
         return dict(V=V, R=R, chi2=x2, S=S, phi=x2 + self.lam * S, g=g)
 
 
+class SharedProblem(Problem):
+    """One image fitted to several channels (Eq. chi2-multi): the forward
+    model is the concatenation of the channels' visibilities, each channel
+    with its own uv, weights and beam; the adjoint of concatenated
+    coefficients is the sum of the channels' adjoint images.  The CG below
+    then runs unchanged on the one image."""
+
+    def __init__(self, n, cell, chans, M, lam):
+        self.n = n
+        self.cell = cell
+        self.chans = [dict(u=np.asarray(c["u"], np.float64), v=np.asarray(c["v"], np.float64),
+                           A=None if c["A"] is None else np.asarray(c["A"], np.float64))
+                      for c in chans]
+        self.sizes = [int(c["u"].shape[0]) for c in self.chans]
+        self.vis = np.concatenate([np.asarray(c["vis"], np.complex128) for c in chans])
+        self.w = np.concatenate([np.asarray(c["w"], np.float64) for c in chans])
+        self.M = float(M)
+        self.lam = float(lam)
+
+    def F(self, img):
+        return np.concatenate([forward(self.n, self.cell, c["u"], c["v"], c["A"], img) for c in self.chans])
+
+    def FH(self, coef):
+        out = np.zeros((self.n, self.n))
+        o = 0
+        for c, z in zip(self.chans, self.sizes):
+            out += adjoint(self.n, self.cell, c["u"], c["v"], c["A"], coef[o:o + z])
+            o += z
+        return out
+
+
 def line_search(a, b, I, d, M, lam, alpha_max, max_steps=100, rtol=1e-13):
     """Exact minimiser of phi on [0, alpha_max] (steps 6-7)."""
     def dphi(al):
