@@ -21,9 +21,10 @@
  * Geometry: image side N (even), pixel (i, j) at x_j = (j - N/2) cell,
  * y_i = (i - N/2) cell (Alg. 3 with the phase centre at pixel (N/2, N/2));
  * linear pixel index N*i + j (row i <-> y).  u, v in wavelengths, cell in
- * radians.  Channels are independent problems (cube mode): each has its own
- * image, visibilities, weights and primary beam; Eq. chi2-multi is the sum
- * of the per-channel chi^2 reported alongside.
+ * radians.  Every channel has its own visibilities, weights and primary
+ * beam.  In cube mode the channels are independent problems, each with its
+ * own image; in shared mode one image is seen by all channels and chi^2 is
+ * the sum over channels (Eq. chi2-multi).
  *
  * Conventions for every entry point:
  *  - Return value: UVMEM_OK (0) or a negative uvmem_status.  On error the
@@ -33,7 +34,8 @@
  *  - Pointers named *_dev are device pointers on the context's device; the
  *    caller owns them.  set_* calls accept host or device pointers and copy
  *    the data into buffers the context owns (the caller may free its copy).
- *  - Image-like arrays are [n_chan][N][N] row-major, element type double for
+ *  - Image-like arrays are [n_img][N][N] row-major (n_img = n_chan in cube
+ *    mode, 1 in shared mode; beam images are per channel), element type double for
  *    UVMEM_FP64 and float for every other precision.  Visibility arrays are
  *    the concatenation of the channels in channel order.
  *  - Hot entry points (phi_and_grad, forward, adjoint, cg_step, cg_run) only
@@ -71,11 +73,19 @@ typedef enum uvmem_precision {
     UVMEM_FP16X3 = 3     /* fp16 hi+lo split (power-of-two scaled), three products */
 } uvmem_precision;
 
+/* Image model.  n_img below is the number of image planes: n_chan in cube
+ * mode, 1 in shared mode.  Images, gradients, the CG state and the scalar
+ * records have one plane / record per image; visibilities, weights and
+ * beams stay per channel. */
 typedef enum uvmem_mode {
-    UVMEM_CUBE = 0       /* one image per channel, channels independent       */
+    UVMEM_CUBE = 0,      /* one image per channel, channels independent       */
+    UVMEM_SHARED = 1     /* one image seen by every channel through its own
+                            uv scale and beam A_c (Eq. chi2-multi):
+                            chi^2 = sum_c chi^2_c, grad chi^2 = sum_c A_c o
+                            Re F_c^H (w_c R_c), S and the CG over the one image */
 } uvmem_mode;
 
-/* Per-channel scalar slots, FP64, layout [n_chan][UVMEM_NSCAL]. */
+/* Per-image scalar slots, FP64, layout [n_img][UVMEM_NSCAL]. */
 enum {
     UVMEM_S_PHI = 0,     /* Phi = chi^2 + lambda S                            */
     UVMEM_S_CHI2 = 1,    /* chi^2                                             */
@@ -88,9 +98,10 @@ enum {
     UVMEM_NSCAL = 8
 };
 
-/* Create a context for images of side n (even, 2..8192) and n_chan >= 1
- * channels.  hip_stream is a hipStream_t (NULL = the null stream) on the
- * current device; all work is enqueued there. */
+/* Create a context for images of side n (even, 2..8192), n_chan >= 1
+ * channels and image model `mode` (uvmem_mode).  hip_stream is a hipStream_t
+ * (NULL = the null stream) on the current device; all work is enqueued
+ * there. */
 int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, void *hip_stream);
 int uvmem_destroy(uvmem_ctx *ctx);
 
@@ -116,15 +127,17 @@ int uvmem_set_prior(uvmem_ctx *ctx, double M, double lambda);
  * it, set_* return UVMEM_ESTATE and the hot entry points allocate nothing. */
 int uvmem_finalize(uvmem_ctx *ctx);
 
-/* One evaluation of Phi and grad Phi at I_dev ([n_chan][N][N]).  grad_dev
- * receives grad Phi ([n_chan][N][N]); scal_dev (may be NULL) receives Phi,
- * chi^2 and S per channel in slots UVMEM_S_PHI..UVMEM_S_S of
- * double[n_chan][UVMEM_NSCAL].  The residuals R are kept in the context. */
+/* One evaluation of Phi and grad Phi at I_dev ([n_img][N][N]).  grad_dev
+ * receives grad Phi ([n_img][N][N]); scal_dev (may be NULL) receives Phi,
+ * chi^2 and S per image in slots UVMEM_S_PHI..UVMEM_S_S of
+ * double[n_img][UVMEM_NSCAL].  The residuals R are kept in the context. */
 int uvmem_phi_and_grad(uvmem_ctx *ctx, const void *I_dev, void *grad_dev, double *scal_dev);
-/* Model visibilities V^m = F(I) (Eq. fft): vis_dev is double[sum Z][2]. */
+/* Model visibilities V^m = F(I) (Eq. fft) of every channel: vis_dev is
+ * double[sum Z][2]; I_dev is [n_img][N][N]. */
 int uvmem_forward(uvmem_ctx *ctx, const void *I_dev, void *vis_dev);
 /* Adjoint A o Re F^H c of complex coefficients c (double[sum Z][2], e.g. the
- * weighted residual w R): img_dev is [n_chan][N][N]. */
+ * weighted residual w R): img_dev is [n_img][N][N] (shared mode: the sum
+ * over channels). */
 int uvmem_adjoint(uvmem_ctx *ctx, const void *coef_dev, void *img_dev);
 /* Copy the current residuals R = V^m - V^o (double[sum Z][2]) to res_dev. */
 int uvmem_get_residual(uvmem_ctx *ctx, void *res_dev);
@@ -132,11 +145,11 @@ int uvmem_get_residual(uvmem_ctx *ctx, void *res_dev);
 /* Projected CG (positively constrained, Sec. 2.6).  cg_init evaluates Phi at
  * I_dev (first setting I_dev to M everywhere if init_to_floor) and sets the
  * first direction.  cg_step performs one iteration in place on I_dev (which
- * must be the same buffer as in cg_init) and writes the per-channel scalars
- * (all UVMEM_NSCAL slots) to scal_dev (may be NULL).  A channel whose line
+ * must be the same buffer as in cg_init) and writes the per-image scalars
+ * (all UVMEM_NSCAL slots) to scal_dev (may be NULL).  An image whose line
  * search stalls (no descent, or zero projected gradient) stops: later steps
  * leave it unchanged.  cg_run performs `iters` steps, writing scalars to
- * scal_hist_dev (double[iters][n_chan][UVMEM_NSCAL], may be NULL); with
+ * scal_hist_dev (double[iters][n_img][UVMEM_NSCAL], may be NULL); with
  * use_graph != 0 it replays one step captured as a HIP graph. */
 int uvmem_cg_init(uvmem_ctx *ctx, void *I_dev, int init_to_floor);
 int uvmem_cg_step(uvmem_ctx *ctx, void *I_dev, double *scal_dev);
@@ -163,7 +176,7 @@ int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *coun
  * Np, channels, precision, total visibilities, forward image blocks, adjoint
  * tile side, adjoint split-K slots, forward workgroups, adjoint workgroups,
  * visibility items, device bytes held, pixel blocks per channel, pixels per
- * pixel block, visibilities per visibility item.  uvmem_chan_range
+ * pixel block, visibilities per visibility item, image planes n_img.  uvmem_chan_range
  * gives a channel's offset into the concatenated visibility arrays and its
  * count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);

@@ -71,7 +71,8 @@ hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
 
 void free_all(uvmem_ctx *c) {
     void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwdp, c->d_adj, c->d_vis,
-                    c->d_slot_base, c->d_vis_base, c->d_R, c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
+                    c->d_slot_base, c->d_vis_base, c->d_ivis_base, c->d_ichan_base, c->d_chan_img, c->d_R,
+                    c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr};
     for (void *p : ptrs)
@@ -200,7 +201,7 @@ int build_layout(uvmem_ctx *c) {
     if (const char *env = std::getenv("UVMEM_PIX_WGS")) pix_wgs = std::max(1L, std::atol(env));
     if (const char *env = std::getenv("UVMEM_VIS_WGS")) vis_wgs = std::max(1L, std::atol(env));
     const int64_t npix = (int64_t)c->n * c->n;
-    c->pix_blk = (int)std::max<int64_t>(NTHR, roundup((npix * C + pix_wgs - 1) / pix_wgs, NTHR));
+    c->pix_blk = (int)std::max<int64_t>(NTHR, roundup((npix * c->nimg + pix_wgs - 1) / pix_wgs, NTHR));
     c->n_pb = (int)((npix + c->pix_blk - 1) / c->pix_blk);
     c->vis_blk = (int)std::max<int64_t>(2 * NTHR, roundup((c->ztot + vis_wgs - 1) / vis_wgs, 2 * NTHR));
     return UVMEM_OK;
@@ -229,13 +230,14 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     *out = nullptr;
     if (n < 2 || n > 8192 || (n % 2) != 0) return UVMEM_EINVAL;
     if (n_chan < 1 || n_chan > 65536) return UVMEM_EINVAL;
-    if (mode != UVMEM_CUBE) return UVMEM_EINVAL;
+    if (mode != UVMEM_CUBE && mode != UVMEM_SHARED) return UVMEM_EINVAL;
     if (precision < UVMEM_FP64 || precision > UVMEM_FP16X3) return UVMEM_EINVAL;
     uvmem_ctx *c = new (std::nothrow) uvmem_ctx();
     if (!c) return UVMEM_ENOMEM;
     c->n = n;
     c->nchan = n_chan;
     c->mode = mode;
+    c->nimg = mode == UVMEM_SHARED ? 1 : n_chan;
     c->prec = precision;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -488,6 +490,14 @@ int uvmem_finalize(uvmem_ctx *c) {
     }
     c->n_fwdp = (int)fwdp.size();
     c->h_vis_base[C] = (int)vis.size();
+    // image planes: channel ranges, visibility-item ranges, channel -> image
+    const int IMG = c->nimg;
+    c->h_ichan_base.assign(IMG + 1, 0);
+    c->h_ivis_base.assign(IMG + 1, 0);
+    c->h_chan_img.assign(C, 0);
+    for (int m = 0; m <= IMG; ++m) c->h_ichan_base[m] = IMG == C ? m : (m == 0 ? 0 : C);
+    for (int m = 0; m <= IMG; ++m) c->h_ivis_base[m] = c->h_vis_base[c->h_ichan_base[m]];
+    for (int ch = 0; ch < C; ++ch) c->h_chan_img[ch] = IMG == C ? ch : 0;
     c->n_slots = slot;
     c->n_adj = (int)adj.size();
     c->n_visit = (int)vis.size();
@@ -534,18 +544,21 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_vis, vis.size()));
     ok(dalloc(c, &c->d_slot_base, C + 1));
     ok(dalloc(c, &c->d_vis_base, C + 1));
+    ok(dalloc(c, &c->d_ivis_base, IMG + 1));
+    ok(dalloc(c, &c->d_ichan_base, IMG + 1));
+    ok(dalloc(c, &c->d_chan_img, C));
     ok(dalloc(c, &c->d_R, c->ztot));
     ok(dalloc(c, &c->d_Vd, c->ztot));
     ok(dalloc(c, &c->d_vpart, (size_t)c->n_fparts * c->ztot));
     ok(dalloc(c, (char **)&c->d_gpart, (size_t)c->n_slots * np * np * (split ? sizeof(float) : sizeof(double))));
     ok(dalloc(c, (char **)&c->d_bop, (size_t)C * np * np * rs));
-    ok(dalloc(c, (char **)&c->d_g, C * npix * rs));
-    ok(dalloc(c, (char **)&c->d_gt, C * npix * rs));
-    ok(dalloc(c, (char **)&c->d_dir, C * npix * rs));
-    ok(dalloc(c, &c->d_scal, (size_t)C * UVMEM_NSCAL));
-    ok(dalloc(c, &c->d_chan, (size_t)C * CH_N));
-    ok(dalloc(c, &c->d_ls, (size_t)2 * C * LSS_N));
-    ok(dalloc(c, &c->d_ppart, (size_t)2 * C * c->n_pb * NPART));
+    ok(dalloc(c, (char **)&c->d_g, IMG * npix * rs));
+    ok(dalloc(c, (char **)&c->d_gt, IMG * npix * rs));
+    ok(dalloc(c, (char **)&c->d_dir, IMG * npix * rs));
+    ok(dalloc(c, &c->d_scal, (size_t)IMG * UVMEM_NSCAL));
+    ok(dalloc(c, &c->d_chan, (size_t)IMG * CH_N));
+    ok(dalloc(c, &c->d_ls, (size_t)2 * IMG * LSS_N));
+    ok(dalloc(c, &c->d_ppart, (size_t)2 * IMG * c->n_pb * NPART));
     ok(dalloc(c, &c->d_vispart, (size_t)std::max(c->n_visit, 1) * NPART));
     ok(dalloc(c, &c->d_flag, 4));
     ok(dalloc(c, &c->d_hist_ptr, 1));
@@ -570,6 +583,9 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_vis, vis.data(), vis.size() * sizeof(VisItem));
     up(c->d_slot_base, c->h_slot_base.data(), (C + 1) * sizeof(int));
     up(c->d_vis_base, c->h_vis_base.data(), (C + 1) * sizeof(int));
+    up(c->d_ivis_base, c->h_ivis_base.data(), (IMG + 1) * sizeof(int));
+    up(c->d_ichan_base, c->h_ichan_base.data(), (IMG + 1) * sizeof(int));
+    up(c->d_chan_img, c->h_chan_img.data(), C * sizeof(int));
     if (e != hipSuccess) return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
     HIPCHK(c, hipDeviceSynchronize());
     // release host staging
@@ -658,7 +674,7 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
     if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_run before cg_init");
     if (I != c->cg_I) return fail(c, UVMEM_EINVAL, "cg_run image differs from cg_init's");
     if (iters < 0) return fail(c, UVMEM_EINVAL, "negative iteration count");
-    const size_t stride = (size_t)c->nchan * UVMEM_NSCAL;
+    const size_t stride = (size_t)c->nimg * UVMEM_NSCAL;
     if (!use_graph) {
         for (int t = 0; t < iters; ++t) {
             s = uvmem_cg_step(c, I, hist ? hist + t * stride : nullptr);
@@ -702,7 +718,7 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
 namespace {
 struct StateHeader {
     uint64_t magic;
-    int32_t n, nchan, prec, pad;
+    int32_t n, nchan, prec, mode;
     int64_t ztot;
 };
 const uint64_t STATE_MAGIC = 0x31534d454d5655ull;  // "UVMEMS1"
@@ -712,15 +728,15 @@ int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {
     int s = check_ready(c);
     if (s) return s;
     if (!bytes) return fail(c, UVMEM_EINVAL, "null size");
-    const size_t img = (size_t)c->nchan * c->n * c->n * real_size(c);
+    const size_t img = (size_t)c->nimg * c->n * c->n * real_size(c);
     const size_t need = sizeof(StateHeader) + 3 * img + c->ztot * sizeof(double2) +
-                        (size_t)c->nchan * (UVMEM_NSCAL + CH_N) * sizeof(double);
+                        (size_t)c->nimg * (UVMEM_NSCAL + CH_N) * sizeof(double);
     if (!blob) { *bytes = need; return UVMEM_OK; }
     if (*bytes < need) return fail(c, UVMEM_EINVAL, "state buffer too small (%zu < %zu)", *bytes, need);
     if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "no CG state");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     char *p = (char *)blob;
-    StateHeader h{STATE_MAGIC, c->n, c->nchan, c->prec, 0, c->ztot};
+    StateHeader h{STATE_MAGIC, c->n, c->nchan, c->prec, c->mode, c->ztot};
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
     HIPCHK(c, hipMemcpy(p, c->d_dir, img, hipMemcpyDeviceToHost)); p += img;
@@ -728,9 +744,9 @@ int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {
     HIPCHK(c, hipMemcpy(p, c->d_g, img, hipMemcpyDeviceToHost)); p += img;
     if (c->ztot) HIPCHK(c, hipMemcpy(p, c->d_R, c->ztot * sizeof(double2), hipMemcpyDeviceToHost));
     p += c->ztot * sizeof(double2);
-    HIPCHK(c, hipMemcpy(p, c->d_scal, c->nchan * UVMEM_NSCAL * sizeof(double), hipMemcpyDeviceToHost));
-    p += c->nchan * UVMEM_NSCAL * sizeof(double);
-    HIPCHK(c, hipMemcpy(p, c->d_chan, c->nchan * CH_N * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(p, c->d_scal, c->nimg * UVMEM_NSCAL * sizeof(double), hipMemcpyDeviceToHost));
+    p += c->nimg * UVMEM_NSCAL * sizeof(double);
+    HIPCHK(c, hipMemcpy(p, c->d_chan, c->nimg * CH_N * sizeof(double), hipMemcpyDeviceToHost));
     *bytes = need;
     return UVMEM_OK;
 }
@@ -740,13 +756,14 @@ int uvmem_cg_set_state(uvmem_ctx *c, const void *blob, size_t bytes) {
     if (s) return s;
     if (!blob) return fail(c, UVMEM_EINVAL, "null state");
     if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_set_state before cg_init");
-    const size_t img = (size_t)c->nchan * c->n * c->n * real_size(c);
+    const size_t img = (size_t)c->nimg * c->n * c->n * real_size(c);
     const size_t need = sizeof(StateHeader) + 3 * img + c->ztot * sizeof(double2) +
-                        (size_t)c->nchan * (UVMEM_NSCAL + CH_N) * sizeof(double);
+                        (size_t)c->nimg * (UVMEM_NSCAL + CH_N) * sizeof(double);
     if (bytes < need) return fail(c, UVMEM_EINVAL, "state blob too small");
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
-    if (h.magic != STATE_MAGIC || h.n != c->n || h.nchan != c->nchan || h.prec != c->prec || h.ztot != c->ztot)
+    if (h.magic != STATE_MAGIC || h.n != c->n || h.nchan != c->nchan || h.prec != c->prec || h.mode != c->mode ||
+        h.ztot != c->ztot)
         return fail(c, UVMEM_EINVAL, "state blob does not match this context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const char *p = (const char *)blob + sizeof h;
@@ -755,9 +772,9 @@ int uvmem_cg_set_state(uvmem_ctx *c, const void *blob, size_t bytes) {
     HIPCHK(c, hipMemcpy(c->d_g, p, img, hipMemcpyHostToDevice)); p += img;
     if (c->ztot) HIPCHK(c, hipMemcpy(c->d_R, p, c->ztot * sizeof(double2), hipMemcpyHostToDevice));
     p += c->ztot * sizeof(double2);
-    HIPCHK(c, hipMemcpy(c->d_scal, p, c->nchan * UVMEM_NSCAL * sizeof(double), hipMemcpyHostToDevice));
-    p += c->nchan * UVMEM_NSCAL * sizeof(double);
-    HIPCHK(c, hipMemcpy(c->d_chan, p, c->nchan * CH_N * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_scal, p, c->nimg * UVMEM_NSCAL * sizeof(double), hipMemcpyHostToDevice));
+    p += c->nimg * UVMEM_NSCAL * sizeof(double);
+    HIPCHK(c, hipMemcpy(c->d_chan, p, c->nimg * CH_N * sizeof(double), hipMemcpyHostToDevice));
     return UVMEM_OK;
 }
 
@@ -806,7 +823,7 @@ int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     if (!c || !out) return UVMEM_EINVAL;
     const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
                             c->n_fwdp, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
-                            c->vis_blk};
+                            c->vis_blk, c->nimg};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
     return UVMEM_OK;

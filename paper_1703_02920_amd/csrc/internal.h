@@ -97,6 +97,7 @@ enum {
 
 struct uvmem_ctx {
     int n = 0, np = 0, nchan = 0, mode = 0, prec = 0;
+    int nimg = 0;                      // image planes: nchan (cube) or 1 (shared)
     hipStream_t stream = nullptr;
     int device = 0;
     double cell = 0.0;
@@ -122,12 +123,15 @@ struct uvmem_ctx {
     int n_fparts = 0;                  // forward partials per visibility: n_ib * n_jb
     int adj_tt = 0, adj_nt = 0;        // adjoint tile side, tiles per side
     int n_slots = 0;
-    int n_pb = 0;                      // pixel blocks per channel
+    int n_pb = 0;                      // pixel blocks per image plane
     int pix_blk = 0;                   // pixels per pixel block (multiple of NTHR)
     int vis_blk = 0;                   // visibilities per visibility item (multiple of 2 NTHR)
     int ls_steps = 8;                  // line-search passes per CG step
-    std::vector<int> h_slot_base;      // nchan+1
-    std::vector<int> h_vis_base;       // nchan+1
+    std::vector<int> h_slot_base;      // split-K slots per channel, nchan+1
+    std::vector<int> h_vis_base;       // visibility items per channel, nchan+1
+    std::vector<int> h_ivis_base;      // visibility items per image, nimg+1
+    std::vector<int> h_ichan_base;     // channels per image, nimg+1
+    std::vector<int> h_chan_img;       // image of each channel, nchan
     int n_adj = 0, n_visit = 0;
 
     // device buffers
@@ -140,14 +144,15 @@ struct uvmem_ctx {
     uvm::AdjItem *d_adj = nullptr;
     uvm::VisItem *d_vis = nullptr;
     int *d_slot_base = nullptr, *d_vis_base = nullptr;
+    int *d_ivis_base = nullptr, *d_ichan_base = nullptr, *d_chan_img = nullptr;
     double2 *d_R = nullptr, *d_Vd = nullptr, *d_vpart = nullptr;
     void *d_gpart = nullptr;                    // split-K adjoint partials [slots][Np][Np]: FP64, FP32 (split)
     void *d_bop = nullptr;                      // operand image [C][np][np]
-    void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [C][n][n]
-    double *d_scal = nullptr;                   // [C][NSCAL]
-    double *d_chan = nullptr;                   // [C][CH_N]
-    double *d_ls = nullptr;                     // [2][C][LSS_N] (ping-pong)
-    double *d_ppart = nullptr;                  // [2][C][n_pb][NPART] (ping-pong)
+    void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [nimg][n][n]
+    double *d_scal = nullptr;                   // [nimg][NSCAL]
+    double *d_chan = nullptr;                   // [nimg][CH_N]
+    double *d_ls = nullptr;                     // [2][nimg][LSS_N] (ping-pong)
+    double *d_ppart = nullptr;                  // [2][nimg][n_pb][NPART] (ping-pong)
     double *d_vispart = nullptr;                // [n_visit][NPART]
     int *d_flag = nullptr;                      // [4]: domain flag, ...
     size_t bytes_device = 0;

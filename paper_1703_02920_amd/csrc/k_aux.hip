@@ -80,15 +80,14 @@ __global__ void k_fill(R *__restrict__ x, R value, long long count) {
 // S = sum I ln(I/M) and the domain flag (I <= 0 or NaN).
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, const R *__restrict__ beam,
-                                                   R *__restrict__ bop,
+                                                   R *__restrict__ bop, const int *__restrict__ ichan_base,
                                                    double *__restrict__ ppart,
                                                    int *__restrict__ flag, int n, int np, int n_pb, int pb_len,
                                                    double M, int with_entropy) {
-    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
+    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;   // image plane, pixel block
     const long long npix = (long long)n * n;
     const R *Ic = I + (size_t)c * npix;
-    const R *Ac = beam + (size_t)c * npix;
-    const size_t cb = (size_t)c * np * np;
+    const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
     double s[1] = {0.0};
     int bad = 0;
     for (int r = 0; r < pb_len / NTHR; ++r) {
@@ -96,7 +95,8 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
         if (p >= npix) break;
         const int i = (int)(p / n), j = (int)(p % n);
         const R x = Ic[p];
-        bop[cb + (size_t)i * np + j] = Ac[p] * x;
+        for (int ch = ch0; ch < ch1; ++ch)
+            bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * x;
         if (with_entropy) {
             const double xd = (double)x;
             if (!(xd > 0.0)) bad = 1;
@@ -193,9 +193,10 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
                                               const float2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
-                                              double *__restrict__ vispart, int mode, int with_max) {
+                                              double *__restrict__ vispart, const int *__restrict__ chan_img,
+                                              int mode, int with_max) {
     const VisItem it = items[blockIdx.x];
-    const double alpha = mode == 3 ? scal[(size_t)it.chan * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
+    const double alpha = mode == 3 ? scal[(size_t)chan_img[it.chan] * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
     vis_item(it, blockIdx.x, vpart, n_parts, ztot, vo, w, R, Vd, out, vispart, mode, with_max, alpha);
 }
 
@@ -207,13 +208,14 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
 //         [0] = gt_new . gt_new, [1] = gt_new . gt_old; gt updated in place.
 template <typename R, int RP, typename PT>
 __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, const int *__restrict__ slot_base,
+                                               const int *__restrict__ ichan_base,
                                                const R *__restrict__ beam, const R *__restrict__ I,
                                                R *__restrict__ out, R *__restrict__ gt,
                                                double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
                                                double M, double Mb, double lam, int mode) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
-    const int s0 = slot_base[c], s1 = slot_base[c + 1];
+    const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
     const size_t np2 = (size_t)np * np;
     double acc[2] = {0.0, 0.0};
     // groups of RP pixels per thread; fixed-order sum over the slots with
@@ -228,32 +230,44 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
             const long long pc = okp[r] ? p : 0;
             off[r] = (size_t)(pc / n) * np + (size_t)(pc % n);
         }
-        double Gs[RP];
+        // grad chi^2 = sum over the image's channels of A_ch o (sum of the
+        // channel's slots)
+        double AG[RP];
 #pragma unroll
-        for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
-        int s = s0;
-        for (; s + 8 <= s1; s += 8) {
-            double v[RP][8];
+        for (int r = 0; r < RP; ++r) AG[r] = 0.0;
+        for (int ch = ch0; ch < ch1; ++ch) {
+            const int s0 = slot_base[ch], s1 = slot_base[ch + 1];
+            double Gs[RP];
 #pragma unroll
-            for (int r = 0; r < RP; ++r)
+            for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
+            int s = s0;
+            for (; s + 8 <= s1; s += 8) {
+                double v[RP][8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
+                for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int r = 0; r < RP; ++r)
+                    for (int u = 0; u < 8; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
-        }
-        for (; s < s1; ++s) {
+                for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int r = 0; r < RP; ++r) Gs[r] += (double)gpart[(size_t)s * np2 + off[r]];
+                    for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
+            }
+            for (; s < s1; ++s) {
+#pragma unroll
+                for (int r = 0; r < RP; ++r) Gs[r] += (double)gpart[(size_t)s * np2 + off[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
+                if (okp[r]) AG[r] += (double)beam[(size_t)ch * npix + p] * Gs[r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
             if (!okp[r]) continue;
             const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
-            const double G = Gs[r];
             const size_t q = (size_t)c * npix + p;
-            double gv = (double)beam[q] * G;
+            double gv = AG[r];
             if (mode >= 1) {
                 const double x = (double)I[q];
                 gv += lam * (log(x / M) + 1.0);
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
                                                   R *__restrict__ dir, const R *__restrict__ beam,
-                                                  R *__restrict__ bop,
+                                                  R *__restrict__ bop, const int *__restrict__ ichan_base,
                                                   const double *__restrict__ pp_gtd,
                                                   const double *__restrict__ scal,
                                                   double *__restrict__ chan,
@@ -406,7 +420,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         ch[CH_GTD] = restart ? -gg : gtd[0];
         ch[CH_GG_OLD] = gg;
     }
-    const size_t cb = (size_t)c * np * np;
+    const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
     double amax = INFINITY;
     double acc[2] = {0.0, 0.0};
     for (int r = 0; r < pb_len / NTHR; ++r) {
@@ -420,7 +434,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         d = (double)dr;
         dir[q] = dr;
         const int i = (int)(p / n), j = (int)(p % n);
-        bop[cb + (size_t)i * np + j] = beam[q] * dr;
+        for (int ch = ch0; ch < ch1; ++ch)
+            bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
         const double x = (double)I[q];
         if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
@@ -643,14 +658,15 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
                                                     int n, int n_pb, int pb_len, double M, double Mb, double lam,
                                                     const VisItem *__restrict__ vitems, const float *__restrict__ w,
                                                     double2 *__restrict__ Rv, const double2 *__restrict__ Vd,
-                                                    double *__restrict__ vispart, int n_pixwg, int with_max) {
+                                                    double *__restrict__ vispart, const int *__restrict__ chan_img,
+                                                    int n_pixwg, int with_max) {
     // workgroups past the pixel grid update the residuals of one visibility
     // item each (step 9); every workgroup derives the channel's final alpha
     // from the line-search state itself
     const bool visw = (int)blockIdx.x >= n_pixwg;
     const int vi = (int)blockIdx.x - n_pixwg;
     const VisItem vit = visw ? vitems[vi] : VisItem{};
-    const int c = visw ? vit.chan : (int)blockIdx.x / n_pb, pb = visw ? -1 : (int)blockIdx.x % n_pb;
+    const int c = visw ? chan_img[vit.chan] : (int)blockIdx.x / n_pb, pb = visw ? -1 : (int)blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     __shared__ double st[LSS_N];
     if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
@@ -741,19 +757,20 @@ __global__ void k_copy_hist(const double *__restrict__ scal, const long long *__
 template <typename R> inline R *P(void *p) { return reinterpret_cast<R *>(p); }
 template <typename R> inline const R *CP(const void *p) { return reinterpret_cast<const R *>(p); }
 
-inline int pix_grid(const uvmem_ctx *c) { return c->nchan * c->n_pb; }
+inline int pix_grid(const uvmem_ctx *c) { return c->nimg * c->n_pb; }
 inline double *pp(const uvmem_ctx *c, int buf) {
-    return c->d_ppart + (size_t)buf * c->nchan * c->n_pb * NPART;
+    return c->d_ppart + (size_t)buf * c->nimg * c->n_pb * NPART;
 }
 // The fp16 split adjoint scales its coefficients by the channel's max |w R|,
 // which the visibility pass leaves in slot 2 of its partial records.
 inline int adj_scaled(const uvmem_ctx *c) { return c->prec == UVMEM_FP16X3 ? 1 : 0; }
-inline double *lsb(const uvmem_ctx *c, int buf) { return c->d_ls + (size_t)buf * c->nchan * LSS_N; }
+inline double *lsb(const uvmem_ctx *c, int buf) { return c->d_ls + (size_t)buf * c->nimg * LSS_N; }
 
 template <typename R>
 hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
     hipLaunchKernelGGL(k_prologue<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_beam),
-                       P<R>(c->d_bop), pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->pix_blk, c->M, with_entropy);
+                       P<R>(c->d_bop), c->d_ichan_base, pp(c, 0), c->d_flag, c->n, c->np, c->n_pb, c->pix_blk, c->M,
+                       with_entropy);
     return hipGetLastError();
 }
 
@@ -765,12 +782,12 @@ void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, 
     const PT *gp = static_cast<const PT *>(c->d_gpart);
     if (c->pix_blk >= 4 * NTHR)
         hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
-                           CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
-                           c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n,
+                           c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
     else
         hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
-                           CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n, c->np, c->n_pb,
-                           c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n,
+                           c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
 }
 
 template <typename R>
@@ -791,7 +808,7 @@ template <typename R>
 hipError_t t_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_g),
                        P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
-    hipLaunchKernelGGL(k_chan_cg_init, dim3(c->nchan), dim3(NTHR), 0, st, pp(c, 0), c->n_pb, c->d_scal,
+    hipLaunchKernelGGL(k_chan_cg_init, dim3(c->nimg), dim3(NTHR), 0, st, pp(c, 0), c->n_pb, c->d_scal,
                        c->d_chan);
     return hipGetLastError();
 }
@@ -802,7 +819,7 @@ hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st);
 }  // namespace
 
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st) {
-    const long long count = (long long)c->nchan * c->n * c->n;
+    const long long count = (long long)c->nimg * c->n * c->n;
     const int blocks = (int)std::min<long long>((count + NTHR - 1) / NTHR, 4096);
     if (c->prec == UVMEM_FP64)
         hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(NTHR), 0, st, P<double>(img), value, count);
@@ -819,8 +836,8 @@ hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, 
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st) {
     if (c->n_visit == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
-                       (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart, mode,
-                       adj_scaled(c));
+                       (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart,
+                       c->d_chan_img, mode, adj_scaled(c));
     return hipGetLastError();
 }
 
@@ -828,7 +845,7 @@ hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t 
     if (c->n_visit == 0 || !adj_scaled(c)) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, (const float *)nullptr, const_cast<double2 *>(coef), c->d_Vd,
-                       (double2 *)nullptr, c->d_scal, c->d_vispart, 4, 1);
+                       (double2 *)nullptr, c->d_scal, c->d_vispart, c->d_chan_img, 4, 1);
     return hipGetLastError();
 }
 
@@ -837,7 +854,7 @@ hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, h
 }
 
 hipError_t launch_chan_phi(const uvmem_ctx *c, double *user_scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_chan_phi, dim3(c->nchan), dim3(NTHR), 0, st, c->d_vispart, c->d_vis_base, pp(c, 0),
+    hipLaunchKernelGGL(k_chan_phi, dim3(c->nimg), dim3(NTHR), 0, st, c->d_vispart, c->d_ivis_base, pp(c, 0),
                        c->n_pb, c->lam, c->d_scal, user_scal);
     return hipGetLastError();
 }
@@ -848,7 +865,7 @@ hipError_t launch_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st)
 
 hipError_t launch_copy_scal(const uvmem_ctx *c, double *, long long *ctr, hipStream_t st) {
     hipLaunchKernelGGL(k_copy_hist, dim3(1), dim3(NTHR), 0, st, c->d_scal,
-                       reinterpret_cast<const long long *>(c->d_hist_ptr), ctr, c->nchan * UVMEM_NSCAL);
+                       reinterpret_cast<const long long *>(c->d_hist_ptr), ctr, c->nimg * UVMEM_NSCAL);
     return hipGetLastError();
 }
 
@@ -856,14 +873,14 @@ namespace {
 template <typename R>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
     hipError_t e;
-    const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
+    const dim3 gp(pix_grid(c)), gc(c->nimg), blk(NTHR);
     // 1. direction update and projection; partial gt.d
     hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
                        c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
     // 2-3. restart test, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
     hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       CP<R>(c->d_beam), P<R>(c->d_bop), pp(c, 0), c->d_scal, c->d_chan, pp(c, 1), c->n,
-                       c->np, c->n_pb, c->pix_blk, c->M, c->Mb);
+                       CP<R>(c->d_beam), P<R>(c->d_bop), c->d_ichan_base, pp(c, 0), c->d_scal, c->d_chan, pp(c, 1),
+                       c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. Vd = F(d)
     return hipSuccess;
@@ -887,14 +904,14 @@ hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t
 namespace {
 template <typename R>
 hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
-    const dim3 gp(pix_grid(c)), gc(c->nchan), blk(NTHR);
+    const dim3 gp(pix_grid(c)), gc(c->nimg), blk(NTHR);
     if (phase == 0) return t_cg_step<R>(c, I, user, st);
     if (phase == 1) {
         // 5. Vd and the quadratic coefficients a, b of chi^2 along d
         if (c->n_visit)
             hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, 2, 0);
+                               c->d_scal, c->d_vispart, c->d_chan_img, 2, 0);
         // 6-7. line search: pass 0 initialises the state (from the visibility
         // partials and the direction pass's partials in pp[1]); pass t > 0
         // advances S^t-1 (ls[t%2]) with P^t-1 (pp[(t+1)%2]); every pass
@@ -903,7 +920,7 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         for (int t = 0; t < L; ++t) {
             hipLaunchKernelGGL(k_ls_step<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_dir), lsb(c, t % 2),
                                lsb(c, (t + 1) % 2), pp(c, (t + 1) % 2), pp(c, t % 2), c->d_vispart,
-                               c->d_vis_base, c->d_chan, c->n, c->n_pb, c->pix_blk, c->M, c->lam, t == 0 ? 1 : 0);
+                               c->d_ivis_base, c->d_chan, c->n, c->n_pb, c->pix_blk, c->M, c->lam, t == 0 ? 1 : 0);
         }
         const int last = (L - 1) % 2;   // pp buffer holding the last partials
         // 8-9. one launch: the final update of the step, I <- max(I + alpha d, M)
@@ -912,14 +929,14 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         hipLaunchKernelGGL(k_cg_update<R>, dim3(pix_grid(c) + c->n_visit), blk, 0, st, P<R>(I), CP<R>(c->d_dir),
                            lsb(c, 1 - last), pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n,
                            c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, c->d_vis, c->d_w, c->d_R, c->d_Vd,
-                           c->d_vispart, pix_grid(c), adj_scaled(c));
+                           c->d_vispart, c->d_chan_img, pix_grid(c), adj_scaled(c));
         return hipGetLastError();
     }
     // 11. gradient at the new point, projected gradient, PR partials
     const int last = (c->ls_steps - 1) % 2;
     grad_launch<R>(c, I, c->d_g, pp(c, last), 2, st);
     // 12. beta and scalars
-    hipLaunchKernelGGL(k_chan_beta, gc, blk, 0, st, c->d_vispart, c->d_vis_base, pp(c, 1 - last), pp(c, last),
+    hipLaunchKernelGGL(k_chan_beta, gc, blk, 0, st, c->d_vispart, c->d_ivis_base, pp(c, 1 - last), pp(c, last),
                        c->n_pb, c->lam, c->d_scal, c->d_chan, user);
     return hipGetLastError();
 }

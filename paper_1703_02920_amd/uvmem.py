@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libuvmem.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ESTATE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+MODES = {"cube": 0, "shared": 1}
 NSCAL = 8
 S_PHI, S_CHI2, S_S, S_ALPHA, S_BETA, S_GNORM2, S_ALPHA_MAX, S_ITER = range(8)
 
@@ -94,20 +95,29 @@ def _ptr(x) -> Optional[int]:
 
 
 class Context:
-    """One imaging problem: image side n, n_chan independent channels."""
+    """One imaging problem: image side n and n_chan channels.  mode "cube"
+    gives every channel its own image (n_img = n_chan independent problems);
+    mode "shared" fits one image to all channels (n_img = 1, chi^2 summed over
+    the channels, each with its own beam)."""
 
     def __init__(self, n: int, n_chan: int = 1, precision: str = "fp32",
-                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
+                 mode: str = "cube"):
+        if mode not in MODES:
+            raise ValueError("mode must be one of %s" % sorted(MODES))
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
         self._lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("uvmem needs a GPU")
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.n, self.n_chan, self.precision = int(n), int(n_chan), precision
+        self.n, self.n_chan, self.precision, self.mode = int(n), int(n_chan), precision, mode
+        self.n_img = self.n_chan if mode == "cube" else 1
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         h = ctypes.c_void_p()
-        code = self._lib.uvmem_create(ctypes.byref(h), self.n, self.n_chan, 0, PRECISIONS[precision],
+        code = self._lib.uvmem_create(ctypes.byref(h), self.n, self.n_chan, MODES[mode], PRECISIONS[precision],
                                       ctypes.c_void_p(self.stream.cuda_stream))
         if code != OK:
             raise UvmemError(code, self._lib.uvmem_strerror(code).decode())
@@ -171,9 +181,9 @@ class Context:
         return self
 
     @classmethod
-    def from_dataset(cls, ds, precision: str = "fp32", **kw) -> "Context":
+    def from_dataset(cls, ds, precision: str = "fp32", mode: str = "cube", **kw) -> "Context":
         """Context for a synthetic data set (paper_1703_02920_amd.synth)."""
-        ctx = cls(ds.n, ds.n_chan, precision, **kw)
+        ctx = cls(ds.n, ds.n_chan, precision, mode=mode, **kw)
         for c, ch in enumerate(ds.channels):
             ctx.set_uv(c, ch.u, ch.v, ds.cell)
             ctx.set_vis(c, ch.vis)
@@ -184,7 +194,8 @@ class Context:
 
     def info(self) -> dict:
         keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_wgs",
-                "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block"]
+                "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block",
+                "n_img"]
         out = (ctypes.c_int64 * len(keys))()
         self._call("uvmem_info", out, len(keys))
         return dict(zip(keys, [int(x) for x in out]))
@@ -196,7 +207,7 @@ class Context:
 
     # ------------------------------------------------------------ tensors
     def image(self, fill: Optional[float] = None) -> torch.Tensor:
-        t = torch.empty((self.n_chan, self.n, self.n), dtype=self.dtype, device=self.device)
+        t = torch.empty((self.n_img, self.n, self.n), dtype=self.dtype, device=self.device)
         if fill is not None:
             t.fill_(fill)
         return t
@@ -204,12 +215,12 @@ class Context:
     def _img(self, I: torch.Tensor) -> torch.Tensor:
         if I.dtype != self.dtype or I.device != self.device or not I.is_contiguous():
             raise ValueError("image must be a contiguous %s tensor on %s" % (self.dtype, self.device))
-        if I.numel() != self.n_chan * self.n * self.n:
-            raise ValueError("image must have n_chan * n * n elements")
+        if I.numel() != self.n_img * self.n * self.n:
+            raise ValueError("image must have n_img * n * n elements")
         return I
 
     def scalars(self) -> torch.Tensor:
-        return torch.zeros((self.n_chan, NSCAL), dtype=torch.float64, device=self.device)
+        return torch.zeros((self.n_img, NSCAL), dtype=torch.float64, device=self.device)
 
     # ------------------------------------------------------------ hot path
     def phi_and_grad(self, I: torch.Tensor, grad: Optional[torch.Tensor] = None,
@@ -251,7 +262,7 @@ class Context:
     def cg_run(self, I: torch.Tensor, iters: int, graph: bool = True,
                hist: Optional[torch.Tensor] = None) -> torch.Tensor:
         if hist is None:
-            hist = torch.zeros((max(iters, 1), self.n_chan, NSCAL), dtype=torch.float64, device=self.device)
+            hist = torch.zeros((max(iters, 1), self.n_img, NSCAL), dtype=torch.float64, device=self.device)
         self._call("uvmem_cg_run", _ptr(self._img(I)), int(iters), _ptr(hist), 1 if graph else 0)
         return hist[:iters]
 
@@ -280,7 +291,7 @@ class Context:
 
 
 class PhiFunction(torch.autograd.Function):
-    """Phi(I) summed over channels as a differentiable torch function; the
+    """Phi(I) summed over the images as a differentiable torch function; the
     backward pass returns g * grad Phi computed by the same HIP evaluation."""
 
     @staticmethod

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from oracle import cg as ocg
-from _common import TOL, Problem, flush, rel, synth
+from _common import CG_TOL, TOL, Problem, flush, rel, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -21,20 +21,6 @@ def _oracle_cg(prob, c, iters, I0):
     ch = prob.chans[c]
     p = ocg.Problem(prob.n, prob.cell, ch["u"], ch["v"], ch["vis"], ch["w"], prob.beam(c), prob.M, prob.lam)
     return ocg.projected_cg(p, iters, I0=I0)
-
-
-# CG trajectory tolerances: FP64 rounding and the fixed-count line search
-# leave ~1e-10 differences that the iteration propagates; the FP32 path
-# carries its 1e-7-level evaluation error through the same iteration.  On
-# this problem every step after the first ends on alpha_max (one more pixel
-# reaches the floor), and alpha_max = min (I - M)/(-d) is decided by pixels
-# just above the floor: the split path's ~1e-5 evaluation error changes
-# which pixel binds, so its trajectory is held to the first step tightly and
-# to the whole run and final image loosely.
-CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7, "first": 1e-12},
-          "fp32": {"phi": 1e-5, "img": 1e-3, "first": 1e-6},
-          "bf16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4},
-          "fp16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4}}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])

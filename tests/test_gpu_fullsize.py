@@ -208,3 +208,64 @@ def test_extreme_image_sizes(n):
     pix = np.arange(0, n * n, max(1, (n * n) // 97))
     ref = prob.oracle_adjoint(0, coef, pix=pix)
     assert rel(G.ravel()[pix], ref) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_c4_shared_sampled_and_point_source(prec):
+    """The 64-channel 256^2 workload fitted with ONE image (Eq. chi2-multi):
+    model visibilities at seeded samples of four channels, the adjoint summed
+    over all 64 channels at seeded pixels, and the point-source property
+    (chi^2 is the sum of the channels' closed forms; grad chi^2 the sum of
+    their adjoints)."""
+    _cuda()
+    flush(f"c4 shared image 64 channels sampled parity {prec}")
+    ds = _ds(4)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context(prec, mode="shared")
+    rng = np.random.default_rng(2004)
+    img = synth.eval_images(ds, "P3")[:1].astype(np.float32)
+    V = ctx.forward(torch.tensor(img, device="cuda")).cpu().numpy()
+    offs = prob.offsets()
+    # the bar applies to the relative l2 error of the whole V^m vector; it is
+    # estimated on 160 seeded visibilities from each of four channels pooled
+    got, refs, per = [], [], []
+    for ch in (0, 17, 40, 63):
+        nv = len(prob.chans[ch]["u"])
+        idx = np.sort(rng.choice(nv, size=min(160, nv), replace=False))
+        ref = oracle.forward_sel(ds.n, ds.cell, idx, prob.chans[ch]["u"], prob.chans[ch]["v"], prob.beam(ch),
+                                 img[0].astype(np.float64))
+        got.append(V[offs[ch] + idx])
+        refs.append(ref)
+        per.append(rel(got[-1], ref))
+    pooled = rel(np.concatenate(got), np.concatenate(refs))
+    flush(f"  forward, sampled visibilities: pooled rel err {pooled:.2e}, per channel "
+          + " ".join(f"{x:.2e}" for x in per))
+    assert pooled < TOL[prec]
+    coef = np.concatenate([prob.chans[ch]["w"].astype(np.float64) * prob.chans[ch]["vis"].astype(np.complex128)
+                           for ch in range(prob.n_chan)])
+    G = ctx.adjoint(torch.tensor(coef, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    pix = np.sort(rng.choice(ds.n * ds.n, size=32, replace=False))
+    gref = sum(prob.oracle_adjoint(ch, coef[offs[ch]:offs[ch + 1]], pix=pix) for ch in range(prob.n_chan))
+    e_a = rel(G[0].ravel()[pix], gref)
+    flush(f"  adjoint summed over 64 channels, sampled pixels: rel err {e_a:.2e}")
+    assert e_a < TOL[prec]
+    F = 0.75
+    pimg = np.full((1, ds.n, ds.n), 1e-30, dtype=np.float32)
+    pimg[0, ds.n // 2, ds.n // 2] = F
+    scal, grad = ctx.phi_and_grad(torch.tensor(pimg, device="cuda"))
+    scal, grad = scal.cpu().numpy(), grad.cpu().numpy()
+    x2 = 0.0
+    gref = np.zeros(len(pix))
+    for ch in range(prob.n_chan):
+        vo = prob.chans[ch]["vis"].astype(np.complex128)
+        w = prob.chans[ch]["w"].astype(np.float64)
+        if len(vo) == 0:
+            continue
+        x, R = oracle.chi2(np.full(len(vo), F + 0j), vo, w)
+        x2 += x
+        gref += prob.oracle_adjoint(ch, w * R, pix=pix)
+    lam_part = ds.lam * (np.log(pimg[0].ravel()[pix].astype(np.float64) / ds.prior_m) + 1.0)
+    e_x2 = abs(scal[0, 1] - x2) / x2
+    e_g = rel(grad[0].ravel()[pix] - lam_part, gref)
+    flush(f"  point-source property: chi2 rel err {e_x2:.2e}, grad chi2 rel err {e_g:.2e}")
+    assert e_x2 < TOL[prec] and e_g < TOL[prec]
