@@ -159,10 +159,12 @@ def eval_error(ds, ctx_a, ctx_b):
             "grad": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb))}
 
 
-def eval_sweep(configs, precs, reps=20, warmup=3):
+def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
     """M1 per configuration and precision: median time of one Phi + grad Phi
     evaluation (forward, chi^2, adjoint, entropy, combine) at the P3 image,
-    timed with events on the context's stream."""
+    timed with events on the context's stream.  mode "shared" fits the first
+    P3 plane to every channel (one image, Eq. chi2-multi); the DFT work per
+    channel is the same as in cube mode."""
     import numpy as np
     import torch
     from paper_1703_02920_amd import synth
@@ -171,10 +173,12 @@ def eval_sweep(configs, precs, reps=20, warmup=3):
     for c in configs:
         ds = synth.make_config(c)
         img_np = synth.eval_images(ds, "P3")
+        if mode == "shared":
+            img_np = img_np[:1]
         for prec in precs:
             if prec == "fp64" and ds.n > 512:
                 continue
-            ctx = Context.from_dataset(ds, prec)
+            ctx = Context.from_dataset(ds, prec, mode=mode)
             img = torch.tensor(img_np, dtype=ctx.dtype, device=ctx.device)
             scal, grad = ctx.scalars(), torch.empty_like(img)
             for _ in range(warmup):
@@ -190,7 +194,7 @@ def eval_sweep(configs, precs, reps=20, warmup=3):
                 ts.append(e0.elapsed_time(e1))
             ctx.check()
             ms = float(np.median(ts))
-            rows.append({"config": f"c{c}", "precision": prec, "ms_per_eval": ms,
+            rows.append({"config": f"c{c}", "mode": mode, "precision": prec, "ms_per_eval": ms,
                          "vis_pixel_evals_per_s": ds.pairs / (ms / 1e3),
                          "algorithmic_tflops": 8.0 * ds.pairs / (ms / 1e3) / 1e12,
                          "frac_of_peak": 8.0 * ds.pairs / (ms / 1e3) / 1e12 / PEAK[prec]})
@@ -199,7 +203,7 @@ def eval_sweep(configs, precs, reps=20, warmup=3):
     return rows
 
 
-def cg_compare(c, precs, iters=None):
+def cg_compare(c, precs, iters=None, mode="cube"):
     """M2: T graph-replayed projected-CG iterations from I = M in each
     precision; iterations/s, and the relative error of Phi_T and of the final
     image against the FP64 trajectory (the FP64 path is held to 1e-12 of the
@@ -213,7 +217,7 @@ def cg_compare(c, precs, iters=None):
     res = {}
     ref = None
     for prec in ["fp64"] + [p for p in precs if p != "fp64"]:
-        ctx = Context.from_dataset(ds, prec)
+        ctx = Context.from_dataset(ds, prec, mode=mode)
         I = ctx.image()
         ctx.cg_init(I, init_to_floor=True)
         ctx.cg_run(I, 1, graph=True)          # capture (and one iteration)
@@ -228,7 +232,7 @@ def cg_compare(c, precs, iters=None):
         ms = e0.elapsed_time(e1)
         phi = hist[-1, :, 0].double().sum().item()
         img = I.double().cpu().numpy()
-        row = {"config": f"c{c}", "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
+        row = {"config": f"c{c}", "mode": mode, "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
                "vis_pixel_evals_per_s": ds.pairs * T / (ms / 1e3), "phi_T": phi}
         if prec == "fp64":
             ref = (phi, img)
@@ -255,6 +259,9 @@ def main():
                     help="only time single Phi + grad evaluations on these configurations (e.g. 1,2,3,4,5)")
     ap.add_argument("--cg-compare", type=int, default=0, metavar="CONFIG",
                     help="only run the configuration's CG iterations in every precision vs FP64")
+    ap.add_argument("--mode", default="cube", choices=["cube", "shared"],
+                    help="image model of --eval-sweep and --cg-compare: an image per channel, or one image "
+                         "fitted to every channel")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,10 +271,11 @@ def main():
 
     import torch
     if args.eval_sweep:
-        eval_sweep([int(x) for x in args.eval_sweep.split(",")], ["fp64", "fp32", "bf16x3", "fp16x3"])
+        eval_sweep([int(x) for x in args.eval_sweep.split(",")], ["fp64", "fp32", "bf16x3", "fp16x3"],
+                   mode=args.mode)
         return
     if args.cg_compare:
-        cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"])
+        cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"], mode=args.mode)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
