@@ -85,6 +85,28 @@ typedef enum uvmem_mode {
                             Re F_c^H (w_c R_c), S and the CG over the one image */
 } uvmem_mode;
 
+/* Forward model of the objective.  UVMEM_FWD_DFT (the default) is the exact
+ * direct DFT above.  UVMEM_FWD_GRIDDED is the paper's GPU approximation
+ * (Sec. 2.4 items 1-4, Alg. 1): B_c = A_c o I zero-padded to an L x L grid,
+ * L = oversample * N; its 2-D DFT on the uniform grid du = 1/(L cell);
+ * modulation by e^{+2 pi i (u x_c + v y_c)} (phase centre at pixel N/2);
+ * then bilinear interpolation at (u_k/du, v_k/du), wrapping modulo L.  The
+ * transforms run in FP64 for UVMEM_FP64 and in FP32 for every other
+ * precision.  The chi^2 gradient is chosen by uvmem_gradient_model. */
+typedef enum uvmem_forward_model {
+    UVMEM_FWD_DFT = 0,
+    UVMEM_FWD_GRIDDED = 1
+} uvmem_forward_model;
+
+typedef enum uvmem_gradient_model {
+    UVMEM_GRAD_ADJOINT = 0,  /* the exact adjoint of the forward model in use:
+                                grad Phi is the gradient of Phi               */
+    UVMEM_GRAD_DFT = 1       /* Eq. chi2gradient with the exact DFT at the
+                                gridded residuals (the paper's combination;
+                                with the gridded model Phi and grad Phi then
+                                belong to different operators)                */
+} uvmem_gradient_model;
+
 /* Per-image scalar slots, FP64, layout [n_img][UVMEM_NSCAL]. */
 enum {
     UVMEM_S_PHI = 0,     /* Phi = chi^2 + lambda S                            */
@@ -120,6 +142,16 @@ int uvmem_set_weights(uvmem_ctx *ctx, int chan, const float *w);
 int uvmem_set_beam(uvmem_ctx *ctx, int chan, double fwhm_rad);
 /* General attenuation image A for the channel: float[N][N]. */
 int uvmem_set_beam_image(uvmem_ctx *ctx, int chan, const float *A);
+/* Choose the forward model (uvmem_forward_model) before finalize.  For
+ * UVMEM_FWD_GRIDDED, oversample >= 1 and L = oversample * N must be a power
+ * of two in [16, 8192] ([16, 4096] for UVMEM_FP64); grad is a
+ * uvmem_gradient_model and also selects what uvmem_adjoint computes.  The
+ * gridded model sorts the visibilities by grid cell at finalize (so the
+ * adjoint's sums have a fixed order) and holds per channel an L x L complex
+ * spectrum, an L x N row-pass buffer and L^2 + 1 cell offsets; it needs fewer
+ * than 2^31 visibilities.  For UVMEM_FWD_DFT, oversample and grad are
+ * ignored.  UVMEM_EINVAL on bad values, UVMEM_ESTATE after finalize. */
+int uvmem_set_forward_model(uvmem_ctx *ctx, int model, int oversample, int grad);
 /* Image floor M > 0 (the paper's G, Eq. minproblem) and entropy weight
  * lambda >= 0 (Eq. phi2). */
 int uvmem_set_prior(uvmem_ctx *ctx, double M, double lambda);
@@ -137,7 +169,8 @@ int uvmem_phi_and_grad(uvmem_ctx *ctx, const void *I_dev, void *grad_dev, double
 int uvmem_forward(uvmem_ctx *ctx, const void *I_dev, void *vis_dev);
 /* Adjoint A o Re F^H c of complex coefficients c (double[sum Z][2], e.g. the
  * weighted residual w R): img_dev is [n_img][N][N] (shared mode: the sum
- * over channels). */
+ * over channels).  F is the exact DFT, or the gridded model when that model
+ * is in use with UVMEM_GRAD_ADJOINT. */
 int uvmem_adjoint(uvmem_ctx *ctx, const void *coef_dev, void *img_dev);
 /* Copy the current residuals R = V^m - V^o (double[sum Z][2]) to res_dev. */
 int uvmem_get_residual(uvmem_ctx *ctx, void *res_dev);
@@ -176,9 +209,10 @@ int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *coun
  * Np, channels, precision, total visibilities, forward image blocks, adjoint
  * tile side, adjoint split-K slots, forward workgroups, adjoint workgroups,
  * visibility items, device bytes held, pixel blocks per channel, pixels per
- * pixel block, visibilities per visibility item, image planes n_img.  uvmem_chan_range
- * gives a channel's offset into the concatenated visibility arrays and its
- * count. */
+ * pixel block, visibilities per visibility item, image planes n_img, forward
+ * model, gridded-model grid side L (0 for the DFT), gradient model.
+ * uvmem_chan_range gives a channel's offset into the concatenated
+ * visibility arrays and its count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);
 int uvmem_chan_range(const uvmem_ctx *ctx, int chan, int64_t *offset, int64_t *nvis);
 

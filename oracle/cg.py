@@ -101,6 +101,29 @@ class SharedProblem(Problem):
         return out
 
 
+class GriddedProblem(Problem):
+    """One channel with the gridded forward model of Sec. 2.4 / Alg. 1
+    (oracle.gridded) on a grid oversample times finer than the image.
+    grad="adjoint" uses that model's exact adjoint; grad="dft" the exact-DFT
+    gradient of Eq. chi2gradient at the gridded residuals (the paper's
+    combination)."""
+
+    def __init__(self, n, cell, u, v, vis, w, A, M, lam, oversample=1, grad="adjoint"):
+        super().__init__(n, cell, u, v, vis, w, A, M, lam)
+        self.oversample = int(oversample)
+        self.grad = grad
+
+    def F(self, img):
+        from .gridded import gridded_forward
+        return gridded_forward(self.n, self.cell, self.u, self.v, self.A, img, self.oversample)
+
+    def FH(self, c):
+        if self.grad == "dft":
+            return adjoint(self.n, self.cell, self.u, self.v, self.A, c)
+        from .gridded import gridded_adjoint
+        return gridded_adjoint(self.n, self.cell, self.u, self.v, self.A, c, self.oversample)
+
+
 def line_search(a, b, I, d, M, lam, alpha_max, max_steps=100, rtol=1e-13):
     """Exact minimiser of phi on [0, alpha_max] (steps 6-7)."""
     def dphi(al):

@@ -74,7 +74,8 @@ void free_all(uvmem_ctx *c) {
                     c->d_slot_base, c->d_vis_base, c->d_ivis_base, c->d_ichan_base, c->d_chan_img, c->d_R,
                     c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
-                    c->d_flag, c->d_hist_ptr, c->d_iter_ctr};
+                    c->d_flag, c->d_hist_ptr, c->d_iter_ctr, c->d_gtw, c->d_gx1, c->d_ggrid, c->d_gcell,
+                    c->d_gperm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -176,7 +177,7 @@ int build_layout(uvmem_ctx *c) {
     else { c->ib_rows = 64; c->jb_cols = 64; }
     c->n_ib = c->np / c->ib_rows;
     c->n_jb = c->np / c->jb_cols;
-    c->n_fparts = c->n_ib * c->n_jb;
+    c->n_fparts = c->fwd_model == UVMEM_FWD_GRIDDED ? 1 : c->n_ib * c->n_jb;
     // adjoint pixel tile: 256 x 256 for the split kernel where the padded
     // side allows (halves its table work per product), else 128 x 128
     // (FP32, split), 64 x 64 (FP64)
@@ -256,6 +257,31 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     c->has_w.assign(n_chan, 0);
     c->has_beam.assign(n_chan, 0);
     *out = c;
+    return UVMEM_OK;
+}
+
+int uvmem_set_forward_model(uvmem_ctx *c, int model, int oversample, int grad) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_forward_model after finalize");
+    if (grad != UVMEM_GRAD_ADJOINT && grad != UVMEM_GRAD_DFT) return fail(c, UVMEM_EINVAL, "bad gradient model %d", grad);
+    if (model == UVMEM_FWD_DFT) {
+        c->fwd_model = model;
+        c->grad_model = UVMEM_GRAD_ADJOINT;
+        c->grid_os = 1;
+        c->grid_lg = 0;
+        return UVMEM_OK;
+    }
+    if (model != UVMEM_FWD_GRIDDED) return fail(c, UVMEM_EINVAL, "bad forward model %d", model);
+    const int64_t L = (int64_t)oversample * c->n;
+    const int64_t lmax = c->prec == UVMEM_FP64 ? 4096 : 8192;
+    if (oversample < 1 || L < 16 || L > lmax || (L & (L - 1)) != 0)
+        return fail(c, UVMEM_EINVAL, "gridded model needs oversample * N a power of two in [16, %lld] (got %lld)",
+                    (long long)lmax, (long long)L);
+    c->fwd_model = model;
+    c->grad_model = grad;
+    c->grid_os = oversample;
+    c->grid_lg = 0;
+    while ((1LL << c->grid_lg) < L) ++c->grid_lg;
     return UVMEM_OK;
 }
 
@@ -383,6 +409,15 @@ int uvmem_finalize(uvmem_ctx *c) {
         if (!c->has_beam[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no beam", ch);
     }
     if (!c->prior_set) return fail(c, UVMEM_ESTATE, "prior not set");
+    if (c->fwd_model == UVMEM_FWD_GRIDDED) {
+        int64_t z = 0;
+        for (int ch = 0; ch < C; ++ch) z += c->nvis[ch];
+        const int64_t L = (int64_t)1 << c->grid_lg;
+        if (z > (int64_t)INT32_MAX - 1) return fail(c, UVMEM_EINVAL, "gridded model: more than 2^31 visibilities");
+        if ((int64_t)C * (L * L + 1) > ((int64_t)1 << 30))
+            return fail(c, UVMEM_ENOMEM, "gridded model: cell tables of %d channels x %lld^2 cells too large", C,
+                        (long long)L);
+    }
     HIPCHK(c, hipSetDevice(c->device));
     build_layout(c);
     const int n = c->n, np = c->np;
@@ -429,6 +464,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     });
     int64_t klen = adj_klen((int64_t)adj_slots * adj_m);
     if (const char *env = std::getenv("UVMEM_ADJ_WGS")) klen = adj_klen(std::max(1L, std::atol(env)));
+    // the gridded model's own adjoint writes one plane per channel
+    const bool grid_adj = c->fwd_model == UVMEM_FWD_GRIDDED && c->grad_model == UVMEM_GRAD_ADJOINT;
     int slot = 0;
     for (int ch = 0; ch < C; ++ch) {
         const int64_t b = c->off[ch], e = c->off[ch + 1];
@@ -436,6 +473,10 @@ int uvmem_finalize(uvmem_ctx *c) {
         for (int64_t k = b; k < e; k += c->vis_blk)
             vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + c->vis_blk, e)});
         c->h_slot_base[ch] = slot;
+        if (grid_adj) {
+            ++slot;
+            continue;
+        }
         int64_t len;
         chunks_of(e - b, klen, len);
         for (int64_t k = b; k < e; k += len, ++slot)
@@ -454,7 +495,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     // g_c = ceil(Z_c / L) for the per-workgroup visibility count L chosen by
     // the same simulation
     std::vector<FwdPItem> fwdp;
-    if (c->ztot > 0) {
+    if (c->ztot > 0 && c->fwd_model == UVMEM_FWD_DFT) {
         const int nblk = c->n_ib * c->n_jb;
         constexpr double FWD_OVERHEAD = 256.0;   // image-block staging, in visibilities
         auto shares = [&](int64_t wgs, int ch) {
@@ -515,6 +556,53 @@ int uvmem_finalize(uvmem_ctx *c) {
             w[o + k] = c->hw[ch][k];
         }
     }
+    // ---- gridded model: twiddles (FP64, rounded to the transform type) and
+    // the visibilities sorted by grid cell (counting sort per channel, stable,
+    // so each cell keeps increasing visibility order).  The cell of a
+    // visibility is computed exactly as the kernels do: floor(a L), mod L.
+    const bool gridded = c->fwd_model == UVMEM_FWD_GRIDDED;
+    const int GL = gridded ? 1 << c->grid_lg : 0;
+    const size_t gcells = (size_t)GL * GL;
+    std::vector<char> gtw;
+    std::vector<int> gcell, gperm;
+    if (gridded) {
+        const size_t csz = 2 * rs;
+        gtw.resize((size_t)(GL / 2) * csz);
+        for (int k = 0; k < GL / 2; ++k) {
+            const double ang = -2.0 * M_PI * (double)k / (double)GL;
+            const double re = std::cos(ang), im = std::sin(ang);
+            if (rs == 8) {
+                reinterpret_cast<double *>(gtw.data())[2 * k] = re;
+                reinterpret_cast<double *>(gtw.data())[2 * k + 1] = im;
+            } else {
+                reinterpret_cast<float *>(gtw.data())[2 * k] = (float)re;
+                reinterpret_cast<float *>(gtw.data())[2 * k + 1] = (float)im;
+            }
+        }
+        gcell.assign((size_t)C * (gcells + 1), 0);
+        gperm.assign(c->ztot, 0);
+        std::vector<int> cellof(c->ztot);
+        for (int ch = 0; ch < C; ++ch) {
+            int *cs = gcell.data() + (size_t)ch * (gcells + 1);
+            std::vector<int> cnt(gcells, 0);
+            for (int64_t k = c->off[ch]; k < c->off[ch + 1]; ++k) {
+                const long long px = (long long)std::floor(a[k] * (double)GL);
+                const long long py = (long long)std::floor(bb[k] * (double)GL);
+                const int cell = (int)((px & (GL - 1)) * GL + (py & (GL - 1)));
+                cellof[k] = cell;
+                ++cnt[cell];
+            }
+            int64_t pos = c->off[ch];
+            for (size_t t = 0; t < gcells; ++t) {
+                cs[t] = (int)pos;
+                pos += cnt[t];
+            }
+            cs[gcells] = (int)pos;
+            std::vector<int> fill(cs, cs + gcells);
+            for (int64_t k = c->off[ch]; k < c->off[ch + 1]; ++k) gperm[fill[cellof[k]]++] = (int)k;
+        }
+    }
+
     std::vector<char> beam(C * npix * rs);
     for (int ch = 0; ch < C; ++ch) {
         for (size_t p = 0; p < npix; ++p) {
@@ -563,6 +651,13 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_flag, 4));
     ok(dalloc(c, &c->d_hist_ptr, 1));
     ok(dalloc(c, &c->d_iter_ctr, 1));
+    if (gridded) {
+        ok(dalloc(c, (char **)&c->d_gtw, gtw.size()));
+        ok(dalloc(c, (char **)&c->d_gx1, (size_t)C * n * GL * 2 * rs));
+        ok(dalloc(c, (char **)&c->d_ggrid, (size_t)C * gcells * 2 * rs));
+        ok(dalloc(c, &c->d_gcell, gcell.size()));
+        ok(dalloc(c, &c->d_gperm, gperm.size()));
+    }
     if (e != hipSuccess) {
         free_all(c);
         c->d_a = nullptr;
@@ -586,6 +681,11 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_ivis_base, c->h_ivis_base.data(), (IMG + 1) * sizeof(int));
     up(c->d_ichan_base, c->h_ichan_base.data(), (IMG + 1) * sizeof(int));
     up(c->d_chan_img, c->h_chan_img.data(), C * sizeof(int));
+    if (gridded) {
+        up(c->d_gtw, gtw.data(), gtw.size());
+        up(c->d_gcell, gcell.data(), gcell.size() * sizeof(int));
+        up(c->d_gperm, gperm.data(), gperm.size() * sizeof(int));
+    }
     if (e != hipSuccess) return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
     HIPCHK(c, hipDeviceSynchronize());
     // release host staging
@@ -719,9 +819,10 @@ namespace {
 struct StateHeader {
     uint64_t magic;
     int32_t n, nchan, prec, mode;
+    int32_t fwd_model, grid_lg, grad_model, pad;
     int64_t ztot;
 };
-const uint64_t STATE_MAGIC = 0x31534d454d5655ull;  // "UVMEMS1"
+const uint64_t STATE_MAGIC = 0x32534d454d5655ull;  // "UVMEMS2"
 }  // namespace
 
 int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {
@@ -736,7 +837,7 @@ int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {
     if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "no CG state");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     char *p = (char *)blob;
-    StateHeader h{STATE_MAGIC, c->n, c->nchan, c->prec, c->mode, c->ztot};
+    StateHeader h{STATE_MAGIC, c->n, c->nchan, c->prec, c->mode, c->fwd_model, c->grid_lg, c->grad_model, 0, c->ztot};
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
     HIPCHK(c, hipMemcpy(p, c->d_dir, img, hipMemcpyDeviceToHost)); p += img;
@@ -763,6 +864,7 @@ int uvmem_cg_set_state(uvmem_ctx *c, const void *blob, size_t bytes) {
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
     if (h.magic != STATE_MAGIC || h.n != c->n || h.nchan != c->nchan || h.prec != c->prec || h.mode != c->mode ||
+        h.fwd_model != c->fwd_model || h.grid_lg != c->grid_lg || h.grad_model != c->grad_model ||
         h.ztot != c->ztot)
         return fail(c, UVMEM_EINVAL, "state blob does not match this context");
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -823,7 +925,8 @@ int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     if (!c || !out) return UVMEM_EINVAL;
     const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
                             c->n_fwdp, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
-                            c->vis_blk, c->nimg};
+                            c->vis_blk, c->nimg, c->fwd_model,
+                            c->fwd_model == UVMEM_FWD_GRIDDED ? (int64_t)1 << c->grid_lg : 0, c->grad_model};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
     return UVMEM_OK;

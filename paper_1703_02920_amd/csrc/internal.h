@@ -98,6 +98,10 @@ enum {
 struct uvmem_ctx {
     int n = 0, np = 0, nchan = 0, mode = 0, prec = 0;
     int nimg = 0;                      // image planes: nchan (cube) or 1 (shared)
+    int fwd_model = 0;                 // UVMEM_FWD_DFT or UVMEM_FWD_GRIDDED
+    int grad_model = 0;                // UVMEM_GRAD_ADJOINT or UVMEM_GRAD_DFT
+    int grid_os = 1;                   // gridded model: Fourier grid side / N
+    int grid_lg = 0;                   // gridded model: log2 of the grid side
     hipStream_t stream = nullptr;
     int device = 0;
     double cell = 0.0;
@@ -155,6 +159,12 @@ struct uvmem_ctx {
     double *d_ppart = nullptr;                  // [2][nimg][n_pb][NPART] (ping-pong)
     double *d_vispart = nullptr;                // [n_visit][NPART]
     int *d_flag = nullptr;                      // [4]: domain flag, ...
+    // gridded forward model (Sec. 2.4): twiddles e^{-2 pi i k/L}, k < L/2;
+    // row-pass buffer [C][N][L] (adjoint: [C][L][N]); spectrum [C][L][L]
+    // (u index major); visibilities sorted by grid cell: per-channel cell
+    // offsets [C][L*L + 1] into perm [ztot] (global visibility indices)
+    void *d_gtw = nullptr, *d_gx1 = nullptr, *d_ggrid = nullptr;
+    int *d_gcell = nullptr, *d_gperm = nullptr;
     size_t bytes_device = 0;
 
     // CG
@@ -183,6 +193,11 @@ namespace uvm {
 hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st);
 // Adjoint: gpart[slot] tiles of Re F^H (w coef) without the beam factor.
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st);
+// Gridded forward model and its exact adjoint (k_grid.hip): the forward
+// writes the single forward partial vpart[0][k]; the adjoint writes the
+// channel's plane gpart[slot_base[c]] (one slot per channel).
+hipError_t launch_grid_forward(const uvmem_ctx *c, const void *bop, hipStream_t st);
+hipError_t launch_grid_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st);
 
 // Auxiliary kernels (k_aux.hip).
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st);

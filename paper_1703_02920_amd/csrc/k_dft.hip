@@ -1041,6 +1041,7 @@ hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipS
 }  // namespace
 
 hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+    if (c->fwd_model == UVMEM_FWD_GRIDDED) return launch_grid_forward(c, bop, st);
     if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st);
     if (c->prec == UVMEM_BF16X3) return fwd_h16<__bf16>(c, bop, st);
     if (c->prec == UVMEM_FP16X3) return fwd_h16<_Float16>(c, bop, st);
@@ -1048,6 +1049,8 @@ hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
 }
 
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+    if (c->fwd_model == UVMEM_FWD_GRIDDED && c->grad_model == UVMEM_GRAD_ADJOINT)
+        return launch_grid_adjoint(c, coef, w, st);
     if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st);
     if (c->prec == UVMEM_BF16X3) return adj_h16<__bf16>(c, coef, w, st);
     if (c->prec == UVMEM_FP16X3) return adj_h16<_Float16>(c, coef, w, st);

@@ -19,12 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libuvmem.so")
 OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ESTATE = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 MODES = {"cube": 0, "shared": 1}
+FORWARD_MODELS = {"dft": 0, "gridded": 1}
+GRADIENT_MODELS = {"adjoint": 0, "dft": 1}
 NSCAL = 8
 S_PHI, S_CHI2, S_S, S_ALPHA, S_BETA, S_GNORM2, S_ALPHA_MAX, S_ITER = range(8)
 
 SYMBOLS = [
     "uvmem_create", "uvmem_destroy", "uvmem_set_uv", "uvmem_set_vis", "uvmem_set_weights",
-    "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_prior", "uvmem_finalize",
+    "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_forward_model", "uvmem_set_prior", "uvmem_finalize",
     "uvmem_phi_and_grad", "uvmem_forward", "uvmem_adjoint", "uvmem_get_residual",
     "uvmem_cg_init", "uvmem_cg_step", "uvmem_cg_run", "uvmem_cg_get_state", "uvmem_cg_set_state",
     "uvmem_check", "uvmem_timing_enable", "uvmem_timing_read", "uvmem_info", "uvmem_chan_range",
@@ -57,6 +59,7 @@ def load() -> ctypes.CDLL:
         "uvmem_set_weights": [vp, ci, vp],
         "uvmem_set_beam": [vp, ci, dbl],
         "uvmem_set_beam_image": [vp, ci, vp],
+        "uvmem_set_forward_model": [vp, ci, ci, ci],
         "uvmem_set_prior": [vp, dbl, dbl],
         "uvmem_finalize": [vp],
         "uvmem_phi_and_grad": [vp, vp, vp, vp],
@@ -171,6 +174,16 @@ class Context:
         A = np.ascontiguousarray(A, np.float32)
         self._call("uvmem_set_beam_image", chan, _ptr(A))
 
+    def set_forward_model(self, model: str = "dft", oversample: int = 1, grad: str = "adjoint"):
+        """Exact DFT ("dft") or the gridded model of Alg. 1 ("gridded": FFT of
+        the image zero-padded to oversample * n, modulation, bilinear
+        interpolation); grad "adjoint" (gradient of the model in use) or
+        "dft" (the exact-DFT gradient at the gridded residuals)."""
+        if model not in FORWARD_MODELS or grad not in GRADIENT_MODELS:
+            raise ValueError("model must be one of %s, grad one of %s" % (sorted(FORWARD_MODELS),
+                                                                          sorted(GRADIENT_MODELS)))
+        self._call("uvmem_set_forward_model", FORWARD_MODELS[model], int(oversample), GRADIENT_MODELS[grad])
+
     def set_prior(self, M: float, lam: float):
         self._call("uvmem_set_prior", float(M), float(lam))
 
@@ -181,9 +194,11 @@ class Context:
         return self
 
     @classmethod
-    def from_dataset(cls, ds, precision: str = "fp32", mode: str = "cube", **kw) -> "Context":
+    def from_dataset(cls, ds, precision: str = "fp32", mode: str = "cube", forward: str = "dft",
+                     oversample: int = 1, grad: str = "adjoint", **kw) -> "Context":
         """Context for a synthetic data set (paper_1703_02920_amd.synth)."""
         ctx = cls(ds.n, ds.n_chan, precision, mode=mode, **kw)
+        ctx.set_forward_model(forward, oversample, grad)
         for c, ch in enumerate(ds.channels):
             ctx.set_uv(c, ch.u, ch.v, ds.cell)
             ctx.set_vis(c, ch.vis)
@@ -195,7 +210,7 @@ class Context:
     def info(self) -> dict:
         keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_wgs",
                 "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block",
-                "n_img"]
+                "n_img", "fwd_model", "grid_side", "grad_model"]
         out = (ctypes.c_int64 * len(keys))()
         self._call("uvmem_info", out, len(keys))
         return dict(zip(keys, [int(x) for x in out]))

@@ -67,9 +67,10 @@ class Problem:
             chans.append(dict(u=u, v=v, vis=vis, w=w, fwhm=(fwhm_px or 0.8 * n) * cell))
         return Problem(n, cell, chans, M, lam)
 
-    def context(self, precision, mode="cube"):
+    def context(self, precision, mode="cube", forward="dft", oversample=1, grad="adjoint"):
         from paper_1703_02920_amd.uvmem import Context
         ctx = Context(self.n, self.n_chan, precision, mode=mode)
+        ctx.set_forward_model(forward, oversample, grad)
         for c, ch in enumerate(self.chans):
             ctx.set_uv(c, ch["u"], ch["v"], self.cell)
             ctx.set_vis(c, ch["vis"])

@@ -1,0 +1,225 @@
+"""Gridded forward model (Sec. 2.4, Alg. 1) and its adjoint on the GPU against
+the oracle's gridded model, element by element: forward and adjoint on
+several grid sizes and oversampling factors, Phi / grad Phi with both
+gradient choices, shared mode, CG trajectories, determinism and graph replay,
+and the full 256^2 x 99,840 and 1024^2 x 5,000,250 workloads.
+
+The gridded transforms run in FP64 for the fp64 precision and in FP32 for
+every other one, so everything the gridded model computes is held to the
+FP32 bar in the split precisions too; the exact-DFT gradient option uses the
+precision's own DFT adjoint and is held to that precision's bar."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cg as ocg
+from oracle import gridded as og
+from _common import CG_TOL, TOL, Problem, flush, rel, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PRECS = ["fp64", "fp32", "bf16x3", "fp16x3"]
+GTOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6, "fp16x3": 1e-6}
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _two_channels(n, seed):
+    """Two channels of different sizes, uv scales and beams."""
+    prob = Problem.random(n, [900, 1333], seed=seed, lam=0.05)
+    prob.chans[1]["u"] = prob.chans[1]["u"] * 0.9
+    prob.chans[1]["v"] = prob.chans[1]["v"] * 0.9
+    prob.chans[0]["fwhm"] = 0.7 * n * prob.cell
+    prob.chans[1]["fwhm"] = 0.45 * n * prob.cell
+    return prob
+
+
+def _gfwd(prob, c, img, s):
+    ch = prob.chans[c]
+    return og.gridded_forward(prob.n, prob.cell, ch["u"], ch["v"], prob.beam(c), img, s)
+
+
+def _gadj(prob, c, coef, s):
+    ch = prob.chans[c]
+    return og.gridded_adjoint(prob.n, prob.cell, ch["u"], ch["v"], prob.beam(c), coef, s)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,s", [(64, 1), (64, 2), (128, 1), (32, 4)])
+def test_gridded_forward_parity(prec, n, s):
+    _cuda()
+    flush(f"gridded forward parity {prec} n={n} oversample={s}")
+    prob = _two_channels(n, seed=n + 7 * s)
+    ctx = prob.context(prec, forward="gridded", oversample=s)
+    info = ctx.info()
+    assert info["fwd_model"] == 1 and info["grid_side"] == s * n
+    img = synth.random_image(n, 90 + s, lo=1e-3, hi=1.0, n_chan=2)
+    I = torch.tensor(img, dtype=ctx.dtype, device="cuda")
+    V = ctx.forward(I).cpu().numpy()
+    Ih = I.cpu().numpy().astype(np.float64)
+    offs = prob.offsets()
+    errs = [rel(V[offs[c]:offs[c + 1]], _gfwd(prob, c, Ih[c], s)) for c in range(2)]
+    flush(f"  rel err per channel {errs[0]:.2e} {errs[1]:.2e}")
+    assert max(errs) < GTOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,s", [(64, 1), (64, 2), (128, 1), (32, 4)])
+def test_gridded_adjoint_parity(prec, n, s):
+    _cuda()
+    flush(f"gridded adjoint parity {prec} n={n} oversample={s}")
+    prob = _two_channels(n, seed=3 * n + s)
+    ctx = prob.context(prec, forward="gridded", oversample=s)
+    offs = prob.offsets()
+    rng = np.random.default_rng(n + s)
+    coef = rng.standard_normal(offs[-1]) + 1j * rng.standard_normal(offs[-1])
+    G = ctx.adjoint(torch.tensor(coef, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    errs = [rel(G[c], _gadj(prob, c, coef[offs[c]:offs[c + 1]], s)) for c in range(2)]
+    flush(f"  rel err per channel {errs[0]:.2e} {errs[1]:.2e}")
+    assert max(errs) < GTOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("grad", ["adjoint", "dft"])
+def test_gridded_phi_grad_parity_c1(prec, grad):
+    """64^2 x 5,130 workload at P3 on a twice finer grid."""
+    _cuda()
+    flush(f"gridded phi/grad c1 {prec} grad={grad}")
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context(prec, forward="gridded", oversample=2, grad=grad)
+    I = torch.tensor(synth.eval_images(ds, "P3"), dtype=ctx.dtype, device="cuda")
+    scal, g = ctx.phi_and_grad(I)
+    scal = scal.cpu().numpy()
+    ch = prob.chans[0]
+    ref = og.gridded_phi_grad(ds.n, ds.cell, ch["u"], ch["v"], prob.beam(0), I.cpu().numpy()[0].astype(np.float64),
+                              ch["vis"].astype(np.complex128), ch["w"].astype(np.float64), ds.prior_m, ds.lam,
+                              oversample=2, grad=grad)
+    e = dict(phi=abs(scal[0, 0] - ref["phi"]) / abs(ref["phi"]), chi2=abs(scal[0, 1] - ref["chi2"]) / ref["chi2"],
+             R=rel(ctx.residual().cpu().numpy(), ref["R"]), grad=rel(g.cpu().numpy()[0], ref["grad"]))
+    flush("  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    gbar = GTOL[prec] if grad == "adjoint" else TOL[prec]
+    assert e["phi"] < GTOL[prec] and e["chi2"] < GTOL[prec] and e["R"] < GTOL[prec]
+    assert e["grad"] < gbar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gridded_shared_mode(prec):
+    """One image, two channels with their own beams (Eq. chi2-multi) through
+    the gridded model: chi^2 summed, gradient = sum of the channels' gridded
+    adjoints, entropy once."""
+    _cuda()
+    n, s = 64, 2
+    prob = _two_channels(n, seed=77)
+    ctx = prob.context(prec, mode="shared", forward="gridded", oversample=s)
+    img = synth.random_image(n, 78, lo=1e-3, hi=1.0)
+    I = torch.tensor(img, dtype=ctx.dtype, device="cuda")
+    scal, g = ctx.phi_and_grad(I)
+    Ih = I.cpu().numpy()[0].astype(np.float64)
+    x2, gchi = 0.0, np.zeros((n, n))
+    for c in range(2):
+        ch = prob.chans[c]
+        x, R = oracle.chi2(_gfwd(prob, c, Ih, s), ch["vis"].astype(np.complex128), ch["w"].astype(np.float64))
+        x2 += x
+        gchi += _gadj(prob, c, ch["w"].astype(np.float64) * R, s)
+    S, gS = oracle.entropy(Ih, prob.M)
+    e_phi = abs(float(scal[0, 0]) - (x2 + prob.lam * S)) / abs(x2 + prob.lam * S)
+    e_g = rel(g.cpu().numpy()[0], gchi + prob.lam * gS)
+    flush(f"gridded shared {prec}: phi {e_phi:.2e} grad {e_g:.2e}")
+    assert e_phi < GTOL[prec] and e_g < GTOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gridded_cg_trajectory_c1(prec):
+    """Projected CG with the gridded model (grid twice finer) against the
+    oracle's CG on the same model."""
+    _cuda()
+    ds = synth.make_config(1)
+    iters = ds.cg_iters
+    prob = Problem.from_dataset(ds)
+    ch = prob.chans[0]
+    op = ocg.GriddedProblem(ds.n, ds.cell, ch["u"], ch["v"], ch["vis"], ch["w"], prob.beam(0), ds.prior_m, ds.lam,
+                            oversample=2)
+    I_ref, traj = ocg.projected_cg(op, iters)
+    ctx = prob.context(prec, forward="gridded", oversample=2)
+    I = ctx.image()
+    ctx.cg_init(I, init_to_floor=True)
+    hist = ctx.cg_run(I, iters, graph=True).cpu().numpy()
+    ctx.check()
+    phis = hist[:, 0, 0]
+    ref_phis = np.array([t["phi"] for t in traj])
+    assert len(traj) == iters
+    e_phi = float(np.max(np.abs(phis - ref_phis) / np.abs(ref_phis)))
+    e_img = rel(I.cpu().numpy()[0], I_ref)
+    flush(f"gridded cg {prec}: max rel phi {e_phi:.2e}, final image {e_img:.2e}")
+    assert np.all(np.diff(phis) <= 1e-12 * np.abs(phis[:-1]))
+    assert e_phi < CG_TOL[prec]["phi"] and e_img < CG_TOL[prec]["img"]
+
+
+def test_gridded_deterministic_and_graph_replay():
+    """Two evaluations give the same bits (the adjoint's sums have a fixed
+    order); graph-replayed CG steps equal eager ones."""
+    _cuda()
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context("fp32", forward="gridded", oversample=1)
+    I = torch.tensor(synth.eval_images(ds, "P3"), dtype=torch.float32, device="cuda")
+    s1, g1 = ctx.phi_and_grad(I)
+    s1, g1 = s1.clone(), g1.clone()
+    s2, g2 = ctx.phi_and_grad(I)
+    assert torch.equal(s1, s2) and torch.equal(g1, g2)
+    out = []
+    for graph in (False, True):
+        J = ctx.image()
+        ctx.cg_init(J)
+        h = ctx.cg_run(J, 4, graph=graph)
+        torch.cuda.synchronize()
+        out.append((h.clone(), J.clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_gridded_rejects_bad_sizes():
+    _cuda()
+    from paper_1703_02920_amd.uvmem import Context, UvmemError
+    for n, s, prec in ((100, 1, "fp32"), (64, 3, "fp32"), (4, 2, "fp32"), (2048, 4, "fp64")):
+        ctx = Context(n, 1, prec)
+        with pytest.raises(UvmemError):
+            ctx.set_forward_model("gridded", s)
+        ctx.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _ds(c):
+    flush(f"  generating workload c{c}")
+    return synth.make_config(c)
+
+
+@pytest.mark.parametrize("c,s", [(2, 1), (2, 2), (5, 2)])
+def test_gridded_full_size(c, s):
+    """Every visibility and pixel of the 256^2 x 99,840 workload (the paper's
+    grid and a twice finer one) and of the 1024^2 x 5,000,250 workload on a
+    2048^2 grid: V^m, R, chi^2, Phi and grad Phi at P3 (FP32 transforms)."""
+    _cuda()
+    flush(f"gridded full size c{c} oversample={s}")
+    ds = _ds(c)
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context("fp32", forward="gridded", oversample=s)
+    img = synth.eval_images(ds, "P3").astype(np.float32)
+    scal, g = ctx.phi_and_grad(torch.tensor(img, device="cuda"))
+    scal = scal.cpu().numpy()
+    ch = prob.chans[0]
+    ref = og.gridded_phi_grad(ds.n, ds.cell, ch["u"], ch["v"], prob.beam(0), img[0].astype(np.float64),
+                              ch["vis"].astype(np.complex128), ch["w"].astype(np.float64), ds.prior_m, ds.lam,
+                              oversample=s)
+    e = dict(phi=abs(scal[0, 0] - ref["phi"]) / abs(ref["phi"]), chi2=abs(scal[0, 1] - ref["chi2"]) / ref["chi2"],
+             R=rel(ctx.residual().cpu().numpy(), ref["R"]), grad=rel(g.cpu().numpy()[0], ref["grad"]))
+    flush("  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    for k, v in e.items():
+        assert v < GTOL["fp32"], (k, v)
