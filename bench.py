@@ -29,7 +29,7 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "fp16x3": 2500.0}   # TFL
 KERNEL_SRC = "paper_1703_02920_amd/csrc/k_dft.hip"
 # DFT kernel functions per precision: (forward, adjoint)
 KERNELS = {"fp32": ("k_forward_p", "k_adjoint"), "fp64": ("k_forward_p", "k_adjoint"),
-           "bf16x3": ("k_forward_h16p", "k_adjoint_h16"), "fp16x3": ("k_forward_h16p", "k_adjoint_h16")}
+           "bf16x3": ("k_forward_h16p", "k_adjoint_h16w"), "fp16x3": ("k_forward_h16p", "k_adjoint_h16w")}
 
 
 def kernel_hash(kernel: str) -> str:
@@ -159,6 +159,132 @@ def eval_error(ds, ctx_a, ctx_b):
             "grad": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb))}
 
 
+def _median_eval_ms(ctx, img, reps=20, warmup=3):
+    """Median ms of one Phi + grad evaluation and the average forward and
+    adjoint launch times (HIP events on the context's stream)."""
+    import numpy as np
+    import torch
+    scal, grad = ctx.scalars(), torch.empty_like(img)
+    for _ in range(warmup):
+        ctx.phi_and_grad(img, grad, scal)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(0, reset=True)
+    ctx.timing_read(1, reset=True)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.phi_and_grad(img, grad, scal)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    (fm, fc), (am, ac) = ctx.timing_read(0), ctx.timing_read(1)
+    ctx.timing(False)
+    ctx.check()
+    return float(np.median(ts)), fm / max(fc, 1), am / max(ac, 1)
+
+
+def grid_error(configs, oversamples, prec="fp32"):
+    """The gridded model of Alg. 1 against the exact DFT model on the same
+    workload and image (P2 = the sky, P3 = M + U[0, 1)): relative error of
+    V^m, chi^2 and grad Phi -- with the gridded model's own gradient and with
+    the exact-DFT gradient at the gridded residuals -- and the time of one
+    Phi + grad evaluation (with forward / adjoint launch times) of each."""
+    import numpy as np
+    import torch
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
+
+    rows = []
+    for c in configs:
+        ds = synth.make_config(c)
+        ex = Context.from_dataset(ds, prec)
+        imgs = {w: torch.tensor(synth.eval_images(ds, w), dtype=ex.dtype, device=ex.device) for w in ("P2", "P3")}
+        ref = {}
+        for w, img in imgs.items():
+            V = ex.forward(img).clone()
+            sc, g = ex.phi_and_grad(img)
+            ref[w] = (V, sc.clone(), g.clone())
+        t_ex = _median_eval_ms(ex, imgs["P3"])
+        ex.close()
+        for s in oversamples:
+            L = s * ds.n
+            if L > 8192 or L & (L - 1):
+                continue
+            for grad in ("adjoint", "dft"):
+                ctx = Context.from_dataset(ds, prec, forward="gridded", oversample=s, grad=grad)
+                for w, img in imgs.items():
+                    V = ctx.forward(img)
+                    sc, g = ctx.phi_and_grad(img)
+                    Vr, scr, gr = ref[w]
+                    row = {"config": f"c{c}", "precision": prec, "oversample": s, "grid": L, "grad": grad,
+                           "image": w, "rel_err_V": rel(V, Vr),
+                           "rel_err_chi2": abs(float(sc[:, 1].sum() - scr[:, 1].sum())) / float(scr[:, 1].sum()),
+                           "rel_err_grad": rel(g, gr)}
+                    if w == "P3":
+                        t = _median_eval_ms(ctx, img)
+                        row.update({"ms_eval": t[0], "ms_forward": t[1], "ms_adjoint": t[2],
+                                    "ms_eval_exact": t_ex[0], "ms_forward_exact": t_ex[1],
+                                    "ms_adjoint_exact": t_ex[2]})
+                    rows.append(row)
+                    print(json.dumps(row), flush=True)
+                ctx.close()
+    return rows
+
+
+def grid_cg(c, oversamples, prec="fp32", iters=None):
+    """T graph-replayed CG iterations with the exact model and with the
+    gridded model (each gradient choice); every final image is scored with
+    the exact objective: Phi_exact(I_T) and chi^2_exact(I_T) relative to the
+    exact run's, the image's relative difference from the exact run's, and
+    iterations/s."""
+    import torch
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+    ds = synth.make_config(c)
+    T = iters or ds.cg_iters
+    ex = Context.from_dataset(ds, prec)
+    runs = [("dft", 1, "adjoint")] + [("gridded", s, g) for s in oversamples for g in ("adjoint", "dft")
+                                      if s * ds.n <= 8192]
+    out, base = [], None
+    for fwd, s, g in runs:
+        ctx = ex if fwd == "dft" else Context.from_dataset(ds, prec, forward=fwd, oversample=s, grad=g)
+        I = ctx.image()
+        ctx.cg_init(I, init_to_floor=True)
+        ctx.cg_run(I, 1, graph=True)
+        ctx.cg_init(I, init_to_floor=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.cg_run(I, T, graph=True)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = e0.elapsed_time(e1)
+        sc, _ = ex.phi_and_grad(I)
+        phi, chi2 = float(sc[:, 0].sum()), float(sc[:, 1].sum())
+        row = {"config": f"c{c}", "precision": prec, "forward": fwd, "oversample": s if fwd != "dft" else None,
+               "grad": g if fwd != "dft" else None, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
+               "phi_exact_T": phi, "chi2_exact_T": chi2}
+        if base is None:
+            base = (phi, chi2, I.clone())
+        else:
+            row["rel_phi_exact_vs_exact_run"] = (phi - base[0]) / abs(base[0])
+            row["rel_chi2_exact_vs_exact_run"] = (chi2 - base[1]) / abs(base[1])
+            row["rel_image_diff_vs_exact_run"] = float(torch.linalg.vector_norm((I - base[2]).double())
+                                                       / torch.linalg.vector_norm(base[2].double()))
+        out.append(row)
+        print(json.dumps(row), flush=True)
+        if ctx is not ex:
+            ctx.close()
+    ex.close()
+    return out
+
+
 def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
     """M1 per configuration and precision: median time of one Phi + grad Phi
     evaluation (forward, chi^2, adjoint, entropy, combine) at the P3 image,
@@ -262,6 +388,11 @@ def main():
     ap.add_argument("--mode", default="cube", choices=["cube", "shared"],
                     help="image model of --eval-sweep and --cg-compare: an image per channel, or one image "
                          "fitted to every channel")
+    ap.add_argument("--grid-error", default="", metavar="CONFIGS",
+                    help="only compare the gridded model (Alg. 1) with the exact DFT on these configurations")
+    ap.add_argument("--grid-cg", type=int, default=0, metavar="CONFIG",
+                    help="only run CG with the exact and the gridded models and score the images exactly")
+    ap.add_argument("--oversample", default="1,2,4", help="gridded-model oversampling factors")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,6 +404,12 @@ def main():
     if args.eval_sweep:
         eval_sweep([int(x) for x in args.eval_sweep.split(",")], ["fp64", "fp32", "bf16x3", "fp16x3"],
                    mode=args.mode)
+        return
+    if args.grid_error:
+        grid_error([int(x) for x in args.grid_error.split(",")], [int(x) for x in args.oversample.split(",")])
+        return
+    if args.grid_cg:
+        grid_cg(args.grid_cg, [int(x) for x in args.oversample.split(",")])
         return
     if args.cg_compare:
         cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"], mode=args.mode)

@@ -75,7 +75,7 @@ void free_all(uvmem_ctx *c) {
                     c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr, c->d_gtw, c->d_gx1, c->d_ggrid, c->d_gcell,
-                    c->d_gperm};
+                    c->d_gperm, c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdlist, c->d_gdsum};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -565,6 +565,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     const size_t gcells = (size_t)GL * GL;
     std::vector<char> gtw;
     std::vector<int> gcell, gperm;
+    std::vector<double> gfxy;
+    std::vector<int> gdidx, gdlist;
     if (gridded) {
         const size_t csz = 2 * rs;
         gtw.resize((size_t)(GL / 2) * csz);
@@ -600,6 +602,24 @@ int uvmem_finalize(uvmem_ctx *c) {
             cs[gcells] = (int)pos;
             std::vector<int> fill(cs, cs + gcells);
             for (int64_t k = c->off[ch]; k < c->off[ch + 1]; ++k) gperm[fill[cellof[k]]++] = (int)k;
+        }
+        gdidx.assign((size_t)C * gcells, -1);
+        for (int ch = 0; ch < C; ++ch) {
+            const int *cs = gcell.data() + (size_t)ch * (gcells + 1);
+            for (size_t t = 0; t < gcells; ++t)
+                if (cs[t + 1] - cs[t] > GRID_DENSE) {
+                    gdidx[(size_t)ch * gcells + t] = (int)(gdlist.size() / 2);
+                    gdlist.push_back(cs[t]);
+                    gdlist.push_back(cs[t + 1]);
+                }
+        }
+        c->n_gdense = (int)(gdlist.size() / 2);
+        gfxy.resize(2 * (size_t)c->ztot);
+        for (int64_t j = 0; j < c->ztot; ++j) {
+            const int64_t k = gperm[j];
+            const double gx = a[k] * (double)GL, gy = bb[k] * (double)GL;
+            gfxy[2 * j] = gx - std::floor(gx);
+            gfxy[2 * j + 1] = gy - std::floor(gy);
         }
     }
 
@@ -657,6 +677,11 @@ int uvmem_finalize(uvmem_ctx *c) {
         ok(dalloc(c, (char **)&c->d_ggrid, (size_t)C * gcells * 2 * rs));
         ok(dalloc(c, &c->d_gcell, gcell.size()));
         ok(dalloc(c, &c->d_gperm, gperm.size()));
+        ok(dalloc(c, &c->d_gfxy, c->ztot));
+        ok(dalloc(c, &c->d_gsc, c->ztot));
+        ok(dalloc(c, &c->d_gdidx, gdidx.size()));
+        ok(dalloc(c, &c->d_gdlist, (size_t)c->n_gdense));
+        ok(dalloc(c, &c->d_gdsum, (size_t)c->n_gdense * 4));
     }
     if (e != hipSuccess) {
         free_all(c);
@@ -685,6 +710,9 @@ int uvmem_finalize(uvmem_ctx *c) {
         up(c->d_gtw, gtw.data(), gtw.size());
         up(c->d_gcell, gcell.data(), gcell.size() * sizeof(int));
         up(c->d_gperm, gperm.data(), gperm.size() * sizeof(int));
+        up(c->d_gfxy, gfxy.data(), gfxy.size() * sizeof(double));
+        up(c->d_gdidx, gdidx.data(), gdidx.size() * sizeof(int));
+        up(c->d_gdlist, gdlist.data(), gdlist.size() * sizeof(int));
     }
     if (e != hipSuccess) return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
     HIPCHK(c, hipDeviceSynchronize());

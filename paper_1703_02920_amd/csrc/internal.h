@@ -30,6 +30,9 @@ constexpr int NPART = 8;
 constexpr int LS_K = 4;
 // Relative tolerance that decides "pixel at the bound I <= M (1 + tol)".
 constexpr double BOUND_TOL = 1e-12;
+// Gridded model: cells holding more visibilities than this are reduced by a
+// wave each before the node gather (bounds the gather's serial loops).
+constexpr int GRID_DENSE = 16;
 // Default number of line-search passes per CG step; a channel whose search
 // has converged skips the remaining passes.
 constexpr int LS_STEPS = 4;
@@ -163,8 +166,17 @@ struct uvmem_ctx {
     // row-pass buffer [C][N][L] (adjoint: [C][L][N]); spectrum [C][L][L]
     // (u index major); visibilities sorted by grid cell: per-channel cell
     // offsets [C][L*L + 1] into perm [ztot] (global visibility indices)
+    // (visibility perm[j] is the j-th in cell order); bilinear fractions
+    // (fx, fy) in that order; the weighted coefficients in that order
     void *d_gtw = nullptr, *d_gx1 = nullptr, *d_ggrid = nullptr;
     int *d_gcell = nullptr, *d_gperm = nullptr;
+    double2 *d_gfxy = nullptr, *d_gsc = nullptr;
+    // dense cells: per-cell index into the dense list ([C][L*L], -1 if not
+    // dense), each dense cell's sorted range, and its four weighted sums
+    int *d_gdidx = nullptr;
+    int2 *d_gdlist = nullptr;
+    double2 *d_gdsum = nullptr;
+    int n_gdense = 0;
     size_t bytes_device = 0;
 
     // CG

@@ -17,9 +17,10 @@
 // first N rows and columns: the channel's plane of the split-K partial
 // buffer, which the gradient kernel multiplies by A_c.
 //
-// Transform: radix-2 decimation in time on P sequences of length L held in
-// LDS, inputs placed at bit-reversed positions, one barrier per stage;
-// twiddles e^{-2 pi i k / L}, k < L/2, from a table built in FP64 at set-up.
+// Transform: decimation in time on P sequences of length L held in LDS,
+// inputs placed at bit-reversed positions, radix-2 stages fused in pairs
+// (one barrier per pair); twiddles e^{-2 pi i k / L}, k < L/2, from a table
+// built in FP64 at set-up.
 // FP64 transforms for the FP64 precision, FP32 otherwise.
 
 #include "internal.h"
@@ -37,6 +38,14 @@ constexpr int GT = 256;   // threads per workgroup of the grid kernels
 
 __device__ __forceinline__ int bitrev(int e, int lg) { return (int)(__brev((unsigned)e) >> (32 - lg)); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b % 8);
+// the column passes renumber them so that each XCD works through one
+// contiguous run of column groups, whose partial cache lines then meet in
+// that XCD's L2.  Identity unless the grid is a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    return (nblocks & 7) ? b : (b & 7) * (nblocks >> 3) + (b >> 3);
+}
+
 // e^{+2 pi i m / L} for an integer m in [0, L) from the table of e^{-2 pi i k / L}.
 template <typename T>
 __device__ __forceinline__ V2<T> expi_pos(const V2<T> *__restrict__ tw, int m, int L) {
@@ -48,34 +57,76 @@ __device__ __forceinline__ V2<T> expi_pos(const V2<T> *__restrict__ tw, int m, i
     return r;
 }
 
+template <typename T>
+__device__ __forceinline__ V2<T> cmul(V2<T> w, V2<T> x) {
+    V2<T> t;
+    t.x = w.x * x.x - w.y * x.y;
+    t.y = w.x * x.y + w.y * x.x;
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void bfly(V2<T> &x0, V2<T> &x1, V2<T> w) {
+    const V2<T> t = cmul<T>(w, x1);
+    V2<T> y0, y1;
+    y0.x = x0.x + t.x;
+    y0.y = x0.y + t.y;
+    y1.x = x0.x - t.x;
+    y1.y = x0.y - t.y;
+    x0 = y0;
+    x1 = y1;
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ V2<T> twid(const V2<T> *__restrict__ tw, int idx) {
+    V2<T> w = tw[idx];
+    if (DIR > 0) w.y = -w.y;
+    return w;
+}
+
 // Stages of the in-place transform of s[r * L + e], r < P (inputs already at
-// bit-reversed positions).  DIR = -1: e^{-}, +1: e^{+}.
+// bit-reversed positions).  DIR = -1: e^{-}, +1: e^{+}.  Radix-2 stage st
+// (span 2h, h = 2^(st-1)) combines s[i] and s[i + h] with W_{2h}^j; pairs of
+// stages run as one radix-4 pass over four elements per thread (the same
+// butterflies, half the LDS round trips and barriers), and an odd last
+// stage runs alone.
 template <typename T, int DIR>
 __device__ void fft_stages(V2<T> *s, int P, int lg, const V2<T> *__restrict__ tw) {
     const int L = 1 << lg;
-    const int nb = P * (L >> 1);
-    for (int st = 1; st <= lg; ++st) {
+    int st = 1;
+    for (; st + 1 <= lg; st += 2) {
         const int h = 1 << (st - 1);
-        const int tstride = L >> st;
+        const int nq = P * (L >> 2);
+        for (int b = threadIdx.x; b < nq; b += GT) {
+            const int r = b >> (lg - 2);
+            const int k = b & ((L >> 2) - 1);
+            const int j = k & (h - 1);
+            const int i0 = r * L + ((k >> (st - 1)) << (st + 1)) + j;
+            V2<T> a0 = s[i0], a1 = s[i0 + h], a2 = s[i0 + 2 * h], a3 = s[i0 + 3 * h];
+            const V2<T> w1 = twid<T, DIR>(tw, j * (L >> st));
+            bfly<T>(a0, a1, w1);
+            bfly<T>(a2, a3, w1);
+            bfly<T>(a0, a2, twid<T, DIR>(tw, j * (L >> (st + 1))));
+            bfly<T>(a1, a3, twid<T, DIR>(tw, (j + h) * (L >> (st + 1))));
+            s[i0] = a0;
+            s[i0 + h] = a1;
+            s[i0 + 2 * h] = a2;
+            s[i0 + 3 * h] = a3;
+        }
+        __syncthreads();
+    }
+    if (st == lg) {
+        const int h = 1 << (st - 1);
+        const int nb = P * (L >> 1);
         for (int b = threadIdx.x; b < nb; b += GT) {
             const int r = b >> (lg - 1);
             const int k = b & ((L >> 1) - 1);
             const int j = k & (h - 1);
             const int i0 = r * L + ((k >> (st - 1)) << st) + j;
-            const int i1 = i0 + h;
-            V2<T> w = tw[j * tstride];
-            if (DIR > 0) w.y = -w.y;
-            const V2<T> x0 = s[i0], x1 = s[i1];
-            V2<T> t;
-            t.x = w.x * x1.x - w.y * x1.y;
-            t.y = w.x * x1.y + w.y * x1.x;
-            V2<T> y0, y1;
-            y0.x = x0.x + t.x;
-            y0.y = x0.y + t.y;
-            y1.x = x0.x - t.x;
-            y1.y = x0.y - t.y;
-            s[i0] = y0;
-            s[i1] = y1;
+            V2<T> x0 = s[i0], x1 = s[i0 + h];
+            bfly<T>(x0, x1, twid<T, DIR>(tw, j * (L >> st)));
+            s[i0] = x0;
+            s[i0 + h] = x1;
         }
         __syncthreads();
     }
@@ -116,7 +167,8 @@ __global__ __launch_bounds__(GT) void k_grid_cols_fwd(const V2<T> *__restrict__ 
     V2<T> *s = reinterpret_cast<V2<T> *>(smem);
     const int L = 1 << lg;
     const int bpc = L / P;
-    const int c = blockIdx.x / bpc, p0 = (blockIdx.x % bpc) * P;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int c = blk / bpc, p0 = (blk % bpc) * P;
     const V2<T> *X = x1 + (size_t)c * n * L;
     for (int x = threadIdx.x; x < P * L; x += GT) {
         const int r = x % P, i = x / P;
@@ -175,12 +227,58 @@ __global__ __launch_bounds__(GT) void k_grid_interp(const VisItem *__restrict__ 
     }
 }
 
+// Adjoint pass 0: the weighted coefficients w_k coef_k in cell-sorted
+// order (w may be null), so that pass 1 reads contiguous ranges.
+__global__ __launch_bounds__(GT) void k_grid_sort_coef(const int *__restrict__ perm, const double2 *__restrict__ coef,
+                                                       const float *__restrict__ w, long long ztot,
+                                                       double2 *__restrict__ sorted) {
+    const long long j = (long long)blockIdx.x * GT + threadIdx.x;
+    if (j >= ztot) return;
+    const int k = perm[j];
+    const double ww = w ? (double)w[k] : 1.0;
+    const double2 cf = coef[k];
+    sorted[j] = make_double2(ww * cf.x, ww * cf.y);
+}
+
+// Adjoint pass 1a: the four weighted sums of each dense cell (more than
+// GRID_DENSE visibilities) -- its shares for the nodes (p0, q0), (p0+1, q0),
+// (p0, q0+1), (p0+1, q0+1) -- one wave per cell, lanes striding over the
+// cell's sorted range, then a fixed butterfly reduction.
+__global__ __launch_bounds__(GT) void k_grid_dense(const int2 *__restrict__ dlist, int ndense,
+                                                   const double2 *__restrict__ fxy,
+                                                   const double2 *__restrict__ sorted, double2 *__restrict__ dsum) {
+    const int lane = threadIdx.x & 63;
+    const int cidx = blockIdx.x * (GT / 64) + (threadIdx.x >> 6);
+    if (cidx >= ndense) return;   // the whole wave leaves together
+    const int2 rg = dlist[cidx];
+    double acc[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) acc[x] = 0.0;
+    for (int j = rg.x + lane; j < rg.y; j += 64) {
+        const double2 f = fxy[j], cf = sorted[j];
+        const double w[4] = {(1.0 - f.x) * (1.0 - f.y), f.x * (1.0 - f.y), (1.0 - f.x) * f.y, f.x * f.y};
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            acc[2 * d] += w[d] * cf.x;
+            acc[2 * d + 1] += w[d] * cf.y;
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+        for (int o = 32; o > 0; o >>= 1) acc[x] += __shfl_xor(acc[x], o, 64);
+    if (lane == 0)
+        for (int d = 0; d < 4; ++d) dsum[(size_t)cidx * 4 + d] = make_double2(acc[2 * d], acc[2 * d + 1]);
+}
+
 // Adjoint pass 1: H[c][p][q] = e^{-2 pi i (p+q)(N/2)/L} sum over the four
-// cells around node (p, q) of bilinear weight x w_k coef_k (w may be null).
+// cells around node (p, q) of bilinear weight x (w coef), reading the
+// cell-sorted coefficients and the bilinear fractions stored in the same
+// order at set-up.
 template <typename T>
-__global__ __launch_bounds__(GT) void k_grid_gather(const int *__restrict__ cell_start, const int *__restrict__ perm,
-                                                    const double *__restrict__ a, const double *__restrict__ b,
-                                                    const double2 *__restrict__ coef, const float *__restrict__ w,
+__global__ __launch_bounds__(GT) void k_grid_gather(const int *__restrict__ cell_start,
+                                                    const double2 *__restrict__ fxy,
+                                                    const double2 *__restrict__ sorted,
+                                                    const int *__restrict__ didx, const double2 *__restrict__ dsum,
                                                     int n, int lg, int nchan, const V2<T> *__restrict__ tw,
                                                     V2<T> *__restrict__ hgrid) {
     const int L = 1 << lg;
@@ -191,19 +289,44 @@ __global__ __launch_bounds__(GT) void k_grid_gather(const int *__restrict__ cell
     const int cell = (int)(t % cells);
     const int p = cell >> lg, q = cell & (L - 1);
     const int *cs = cell_start + (size_t)c * (cells + 1);
+    int jb[4], je[4], di[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int src = ((p - (d & 1)) & (L - 1)) * L + ((q - (d >> 1)) & (L - 1));
+        jb[d] = cs[src];
+        je[d] = cs[src + 1];
+        di[d] = didx[(size_t)c * cells + src];
+    }
+    // sums in sorted order; four visibilities' loads issued together
     double hx = 0.0, hy = 0.0;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int dp = d & 1, dq = d >> 1;
-        const int sp = (p - dp) & (L - 1), sq = (q - dq) & (L - 1);
-        const int src = sp * L + sq;
-        for (int j = cs[src]; j < cs[src + 1]; ++j) {
-            const int k = perm[j];
-            int p0, q0;
-            double fx, fy;
-            grid_node(a[k], b[k], L, p0, q0, fx, fy);
-            const double wt = (dp ? fx : 1.0 - fx) * (dq ? fy : 1.0 - fy) * (w ? (double)w[k] : 1.0);
-            const double2 cf = coef[k];
+        if (di[d] >= 0) {   // a dense cell: its share for this node, summed in pass 1a
+            const double2 v = dsum[(size_t)di[d] * 4 + d];
+            hx += v.x;
+            hy += v.y;
+            continue;
+        }
+        int j = jb[d];
+        for (; j + 4 <= je[d]; j += 4) {
+            double2 f[4], cf[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                f[u] = fxy[j + u];
+                cf[u] = sorted[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double wt = (dp ? f[u].x : 1.0 - f[u].x) * (dq ? f[u].y : 1.0 - f[u].y);
+                hx += wt * cf[u].x;
+                hy += wt * cf[u].y;
+            }
+        }
+        for (; j < je[d]; ++j) {
+            const double2 f = fxy[j];
+            const double wt = (dp ? f.x : 1.0 - f.x) * (dq ? f.y : 1.0 - f.y);
+            const double2 cf = sorted[j];
             hx += wt * cf.x;
             hy += wt * cf.y;
         }
@@ -249,7 +372,8 @@ __global__ __launch_bounds__(GT) void k_grid_cols_inv(const V2<T> *__restrict__ 
     V2<T> *s = reinterpret_cast<V2<T> *>(smem);
     const int L = 1 << lg;
     const int bpc = (n + P - 1) / P;
-    const int c = blockIdx.x / bpc, i0 = (blockIdx.x % bpc) * P;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int c = blk / bpc, i0 = (blk % bpc) * P;
     const V2<T> *Y = y + (size_t)c * L * n;
     for (int x = threadIdx.x; x < P * L; x += GT) {
         const int r = x % P, pp = x / P, i = i0 + r;
@@ -308,8 +432,14 @@ hipError_t grid_adj_t(const uvmem_ctx *c, const double2 *coef, const float *w, h
     V2<T> *hgrid = reinterpret_cast<V2<T> *>(c->d_ggrid);
     const size_t esz = sizeof(V2<T>);
     const long long cells = (long long)L * L * C;
+    if (c->ztot > 0)
+        hipLaunchKernelGGL(k_grid_sort_coef, dim3((unsigned)((c->ztot + GT - 1) / GT)), dim3(GT), 0, st, c->d_gperm,
+                           coef, w, (long long)c->ztot, c->d_gsc);
+    if (c->n_gdense > 0)
+        hipLaunchKernelGGL(k_grid_dense, dim3((c->n_gdense + GT / 64 - 1) / (GT / 64)), dim3(GT), 0, st, c->d_gdlist,
+                           c->n_gdense, c->d_gfxy, c->d_gsc, c->d_gdsum);
     hipLaunchKernelGGL((k_grid_gather<T>), dim3((unsigned)((cells + GT - 1) / GT)), dim3(GT), 0, st, c->d_gcell,
-                       c->d_gperm, c->d_a, c->d_b, coef, w, n, lg, C, tw, hgrid);
+                       c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdsum, n, lg, C, tw, hgrid);
     const int pr = seqs_rows(L, esz), pc = seqs_cols(L, esz, C);
     hipLaunchKernelGGL((k_grid_rows_inv<T>), dim3(C * (L / pr)), dim3(GT), pr * L * esz, st, hgrid, n, lg, pr, tw, y);
     hipLaunchKernelGGL((k_grid_cols_inv<T, PT>), dim3(C * ((n + pc - 1) / pc)), dim3(GT), pc * L * esz, st, y, n,
