@@ -195,3 +195,43 @@ def phi_grad_shared(n, cell, chans, I, M, lam):
     return dict(phi=x2 + lam * S, chi2=x2, S=S, grad=gchi + lam * gS, gchi2=gchi,
                 V=np.concatenate(Vs) if Vs else np.zeros(0, np.complex128),
                 R=np.concatenate(Rs) if Rs else np.zeros(0, np.complex128))
+
+
+def beam_at(n: int, cell: float, fwhm: float, x0: float, y0: float) -> np.ndarray:
+    """Gaussian attenuation image centred on a pointing at (x0, y0) radians
+    from the image centre (Sec. 2.4 item 1: for a mosaic, each pointing's
+    attenuation image is centred on its field)."""
+    c = (np.arange(n) - n // 2) * cell
+    dx2 = (c - x0) ** 2
+    dy2 = (c - y0) ** 2
+    return np.exp(-4.0 * np.log(2.0) * (dy2[:, None] + dx2[None, :]) / (fwhm * fwhm))
+
+
+def phi_grad_mosaic(n, cell, pointings, I, M, lam):
+    """One image fitted to several pointings (Sec. 1, mosaic support;
+    Sec. 2.4 items 1 and 3).  Pointing p (keys u, v, A, vis, w, x0, y0) sees
+    the image through its attenuation image A (centred on its field) with
+    its phase-tracking centre at (x0, y0):
+        V_k = e^{+2 pi i (u_k x0 + v_k y0)} sum_ij A_ij I_ij e^{-2 pi i (u_k x_j + v_k y_i)}
+    (the exponent of Eq. fft measured from the pointing's centre).  chi^2 is
+    summed over pointings (as over channels in Eq. chi2-multi); differentiating
+    1/2 w |V - V^o|^2 gives the pointing's gradient
+        A o Re sum_k w_k R_k e^{-2 pi i (u_k x0 + v_k y0)} e^{+2 pi i (u_k x_j + v_k y_i)},
+    the adjoint of the phase-shifted coefficients.  S counted once."""
+    I = _f64(I)
+    x2 = 0.0
+    gchi = np.zeros((n, n))
+    Vs, Rs = [], []
+    for p in pointings:
+        u, v = _f64(p["u"]), _f64(p["v"])
+        shift = np.exp(2j * np.pi * (u * p["x0"] + v * p["y0"]))
+        V = shift * forward(n, cell, u, v, p["A"], I)
+        x, R = chi2(V, p["vis"], p["w"])
+        gchi += adjoint(n, cell, u, v, p["A"], _f64(p["w"]) * R * np.conj(shift))
+        x2 += x
+        Vs.append(V)
+        Rs.append(R)
+    S, gS = entropy(I, M)
+    return dict(phi=x2 + lam * S, chi2=x2, S=S, grad=gchi + lam * gS, gchi2=gchi,
+                V=np.concatenate(Vs) if Vs else np.zeros(0, np.complex128),
+                R=np.concatenate(Rs) if Rs else np.zeros(0, np.complex128))

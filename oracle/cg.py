@@ -101,6 +101,29 @@ class SharedProblem(Problem):
         return out
 
 
+class MosaicProblem(SharedProblem):
+    """One image fitted to several pointings (oracle.phi_grad_mosaic): each
+    pointing's forward model carries the phase factor of its phase-tracking
+    centre (keys x0, y0) and the adjoint its conjugate."""
+
+    def __init__(self, n, cell, pointings, M, lam):
+        super().__init__(n, cell, pointings, M, lam)
+        self.shifts = [np.exp(2j * np.pi * (np.asarray(p["u"], np.float64) * p["x0"]
+                                            + np.asarray(p["v"], np.float64) * p["y0"])) for p in pointings]
+
+    def F(self, img):
+        return np.concatenate([s * forward(self.n, self.cell, c["u"], c["v"], c["A"], img)
+                               for c, s in zip(self.chans, self.shifts)])
+
+    def FH(self, coef):
+        out = np.zeros((self.n, self.n))
+        o = 0
+        for c, s, z in zip(self.chans, self.shifts, self.sizes):
+            out += adjoint(self.n, self.cell, c["u"], c["v"], c["A"], coef[o:o + z] * np.conj(s))
+            o += z
+        return out
+
+
 class GriddedProblem(Problem):
     """One channel with the gridded forward model of Sec. 2.4 / Alg. 1
     (oracle.gridded) on a grid oversample times finer than the image.
