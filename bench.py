@@ -285,7 +285,7 @@ def grid_cg(c, oversamples, prec="fp32", iters=None):
     return out
 
 
-def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
+def eval_sweep(configs, precs, reps=20, warmup=3, mode=None):
     """M1 per configuration and precision: median time of one Phi + grad Phi
     evaluation (forward, chi^2, adjoint, entropy, combine) at the P3 image,
     timed with events on the context's stream.  mode "shared" fits the first
@@ -299,12 +299,13 @@ def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
     for c in configs:
         ds = synth.make_config(c)
         img_np = synth.eval_images(ds, "P3")
-        if mode == "shared":
+        md = mode or ("shared" if ds.shared else "cube")
+        if md == "shared":
             img_np = img_np[:1]
         for prec in precs:
             if prec == "fp64" and ds.n > 512:
                 continue
-            ctx = Context.from_dataset(ds, prec, mode=mode)
+            ctx = Context.from_dataset(ds, prec, mode=md)
             img = torch.tensor(img_np, dtype=ctx.dtype, device=ctx.device)
             scal, grad = ctx.scalars(), torch.empty_like(img)
             for _ in range(warmup):
@@ -320,7 +321,7 @@ def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
                 ts.append(e0.elapsed_time(e1))
             ctx.check()
             ms = float(np.median(ts))
-            rows.append({"config": f"c{c}", "mode": mode, "precision": prec, "ms_per_eval": ms,
+            rows.append({"config": f"c{c}", "mode": md, "precision": prec, "ms_per_eval": ms,
                          "vis_pixel_evals_per_s": ds.pairs / (ms / 1e3),
                          "algorithmic_tflops": 8.0 * ds.pairs / (ms / 1e3) / 1e12,
                          "frac_of_peak": 8.0 * ds.pairs / (ms / 1e3) / 1e12 / PEAK[prec]})
@@ -329,7 +330,7 @@ def eval_sweep(configs, precs, reps=20, warmup=3, mode="cube"):
     return rows
 
 
-def cg_compare(c, precs, iters=None, mode="cube"):
+def cg_compare(c, precs, iters=None, mode=None):
     """M2: T graph-replayed projected-CG iterations from I = M in each
     precision; iterations/s, and the relative error of Phi_T and of the final
     image against the FP64 trajectory (the FP64 path is held to 1e-12 of the
@@ -358,7 +359,7 @@ def cg_compare(c, precs, iters=None, mode="cube"):
         ms = e0.elapsed_time(e1)
         phi = hist[-1, :, 0].double().sum().item()
         img = I.double().cpu().numpy()
-        row = {"config": f"c{c}", "mode": mode, "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
+        row = {"config": f"c{c}", "mode": ctx.mode, "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
                "vis_pixel_evals_per_s": ds.pairs * T / (ms / 1e3), "phi_T": phi}
         if prec == "fp64":
             ref = (phi, img)
@@ -376,7 +377,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload configuration (1..5)")
+    ap.add_argument("--config", type=int, default=2, help="workload configuration (1..6)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
     ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -385,9 +386,9 @@ def main():
                     help="only time single Phi + grad evaluations on these configurations (e.g. 1,2,3,4,5)")
     ap.add_argument("--cg-compare", type=int, default=0, metavar="CONFIG",
                     help="only run the configuration's CG iterations in every precision vs FP64")
-    ap.add_argument("--mode", default="cube", choices=["cube", "shared"],
+    ap.add_argument("--mode", default=None, choices=["cube", "shared"],
                     help="image model of --eval-sweep and --cg-compare: an image per channel, or one image "
-                         "fitted to every channel")
+                         "fitted to every channel (default: shared for the mosaic workload, cube otherwise)")
     ap.add_argument("--grid-error", default="", metavar="CONFIGS",
                     help="only compare the gridded model (Alg. 1) with the exact DFT on these configurations")
     ap.add_argument("--grid-cg", type=int, default=0, metavar="CONFIG",

@@ -142,6 +142,20 @@ int uvmem_set_weights(uvmem_ctx *ctx, int chan, const float *w);
 int uvmem_set_beam(uvmem_ctx *ctx, int chan, double fwhm_rad);
 /* General attenuation image A for the channel: float[N][N]. */
 int uvmem_set_beam_image(uvmem_ctx *ctx, int chan, const float *A);
+/* Pointing of channel `chan` in a mosaic (Sec. 1, mosaic support; Sec. 2.4
+ * items 1 and 3): the channel's Gaussian primary beam (uvmem_set_beam) is
+ * centred at (x0, y0) radians from the image centre, and its visibilities
+ * are phase-referenced to (x0, y0), so that its model is
+ *   V_k = e^{+2 pi i (u_k x0 + v_k y0)} sum_ij A_ij I_ij e^{-2 pi i (u_k x_j + v_k y_i)}.
+ * At finalize the library rotates the channel's observed visibilities by
+ * e^{-2 pi i (u_k x0 + v_k y0)} (FP64, phase reduced mod 1); chi^2 and all
+ * gradients are unchanged by it, but the channel's residuals
+ * (uvmem_get_residual) and model visibilities (uvmem_forward) are then
+ * referenced to the image centre.  A beam image from uvmem_set_beam_image is
+ * used as given.  Fitting one image to all pointings is shared mode.
+ * Default (0, 0).  UVMEM_EINVAL for a bad channel or a non-finite centre,
+ * UVMEM_ESTATE after finalize. */
+int uvmem_set_phase_centre(uvmem_ctx *ctx, int chan, double x0_rad, double y0_rad);
 /* Choose the forward model (uvmem_forward_model) before finalize.  For
  * UVMEM_FWD_GRIDDED, oversample >= 1 and L = oversample * N must be a power
  * of two in [16, 8192] ([16, 4096] for UVMEM_FP64); grad is a

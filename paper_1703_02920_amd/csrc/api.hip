@@ -252,6 +252,8 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     c->hw.resize(n_chan);
     c->hbeam.resize(n_chan);
     c->fwhm.assign(n_chan, 0.0);
+    c->cx.assign(n_chan, 0.0);
+    c->cy.assign(n_chan, 0.0);
     c->has_uv.assign(n_chan, 0);
     c->has_vis.assign(n_chan, 0);
     c->has_w.assign(n_chan, 0);
@@ -375,6 +377,16 @@ int uvmem_set_beam_image(uvmem_ctx *c, int chan, const float *A) {
         if (!std::isfinite(c->hbeam[chan][p])) return fail(c, UVMEM_EINVAL, "non-finite beam value");
     c->fwhm[chan] = 0.0;
     c->has_beam[chan] = 1;
+    return UVMEM_OK;
+}
+
+int uvmem_set_phase_centre(uvmem_ctx *c, int chan, double x0_rad, double y0_rad) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_phase_centre after finalize");
+    if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "bad channel %d", chan);
+    if (!std::isfinite(x0_rad) || !std::isfinite(y0_rad)) return fail(c, UVMEM_EINVAL, "non-finite centre");
+    c->cx[chan] = x0_rad;
+    c->cy[chan] = y0_rad;
     return UVMEM_OK;
 }
 
@@ -545,14 +557,26 @@ int uvmem_finalize(uvmem_ctx *c) {
 
     // ---- host-side conversions
     std::vector<double> a(c->ztot), bb(c->ztot);
-    std::vector<float> vo(2 * c->ztot), w(c->ztot);
+    std::vector<double> vo(2 * c->ztot);
+    std::vector<float> w(c->ztot);
     for (int ch = 0; ch < C; ++ch) {
         const int64_t o = c->off[ch];
         for (int64_t k = 0; k < c->nvis[ch]; ++k) {
             a[o + k] = c->hu[ch][k] * c->cell;
             bb[o + k] = c->hv[ch][k] * c->cell;
-            vo[2 * (o + k)] = c->hvis[ch][2 * k];
-            vo[2 * (o + k) + 1] = c->hvis[ch][2 * k + 1];
+            if (c->cx[ch] != 0.0 || c->cy[ch] != 0.0) {
+                // phase reference moved from the pointing centre to the image
+                // centre: V^o e^{-2 pi i (u x0 + v y0)}, phase reduced mod 1
+                const double ph = c->hu[ch][k] * c->cx[ch] + c->hv[ch][k] * c->cy[ch];
+                const double f = ph - std::nearbyint(ph);
+                const double cs = std::cos(2.0 * M_PI * f), sn = std::sin(2.0 * M_PI * f);
+                const double re = c->hvis[ch][2 * k], im = c->hvis[ch][2 * k + 1];
+                vo[2 * (o + k)] = re * cs + im * sn;
+                vo[2 * (o + k) + 1] = im * cs - re * sn;
+            } else {
+                vo[2 * (o + k)] = c->hvis[ch][2 * k];
+                vo[2 * (o + k) + 1] = c->hvis[ch][2 * k + 1];
+            }
             w[o + k] = c->hw[ch][k];
         }
     }
@@ -630,8 +654,8 @@ int uvmem_finalize(uvmem_ctx *c) {
             if (!c->hbeam[ch].empty()) {
                 A = c->hbeam[ch][p];
             } else {
-                const double x = (double)((int)(p % n) - n / 2) * c->cell;
-                const double y = (double)((int)(p / n) - n / 2) * c->cell;
+                const double x = (double)((int)(p % n) - n / 2) * c->cell - c->cx[ch];
+                const double y = (double)((int)(p / n) - n / 2) * c->cell - c->cy[ch];
                 A = std::exp(-4.0 * std::log(2.0) * (x * x + y * y) / (c->fwhm[ch] * c->fwhm[ch]));
             }
             if (rs == 8) reinterpret_cast<double *>(beam.data())[ch * npix + p] = A;
@@ -695,7 +719,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     };
     up(c->d_a, a.data(), a.size() * 8);
     up(c->d_b, bb.data(), bb.size() * 8);
-    up(c->d_vo, vo.data(), vo.size() * 4);
+    up(c->d_vo, vo.data(), vo.size() * 8);
     up(c->d_w, w.data(), w.size() * 4);
     up(c->d_beam, beam.data(), beam.size());
     up(c->d_fwdp, fwdp.data(), fwdp.size() * sizeof(FwdPItem));

@@ -120,6 +120,7 @@ struct uvmem_ctx {
     std::vector<std::vector<double>> hu, hv;
     std::vector<std::vector<float>> hvis, hw, hbeam;
     std::vector<double> fwhm;
+    std::vector<double> cx, cy;        // pointing centres (radians from the image centre)
     std::vector<char> has_uv, has_vis, has_w, has_beam;
 
     // layout
@@ -143,7 +144,7 @@ struct uvmem_ctx {
 
     // device buffers
     double *d_a = nullptr, *d_b = nullptr;      // u cell, v cell
-    float2 *d_vo = nullptr;
+    double2 *d_vo = nullptr;                    // observed V^o (rotated to the image centre for pointings)
     float *d_w = nullptr;
     void *d_beam = nullptr;                     // real [C][n][n]
     uvm::FwdPItem *d_fwdp = nullptr;

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
 // with_max (modes 1, 3, 4): partial[2] = max over the item of w max(|Re R|, |Im R|)
 // One visibility item (index `item`); `alpha` is the step length of mode 3.
 __device__ __forceinline__ void vis_item(const VisItem it, int item, const double2 *__restrict__ vpart,
-                                         int n_parts, long long ztot, const float2 *__restrict__ vo,
+                                         int n_parts, long long ztot, const double2 *__restrict__ vo,
                                          const float *__restrict__ w, double2 *__restrict__ R,
                                          double2 *__restrict__ Vd, double2 *__restrict__ out,
                                          double *__restrict__ vispart, int mode, int with_max, double alpha) {
@@ -151,7 +151,7 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
             if (mode == 0) {
                 out[k] = v[u];
             } else if (mode == 1) {
-                const float2 o = vo[k];
+                const double2 o = vo[k];
                 const double2 r = make_double2(v[u].x - (double)o.x, v[u].y - (double)o.y);
                 R[k] = r;
                 acc[0] += ww * (r.x * r.x + r.y * r.y);
@@ -190,7 +190,7 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
 
 __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
                                               const double2 *__restrict__ vpart, int n_parts, long long ztot,
-                                              const float2 *__restrict__ vo, const float *__restrict__ w,
+                                              const double2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
                                               double *__restrict__ vispart, const int *__restrict__ chan_img,

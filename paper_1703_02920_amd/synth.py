@@ -69,6 +69,8 @@ class Channel:
     w: np.ndarray          # float32 [Z], 1/sigma^2 (0 = flagged)
     fwhm: float            # primary beam FWHM, radians
     wavelength: float      # metres
+    x0: float = 0.0        # pointing centre (mosaics): beam centre and phase-
+    y0: float = 0.0        # tracking centre, radians from the image centre
 
     @property
     def nvis(self) -> int:
@@ -86,6 +88,7 @@ class Dataset:
     lam: float                  # entropy weight lambda
     cg_iters: int
     description: str = ""
+    shared: bool = False        # one image for all channels (mosaic pointings)
 
     @property
     def n_chan(self) -> int:
@@ -279,6 +282,7 @@ _CFG = {
     3: dict(n_ant=50, diam=3000.0, n_int=816, n=512, noise=0.005, iters=20),
     4: dict(n_ant=45, diam=1500.0, n_int=304, n=256, noise=0.005, iters=50, n_chan=64),
     5: dict(n_ant=60, diam=8000.0, n_int=2825, n=1024, noise=0.002, iters=30),
+    6: dict(n_ant=16, diam=400.0, n_int=54, n=512, noise=0.01, iters=20, n_point=23),
 }
 
 DESCRIPTIONS = {
@@ -287,6 +291,7 @@ DESCRIPTIONS = {
     3: "c3: 512x512, 1 channel, 999,600 vis (50 ant, 3 km), disk+spiral sky",
     4: "c4: 64 channels x 256x256, per-channel Z_c in [2e4, 3e5] (45 ant, 1.5 km)",
     5: "c5: 1024x1024, 1 channel, 5,000,250 vis (60 ant, 8 km)",
+    6: "c6: mosaic, one 512x512 image, 23 pointings, 149,040 vis (16 ant, 400 m), lambda 0.1",
 }
 
 WAVELENGTH = 1.3e-3
@@ -359,7 +364,7 @@ def _disk_spiral(n: int, cell: float) -> Components:
     return comp
 
 
-CACHE_VERSION = 1
+CACHE_VERSION = 2
 
 
 def make_config(c: int, channels: Optional[int] = None, cache: bool = True) -> Dataset:
@@ -388,10 +393,10 @@ def make_config(c: int, channels: Optional[int] = None, cache: bool = True) -> D
 
 def _save(ds: Dataset, path: str) -> None:
     arrs = dict(n=ds.n, cell=ds.cell, sky=ds.sky, prior_m=ds.prior_m, lam=ds.lam, cg_iters=ds.cg_iters,
-                name=ds.name, description=ds.description, n_chan=ds.n_chan)
+                name=ds.name, description=ds.description, n_chan=ds.n_chan, shared=ds.shared)
     for i, ch in enumerate(ds.channels):
         arrs.update({f"u{i}": ch.u, f"v{i}": ch.v, f"vis{i}": ch.vis, f"w{i}": ch.w,
-                     f"fwhm{i}": ch.fwhm, f"lam{i}": ch.wavelength})
+                     f"fwhm{i}": ch.fwhm, f"lam{i}": ch.wavelength, f"x0{i}": ch.x0, f"y0{i}": ch.y0})
     tmp = path + ".tmp%d.npz" % os.getpid()
     np.savez(tmp, **arrs)
     os.replace(tmp, path)
@@ -399,16 +404,19 @@ def _save(ds: Dataset, path: str) -> None:
 
 def _load(path: str) -> Dataset:
     z = np.load(path, allow_pickle=False)
-    chans = [Channel(z[f"u{i}"], z[f"v{i}"], z[f"vis{i}"], z[f"w{i}"], float(z[f"fwhm{i}"]), float(z[f"lam{i}"]))
+    chans = [Channel(z[f"u{i}"], z[f"v{i}"], z[f"vis{i}"], z[f"w{i}"], float(z[f"fwhm{i}"]), float(z[f"lam{i}"]),
+                     float(z[f"x0{i}"]), float(z[f"y0{i}"]))
              for i in range(int(z["n_chan"]))]
     return Dataset(str(z["name"]), int(z["n"]), float(z["cell"]), chans, z["sky"], float(z["prior_m"]),
-                   float(z["lam"]), int(z["cg_iters"]), str(z["description"]))
+                   float(z["lam"]), int(z["cg_iters"]), str(z["description"]), bool(z["shared"]))
 
 
 def _make_config(c: int, channels: Optional[int] = None) -> Dataset:
     if c not in _CFG:
         raise ValueError(f"unknown configuration {c}")
     p = _CFG[c]
+    if c == 6:
+        return _make_mosaic(p)
     r_layout, r_sky, r_noise, r_flag, _ = _rngs(c)
     n = p["n"]
     pos = antenna_layout(r_layout, p["n_ant"], p["diam"])
@@ -475,6 +483,57 @@ def _make_config(c: int, channels: Optional[int] = None) -> Dataset:
     return ds
 
 
+def hex_pointings(count: int, spacing: float) -> np.ndarray:
+    """The `count` points of a hexagonal grid of the given spacing nearest the
+    origin (ties broken by angle): a Nyquist-sampled mosaic pattern."""
+    pts = []
+    r = int(math.ceil(math.sqrt(count))) + 2
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            x = spacing * (a + 0.5 * b)
+            y = spacing * (math.sqrt(3.0) / 2.0) * b
+            pts.append((round(x * x + y * y, 12), round(math.atan2(y, x), 12), x, y))
+    pts.sort()
+    return np.asarray([(x, y) for _, _, x, y in pts[:count]])
+
+
+def _make_mosaic(p: dict) -> Dataset:
+    """c6: mosaic (Sec. 1, mosaic support; Sec. 2.4 items 1 and 3): one sky
+    observed in n_point pointings on a hexagonal grid spaced FWHM/2; pointing
+    p has its primary beam and its phase-tracking centre at (x_p, y_p), its
+    own hour-angle span and noise stream.  Visibilities of pointing p are
+    those of the sky seen through the beam centred at (x_p, y_p), with phases
+    relative to (x_p, y_p): the closed forms above with every component
+    position taken relative to the pointing centre."""
+    r_layout, r_sky, r_noise, _, _ = _rngs(6)
+    n = p["n"]
+    fwhm0 = beam_fwhm(WAVELENGTH)
+    cell = 5.0 * fwhm0 / n
+    pos = antenna_layout(r_layout, p["n_ant"], p["diam"])
+    bl, p_idx, q_idx = baselines(pos)
+    n_bl = bl.shape[0]
+    comp = (_gaussians(r_sky, 2, n, cell, 25.0, 40.0, 0.5, 1.0, n / 10)
+            + _gaussians(r_sky, 30, n, cell, 3.0, 15.0, 0.1, 1.0, 0.3 * n)
+            + _points(r_sky, 10, n, cell, 0.2, 1.0, 0.3 * n))
+    img = sample_sky(comp, n, cell)
+    scale = 1.0 / float(img.max())
+    comp = comp.scaled(scale)
+    sky = img * scale
+    cen = hex_pointings(p["n_point"], 0.5 * fwhm0)
+    slot_bl = np.tile(np.arange(n_bl), p["n_int"])
+    chans = []
+    for k, (xp, yp) in enumerate(cen):
+        u, v = uv_tracks(bl, p["n_int"], WAVELENGTH, ha_span_h=1.5 + 0.5 * k / max(1, len(cen) - 1))
+        rel = Components(comp.x0 - xp, comp.y0 - yp, comp.amp, comp.sig)
+        vt = sky_visibilities(rel, u, v, cell, fwhm0)
+        rn = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 6, 2000 + k])))
+        vis, w = add_noise(rn, vt, p["noise"], p_idx, q_idx, p["n_ant"], slot_bl)
+        chans.append(Channel(u, v, vis, w, fwhm0, WAVELENGTH, float(xp), float(yp)))
+    ds = Dataset("c6", n, cell, chans, sky[None], PRIOR_M, 0.1, p["iters"], DESCRIPTIONS[6], shared=True)
+    _check_nyquist(ds)
+    return ds
+
+
 def _check_nyquist(ds: Dataset) -> None:
     """Sec. 2.3: the cell must satisfy 1/Delta x >= 2 u_max."""
     for ch in ds.channels:
@@ -491,7 +550,7 @@ def _check_nyquist(ds: Dataset) -> None:
 def eval_images(ds: Dataset, which: str) -> np.ndarray:
     """Images at which a single evaluation is compared:
     P1 = M everywhere; P2 = max(true sky, M); P3 = M + U[0, 1) (seeded)."""
-    shape = (ds.n_chan, ds.n, ds.n)
+    shape = (1 if ds.shared else ds.n_chan, ds.n, ds.n)
     if which == "P1":
         return np.full(shape, ds.prior_m)
     if which == "P2":

@@ -26,7 +26,7 @@ S_PHI, S_CHI2, S_S, S_ALPHA, S_BETA, S_GNORM2, S_ALPHA_MAX, S_ITER = range(8)
 
 SYMBOLS = [
     "uvmem_create", "uvmem_destroy", "uvmem_set_uv", "uvmem_set_vis", "uvmem_set_weights",
-    "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_forward_model", "uvmem_set_prior", "uvmem_finalize",
+    "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_phase_centre", "uvmem_set_forward_model", "uvmem_set_prior", "uvmem_finalize",
     "uvmem_phi_and_grad", "uvmem_forward", "uvmem_adjoint", "uvmem_get_residual",
     "uvmem_cg_init", "uvmem_cg_step", "uvmem_cg_run", "uvmem_cg_get_state", "uvmem_cg_set_state",
     "uvmem_check", "uvmem_timing_enable", "uvmem_timing_read", "uvmem_info", "uvmem_chan_range",
@@ -60,6 +60,7 @@ def load() -> ctypes.CDLL:
         "uvmem_set_beam": [vp, ci, dbl],
         "uvmem_set_beam_image": [vp, ci, vp],
         "uvmem_set_forward_model": [vp, ci, ci, ci],
+        "uvmem_set_phase_centre": [vp, ci, dbl, dbl],
         "uvmem_set_prior": [vp, dbl, dbl],
         "uvmem_finalize": [vp],
         "uvmem_phi_and_grad": [vp, vp, vp, vp],
@@ -174,6 +175,12 @@ class Context:
         A = np.ascontiguousarray(A, np.float32)
         self._call("uvmem_set_beam_image", chan, _ptr(A))
 
+    def set_phase_centre(self, chan: int, x0: float, y0: float):
+        """Mosaic pointing: beam centre and phase-tracking centre of the
+        channel, radians from the image centre (residuals and model
+        visibilities of the channel are then referenced to the image centre)."""
+        self._call("uvmem_set_phase_centre", chan, float(x0), float(y0))
+
     def set_forward_model(self, model: str = "dft", oversample: int = 1, grad: str = "adjoint"):
         """Exact DFT ("dft") or the gridded model of Alg. 1 ("gridded": FFT of
         the image zero-padded to oversample * n, modulation, bilinear
@@ -194,9 +201,12 @@ class Context:
         return self
 
     @classmethod
-    def from_dataset(cls, ds, precision: str = "fp32", mode: str = "cube", forward: str = "dft",
+    def from_dataset(cls, ds, precision: str = "fp32", mode: Optional[str] = None, forward: str = "dft",
                      oversample: int = 1, grad: str = "adjoint", **kw) -> "Context":
-        """Context for a synthetic data set (paper_1703_02920_amd.synth)."""
+        """Context for a synthetic data set (paper_1703_02920_amd.synth); the
+        mode defaults to "shared" for a mosaic data set, else "cube"."""
+        if mode is None:
+            mode = "shared" if getattr(ds, "shared", False) else "cube"
         ctx = cls(ds.n, ds.n_chan, precision, mode=mode, **kw)
         ctx.set_forward_model(forward, oversample, grad)
         for c, ch in enumerate(ds.channels):
@@ -204,6 +214,8 @@ class Context:
             ctx.set_vis(c, ch.vis)
             ctx.set_weights(c, ch.w)
             ctx.set_beam(c, ch.fwhm)
+            if ch.x0 or ch.y0:
+                ctx.set_phase_centre(c, ch.x0, ch.y0)
         ctx.set_prior(ds.prior_m, ds.lam)
         return ctx.finalize()
 

@@ -56,7 +56,7 @@ class Problem:
     def from_dataset(ds, channels=None):
         idx = range(ds.n_chan) if channels is None else channels
         chans = [dict(u=ds.channels[c].u, v=ds.channels[c].v, vis=ds.channels[c].vis, w=ds.channels[c].w,
-                      fwhm=ds.channels[c].fwhm) for c in idx]
+                      fwhm=ds.channels[c].fwhm, x0=ds.channels[c].x0, y0=ds.channels[c].y0) for c in idx]
         return Problem(ds.n, ds.cell, chans, ds.prior_m, ds.lam)
 
     @staticmethod
@@ -76,11 +76,26 @@ class Problem:
             ctx.set_vis(c, ch["vis"])
             ctx.set_weights(c, ch["w"])
             ctx.set_beam(c, ch["fwhm"])
+            if ch.get("x0", 0.0) or ch.get("y0", 0.0):
+                ctx.set_phase_centre(c, ch["x0"], ch["y0"])
         ctx.set_prior(self.M, self.lam)
         return ctx.finalize()
 
     def beam(self, c):
-        return oracle.beam(self.n, self.cell, self.chans[c]["fwhm"])
+        ch = self.chans[c]
+        if ch.get("x0", 0.0) or ch.get("y0", 0.0):
+            return oracle.beam_at(self.n, self.cell, ch["fwhm"], ch["x0"], ch["y0"])
+        return oracle.beam(self.n, self.cell, ch["fwhm"])
+
+    def oracle_pointings(self):
+        return [dict(u=ch["u"], v=ch["v"], A=self.beam(c), vis=ch["vis"].astype(np.complex128),
+                     w=ch["w"].astype(np.float64), x0=ch.get("x0", 0.0), y0=ch.get("y0", 0.0))
+                for c, ch in enumerate(self.chans)]
+
+    def shifts(self):
+        """e^{+2 pi i (u x0 + v y0)} per visibility, channels concatenated."""
+        return np.concatenate([np.exp(2j * np.pi * (ch["u"] * ch.get("x0", 0.0) + ch["v"] * ch.get("y0", 0.0)))
+                               for ch in self.chans])
 
     def oracle_forward(self, c, img):
         ch = self.chans[c]
