@@ -199,14 +199,18 @@ def line_search(a, b, I, d, M, lam, alpha_max, max_steps=100, rtol=1e-13):
     return al, steps
 
 
-def projected_cg(prob: Problem, iters: int, I0: Optional[np.ndarray] = None):
+def projected_cg(prob: Problem, iters: int, I0: Optional[np.ndarray] = None, free: Optional[np.ndarray] = None):
     """Run `iters` iterations; returns the final image and the trajectory
-    (per iteration: phi, chi2, S, alpha, beta, |gt|^2 after the step)."""
+    (per iteration: phi, chi2, S, alpha, beta, |gt|^2 after the step).
+    `free` (optional boolean image) is a focus-of-attention region (Sec. 6):
+    pixels outside it are not free parameters and join the active set, so
+    they keep their value."""
     M, lam = prob.M, prob.lam
+    fixed = np.zeros((prob.n, prob.n), bool) if free is None else ~np.asarray(free, bool)
     I = np.full((prob.n, prob.n), M) if I0 is None else np.array(I0, np.float64)
     ev = prob.evaluate(I)
     at_bound = I <= M * (1 + BOUND_TOL)
-    act = at_bound & (ev["g"] > 0)
+    act = (at_bound & (ev["g"] > 0)) | fixed
     gt = np.where(act, 0.0, ev["g"])
     d = -gt
     traj = []
@@ -231,7 +235,7 @@ def projected_cg(prob: Problem, iters: int, I0: Optional[np.ndarray] = None):
         I = np.maximum(I + alpha * d, M)
         ev = prob.evaluate(I)
         at_bound = I <= M * (1 + BOUND_TOL)
-        act = at_bound & (ev["g"] > 0)
+        act = (at_bound & (ev["g"] > 0)) | fixed
         gt_new = np.where(act, 0.0, ev["g"])
         beta = max(0.0, float(np.sum(gt_new * (gt_new - gt))) / gg)
         d = -gt_new + beta * d
