@@ -166,6 +166,14 @@ int uvmem_set_phase_centre(uvmem_ctx *ctx, int chan, double x0_rad, double y0_ra
  * than 2^31 visibilities.  For UVMEM_FWD_DFT, oversample and grad are
  * ignored.  UVMEM_EINVAL on bad values, UVMEM_ESTATE after finalize. */
 int uvmem_set_forward_model(uvmem_ctx *ctx, int model, int oversample, int grad);
+/* Focus of attention (Sec. 6: reconstruction restricted to a region the
+ * user selects, fewer free parameters): mask of image plane `img`,
+ * uint8[N][N] (host or device; nonzero = free pixel).  NULL (the default)
+ * makes every pixel free.  Pixels outside the mask are not free parameters:
+ * the CG keeps them at their current value and uvmem_phi_and_grad reports
+ * grad Phi = 0 there; Phi, chi^2 and S still cover every pixel.  Call before
+ * finalize; UVMEM_EINVAL for a bad plane, UVMEM_ESTATE after finalize. */
+int uvmem_set_mask(uvmem_ctx *ctx, int img, const uint8_t *mask);
 /* Image floor M > 0 (the paper's G, Eq. minproblem) and entropy weight
  * lambda >= 0 (Eq. phi2). */
 int uvmem_set_prior(uvmem_ctx *ctx, double M, double lambda);
@@ -188,6 +196,31 @@ int uvmem_forward(uvmem_ctx *ctx, const void *I_dev, void *vis_dev);
 int uvmem_adjoint(uvmem_ctx *ctx, const void *coef_dev, void *img_dev);
 /* Copy the current residuals R = V^m - V^o (double[sum Z][2]) to res_dev. */
 int uvmem_get_residual(uvmem_ctx *ctx, void *res_dev);
+
+/* Natural-weight dirty image and point spread function (App. A, Eq. dirty
+ * and Eq. PSF) of every image plane, without attenuation:
+ *   dirty_ij = Re sum_k w_k V^o_k e^{+2 pi i (u_k x_j + v_k y_i)} / sum_k w_k
+ *   psf_ij   = sum_k w_k cos(2 pi (u_k x_j + v_k y_i)) / sum_k w_k
+ * with the sums over the channels of the plane (shared mode: all channels;
+ * mosaic pointings contribute in the image-centre frame).  They are
+ * computed with the adjoint in use (the exact DFT, or the gridded model
+ * under UVMEM_GRAD_ADJOINT).  Outputs [n_img][N][N] in the precision's real
+ * type; either may be NULL.  Enqueued on the stream; the direction
+ * visibilities and split-K partials serve as scratch (no CG state is
+ * touched). */
+int uvmem_dirty_image(uvmem_ctx *ctx, void *dirty_dev, void *psf_dev);
+/* Thermal noise of the dirty image, sigma_D = 1 / sqrt(sum_k w_k) per image
+ * plane (App. B), into host double[n_img]; INFINITY for a plane without
+ * weight.  UVMEM_ESTATE before finalize. */
+int uvmem_noise(const uvmem_ctx *ctx, double *sigma_d);
+/* Clean beam (App. A): an elliptical Gaussian fitted to the main lobe of
+ * each PSF plane psf_dev ([n_img][N][N] from uvmem_dirty_image): the pixels
+ * with PSF >= 1/2 connected to the centre pixel, least squares of -ln PSF as
+ * a quadratic form in the pixel offsets.  bmaj, bmin: full widths at half
+ * maximum along the major and minor axes (radians); bpa: angle of the major
+ * axis from +y towards +x in degrees, in (-90, 90]; host double[n_img] each.
+ * Synchronises the stream; UVMEM_EDOMAIN if a lobe cannot be fitted. */
+int uvmem_fit_beam(uvmem_ctx *ctx, const void *psf_dev, double *bmaj, double *bmin, double *bpa);
 
 /* Projected CG (positively constrained, Sec. 2.6).  cg_init evaluates Phi at
  * I_dev (first setting I_dev to M everywhere if init_to_floor) and sets the

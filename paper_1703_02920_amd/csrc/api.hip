@@ -75,7 +75,8 @@ void free_all(uvmem_ctx *c) {
                     c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr, c->d_gtw, c->d_gx1, c->d_ggrid, c->d_gcell,
-                    c->d_gperm, c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdlist, c->d_gdsum};
+                    c->d_gperm, c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdlist, c->d_gdsum, c->d_wscale,
+                    c->d_mask};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -253,6 +254,7 @@ int uvmem_create(uvmem_ctx **out, int n, int n_chan, int mode, int precision, vo
     c->hbeam.resize(n_chan);
     c->fwhm.assign(n_chan, 0.0);
     c->cx.assign(n_chan, 0.0);
+    c->hmask.resize(c->nimg);
     c->cy.assign(n_chan, 0.0);
     c->has_uv.assign(n_chan, 0);
     c->has_vis.assign(n_chan, 0);
@@ -387,6 +389,20 @@ int uvmem_set_phase_centre(uvmem_ctx *c, int chan, double x0_rad, double y0_rad)
     if (!std::isfinite(x0_rad) || !std::isfinite(y0_rad)) return fail(c, UVMEM_EINVAL, "non-finite centre");
     c->cx[chan] = x0_rad;
     c->cy[chan] = y0_rad;
+    return UVMEM_OK;
+}
+
+int uvmem_set_mask(uvmem_ctx *c, int img, const uint8_t *mask) {
+    if (!c) return UVMEM_EINVAL;
+    if (c->finalized) return fail(c, UVMEM_ESTATE, "set_mask after finalize");
+    if (img < 0 || img >= c->nimg) return fail(c, UVMEM_EINVAL, "bad image plane %d", img);
+    if (!mask) {
+        std::vector<unsigned char>().swap(c->hmask[img]);
+        return UVMEM_OK;
+    }
+    c->hmask[img].resize((size_t)c->n * c->n);
+    HIPCHK(c, fetch(c->hmask[img].data(), mask, (size_t)c->n * c->n));
+    for (auto &x : c->hmask[img]) x = x ? 1 : 0;
     return UVMEM_OK;
 }
 
@@ -647,6 +663,20 @@ int uvmem_finalize(uvmem_ctx *c) {
         }
     }
 
+    c->h_wsum.assign(c->nimg, 0.0);
+    for (int ch = 0; ch < C; ++ch)
+        for (int64_t k = 0; k < c->nvis[ch]; ++k) c->h_wsum[c->nimg == C ? ch : 0] += (double)c->hw[ch][k];
+    std::vector<double> wscale(c->nimg);
+    for (int m = 0; m < c->nimg; ++m) wscale[m] = c->h_wsum[m] > 0.0 ? 1.0 / c->h_wsum[m] : 0.0;
+    bool any_mask = false;
+    for (auto &mk : c->hmask) any_mask = any_mask || !mk.empty();
+    std::vector<unsigned char> mask;
+    if (any_mask) {
+        mask.assign((size_t)c->nimg * npix, 1);
+        for (int m = 0; m < c->nimg; ++m)
+            if (!c->hmask[m].empty()) std::memcpy(mask.data() + (size_t)m * npix, c->hmask[m].data(), npix);
+    }
+
     std::vector<char> beam(C * npix * rs);
     for (int ch = 0; ch < C; ++ch) {
         for (size_t p = 0; p < npix; ++p) {
@@ -695,6 +725,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_flag, 4));
     ok(dalloc(c, &c->d_hist_ptr, 1));
     ok(dalloc(c, &c->d_iter_ctr, 1));
+    ok(dalloc(c, &c->d_wscale, (size_t)c->nimg));
+    if (any_mask) ok(dalloc(c, &c->d_mask, mask.size()));
     if (gridded) {
         ok(dalloc(c, (char **)&c->d_gtw, gtw.size()));
         ok(dalloc(c, (char **)&c->d_gx1, (size_t)C * n * GL * 2 * rs));
@@ -730,6 +762,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_ivis_base, c->h_ivis_base.data(), (IMG + 1) * sizeof(int));
     up(c->d_ichan_base, c->h_ichan_base.data(), (IMG + 1) * sizeof(int));
     up(c->d_chan_img, c->h_chan_img.data(), C * sizeof(int));
+    up(c->d_wscale, wscale.data(), wscale.size() * sizeof(double));
+    if (any_mask) up(c->d_mask, mask.data(), mask.size());
     if (gridded) {
         up(c->d_gtw, gtw.data(), gtw.size());
         up(c->d_gcell, gcell.data(), gcell.size() * sizeof(int));
@@ -791,6 +825,121 @@ int uvmem_get_residual(uvmem_ctx *c, void *res) {
     if (!res && c->ztot) return fail(c, UVMEM_EINVAL, "null output");
     if (c->ztot)
         HIPCHK(c, hipMemcpyAsync(res, c->d_R, c->ztot * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+    return UVMEM_OK;
+}
+
+int uvmem_dirty_image(uvmem_ctx *c, void *dirty, void *psf) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (dirty) {
+        HIPCHK(c, launch_coef_max(c, c->d_vo, c->stream));
+        HIPCHK(c, launch_adjoint(c, c->d_vo, c->d_w, c->stream));
+        HIPCHK(c, launch_grad(c, nullptr, dirty, 3, c->stream));
+    }
+    if (psf) {
+        HIPCHK(c, launch_fill_c(c, c->d_Vd, 1.0, 0.0, c->stream));
+        HIPCHK(c, launch_coef_max(c, c->d_Vd, c->stream));
+        HIPCHK(c, launch_adjoint(c, c->d_Vd, c->d_w, c->stream));
+        HIPCHK(c, launch_grad(c, nullptr, psf, 3, c->stream));
+    }
+    return UVMEM_OK;
+}
+
+int uvmem_noise(const uvmem_ctx *c, double *sigma_d) {
+    if (!c || !sigma_d) return UVMEM_EINVAL;
+    if (!c->finalized) return UVMEM_ESTATE;
+    for (int m = 0; m < c->nimg; ++m) sigma_d[m] = c->h_wsum[m] > 0.0 ? 1.0 / std::sqrt(c->h_wsum[m]) : INFINITY;
+    return UVMEM_OK;
+}
+
+extern "C++" {
+namespace {
+// Elliptical Gaussian fitted to the main lobe of one PSF plane: the pixels
+// with PSF >= 1/2 connected to the centre pixel (4-neighbours), least
+// squares of -ln PSF = A dx^2 + B dx dy + C dy^2 (the peak is 1 at the
+// centre by construction).  Returns false when the lobe is too small or the
+// fitted form is not positive definite.
+template <typename R>
+bool fit_beam_plane(const R *psf, int n, double cell, double &bmaj, double &bmin, double &bpa) {
+    const int c0 = n / 2;
+    std::vector<char> seen((size_t)n * n, 0);
+    std::vector<int> stack{c0 * n + c0};
+    seen[(size_t)c0 * n + c0] = 1;
+    double S[3][3] = {{0}}, t[3] = {0};
+    int count = 0;
+    while (!stack.empty()) {
+        const int p = stack.back();
+        stack.pop_back();
+        const int i = p / n, j = p % n;
+        const double val = (double)psf[p];
+        if (!(val >= 0.5)) continue;
+        if (val > 0.0 && (i != c0 || j != c0)) {
+            const double dx = j - c0, dy = i - c0;
+            const double phi[3] = {dx * dx, dx * dy, dy * dy};
+            const double y = -std::log(val);
+            for (int a = 0; a < 3; ++a) {
+                t[a] += phi[a] * y;
+                for (int b = 0; b < 3; ++b) S[a][b] += phi[a] * phi[b];
+            }
+            ++count;
+        }
+        const int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+        for (auto &q : nb) {
+            if (q[0] < 0 || q[0] >= n || q[1] < 0 || q[1] >= n) continue;
+            const size_t id = (size_t)q[0] * n + q[1];
+            if (!seen[id]) { seen[id] = 1; stack.push_back((int)id); }
+        }
+    }
+    if (count < 3) return false;
+    // 3 x 3 solve by Cramer's rule
+    auto det3 = [](const double m[3][3]) {
+        return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+               m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+    };
+    const double D = det3(S);
+    if (!(std::fabs(D) > 0.0)) return false;
+    double x[3];
+    for (int k = 0; k < 3; ++k) {
+        double M[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) M[a][b] = b == k ? t[a] : S[a][b];
+        x[k] = det3(M) / D;
+    }
+    const double A = x[0], B = x[1], Cq = x[2];
+    const double mid = 0.5 * (A + Cq), rad = std::sqrt(0.25 * (A - Cq) * (A - Cq) + 0.25 * B * B);
+    const double lmin = mid - rad, lmax = mid + rad;
+    if (!(lmin > 0.0)) return false;
+    // major axis: eigenvector of the smaller eigenvalue
+    double ex = 0.5 * B, ey = lmin - A;
+    if (std::fabs(ex) + std::fabs(ey) < 1e-300 * (std::fabs(A) + std::fabs(Cq))) { ex = lmin - Cq; ey = 0.5 * B; }
+    if (std::fabs(ex) + std::fabs(ey) == 0.0) { ex = A <= Cq ? 1.0 : 0.0; ey = A <= Cq ? 0.0 : 1.0; }
+    bmaj = 2.0 * std::sqrt(std::log(2.0) / lmin) * cell;
+    bmin = 2.0 * std::sqrt(std::log(2.0) / lmax) * cell;
+    double ang = std::atan2(ex, ey) * 180.0 / M_PI;   // from +y towards +x
+    while (ang > 90.0) ang -= 180.0;
+    while (ang <= -90.0) ang += 180.0;
+    bpa = ang;
+    return true;
+}
+}  // namespace
+}  // extern "C++"
+
+int uvmem_fit_beam(uvmem_ctx *c, const void *psf, double *bmaj, double *bmin, double *bpa) {
+    int s = check_ready(c);
+    if (s) return s;
+    if (!psf || !bmaj || !bmin || !bpa) return fail(c, UVMEM_EINVAL, "null argument");
+    const size_t npix = (size_t)c->n * c->n;
+    std::vector<char> host(c->nimg * npix * real_size(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(host.data(), psf, host.size(), hipMemcpyDeviceToHost));
+    for (int m = 0; m < c->nimg; ++m) {
+        const bool okf = c->prec == UVMEM_FP64
+            ? fit_beam_plane(reinterpret_cast<const double *>(host.data()) + m * npix, c->n, c->cell, bmaj[m],
+                             bmin[m], bpa[m])
+            : fit_beam_plane(reinterpret_cast<const float *>(host.data()) + m * npix, c->n, c->cell, bmaj[m],
+                             bmin[m], bpa[m]);
+        if (!okf) return fail(c, UVMEM_EDOMAIN, "image %d: PSF main lobe cannot be fitted", m);
+    }
     return UVMEM_OK;
 }
 

@@ -163,6 +163,10 @@ struct uvmem_ctx {
     double *d_ppart = nullptr;                  // [2][nimg][n_pb][NPART] (ping-pong)
     double *d_vispart = nullptr;                // [n_visit][NPART]
     int *d_flag = nullptr;                      // [4]: domain flag, ...
+    double *d_wscale = nullptr;                 // [nimg] 1 / sum of the image's weights (0 if none)
+    unsigned char *d_mask = nullptr;            // [nimg][N][N] focus-of-attention mask, or null
+    std::vector<double> h_wsum;                 // sum of the weights per image
+    std::vector<std::vector<unsigned char>> hmask;   // staged masks per image (empty = all free)
     // gridded forward model (Sec. 2.4): twiddles e^{-2 pi i k/L}, k < L/2;
     // row-pass buffer [C][N][L] (adjoint: [C][L][N]); spectrum [C][L][L]
     // (u index major); visibilities sorted by grid cell: per-channel cell
@@ -214,6 +218,8 @@ hipError_t launch_grid_adjoint(const uvmem_ctx *c, const double2 *coef, const fl
 
 // Auxiliary kernels (k_aux.hip).
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st);
+// Fill a sum-Z complex visibility buffer with (re, im).
+hipError_t launch_fill_c(const uvmem_ctx *c, double2 *x, double re, double im, hipStream_t st);
 hipError_t launch_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st);
 hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_t st);
 // Per-item max |coef| (slot 2 of the visibility partials) for the scaled

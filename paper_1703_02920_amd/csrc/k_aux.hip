@@ -206,13 +206,17 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
 // mode 1: out = A o G + lambda (ln(I/M) + 1)            (grad Phi)
 // mode 2: as 1 into g; gt = g with zeros on the active set; partials
 //         [0] = gt_new . gt_new, [1] = gt_new . gt_old; gt updated in place.
+// mode 3: out = scale_img x G without the attenuation (dirty image / PSF).
+// With a focus-of-attention mask, pixels outside it are not free: modes 1
+// and 2 write 0 there (gradient and projected gradient).
 template <typename R, int RP, typename PT>
 __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, const int *__restrict__ slot_base,
                                                const int *__restrict__ ichan_base,
                                                const R *__restrict__ beam, const R *__restrict__ I,
                                                R *__restrict__ out, R *__restrict__ gt,
-                                               double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
-                                               double M, double Mb, double lam, int mode) {
+                                               double *__restrict__ ppart, const double *__restrict__ img_scale,
+                                               const unsigned char *__restrict__ mask, int n, int np, int n_pb,
+                                               int pb_len, double M, double Mb, double lam, int mode) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
 #pragma unroll
             for (int r = 0; r < RP; ++r) {
                 const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
-                if (okp[r]) AG[r] += (double)beam[(size_t)ch * npix + p] * Gs[r];
+                if (okp[r]) AG[r] += (mode == 3 ? 1.0 : (double)beam[(size_t)ch * npix + p]) * Gs[r];
             }
         }
 #pragma unroll
@@ -268,9 +272,11 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
             const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
             const size_t q = (size_t)c * npix + p;
             double gv = AG[r];
-            if (mode >= 1) {
+            if (mode == 3) gv *= img_scale[c];
+            if (mode == 1 || mode == 2) {
                 const double x = (double)I[q];
                 gv += lam * (log(x / M) + 1.0);
+                if (mask && !mask[q]) gv = 0.0;
             }
             const R gr = (R)gv;
             out[q] = gr;
@@ -782,12 +788,12 @@ void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, 
     const PT *gp = static_cast<const PT *>(c->d_gpart);
     if (c->pix_blk >= 4 * NTHR)
         hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
-                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n,
-                           c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
+                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
     else
         hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
-                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart, c->n,
-                           c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
+                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
 }
 
 template <typename R>
@@ -817,6 +823,20 @@ template <typename R>
 hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st);
 
 }  // namespace
+
+__global__ void k_fill_c(double2 *__restrict__ x, double2 value, long long count) {
+    long long i = (long long)blockIdx.x * NTHR + threadIdx.x;
+    const long long stride = (long long)gridDim.x * NTHR;
+    for (; i < count; i += stride) x[i] = value;
+}
+
+hipError_t launch_fill_c(const uvmem_ctx *c, double2 *x, double re, double im, hipStream_t st) {
+    const long long count = c->ztot;
+    if (count == 0) return hipSuccess;
+    const int blocks = (int)std::min<long long>((count + NTHR - 1) / NTHR, 4096);
+    hipLaunchKernelGGL(k_fill_c, dim3(blocks), dim3(NTHR), 0, st, x, make_double2(re, im), count);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st) {
     const long long count = (long long)c->nimg * c->n * c->n;

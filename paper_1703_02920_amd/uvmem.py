@@ -29,6 +29,7 @@ SYMBOLS = [
     "uvmem_set_beam", "uvmem_set_beam_image", "uvmem_set_phase_centre", "uvmem_set_forward_model", "uvmem_set_prior", "uvmem_finalize",
     "uvmem_phi_and_grad", "uvmem_forward", "uvmem_adjoint", "uvmem_get_residual",
     "uvmem_cg_init", "uvmem_cg_step", "uvmem_cg_run", "uvmem_cg_get_state", "uvmem_cg_set_state",
+    "uvmem_set_mask", "uvmem_dirty_image", "uvmem_noise", "uvmem_fit_beam",
     "uvmem_check", "uvmem_timing_enable", "uvmem_timing_read", "uvmem_info", "uvmem_chan_range",
     "uvmem_last_error", "uvmem_strerror",
 ]
@@ -61,6 +62,10 @@ def load() -> ctypes.CDLL:
         "uvmem_set_beam_image": [vp, ci, vp],
         "uvmem_set_forward_model": [vp, ci, ci, ci],
         "uvmem_set_phase_centre": [vp, ci, dbl, dbl],
+        "uvmem_set_mask": [vp, ci, vp],
+        "uvmem_dirty_image": [vp, vp, vp],
+        "uvmem_noise": [vp, ctypes.POINTER(dbl)],
+        "uvmem_fit_beam": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "uvmem_set_prior": [vp, dbl, dbl],
         "uvmem_finalize": [vp],
         "uvmem_phi_and_grad": [vp, vp, vp, vp],
@@ -181,6 +186,17 @@ class Context:
         visibilities of the channel are then referenced to the image centre)."""
         self._call("uvmem_set_phase_centre", chan, float(x0), float(y0))
 
+    def set_mask(self, img: int, mask):
+        """Focus of attention: boolean [n][n] array of the free pixels of
+        image plane `img` (None: all free)."""
+        if mask is None:
+            self._call("uvmem_set_mask", img, None)
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.shape != (self.n, self.n):
+            raise ValueError("mask must be n x n")
+        self._call("uvmem_set_mask", img, _ptr(m))
+
     def set_forward_model(self, model: str = "dft", oversample: int = 1, grad: str = "adjoint"):
         """Exact DFT ("dft") or the gridded model of Alg. 1 ("gridded": FFT of
         the image zero-padded to oversample * n, modulation, bilinear
@@ -276,6 +292,30 @@ class Context:
         out = torch.empty(max(self.ztot, 1), dtype=torch.complex128, device=self.device)[: self.ztot]
         self._call("uvmem_get_residual", _ptr(out) if self.ztot else None)
         return out
+
+    def dirty_image(self, dirty: bool = True, psf: bool = True):
+        """Natural-weight dirty image and PSF (n_img planes each; None for the
+        ones not asked for)."""
+        d = self.image() if dirty else None
+        p = self.image() if psf else None
+        self._call("uvmem_dirty_image", _ptr(d) if d is not None else None, _ptr(p) if p is not None else None)
+        return d, p
+
+    def noise(self) -> np.ndarray:
+        """sigma_D = 1 / sqrt(sum w) per image plane."""
+        out = (ctypes.c_double * self.n_img)()
+        code = self._lib.uvmem_noise(self._h, out)
+        if code != OK:
+            raise UvmemError(code, self._lib.uvmem_strerror(code).decode())
+        return np.array(out[:])
+
+    def fit_beam(self, psf: torch.Tensor):
+        """(bmaj, bmin, bpa) per image plane: FWHM in radians, angle of the
+        major axis from +y towards +x in degrees."""
+        psf = self._img(psf)
+        a, b, p = ((ctypes.c_double * self.n_img)() for _ in range(3))
+        self._call("uvmem_fit_beam", _ptr(psf), a, b, p)
+        return np.array(a[:]), np.array(b[:]), np.array(p[:])
 
     def cg_init(self, I: torch.Tensor, init_to_floor: bool = True):
         self._cg_I = self._img(I)
