@@ -330,7 +330,16 @@ def eval_sweep(configs, precs, reps=20, warmup=3, mode=None):
     return rows
 
 
-def cg_compare(c, precs, iters=None, mode=None):
+def centred_region(n, frac):
+    """Boolean n x n mask of the centred square of side frac * n."""
+    import numpy as np
+    m = np.zeros((n, n), bool)
+    h = int(round(frac * n / 2))
+    m[n // 2 - h:n // 2 + h, n // 2 - h:n // 2 + h] = True
+    return m
+
+
+def cg_compare(c, precs, iters=None, mode=None, region=None):
     """M2: T graph-replayed projected-CG iterations from I = M in each
     precision; iterations/s, and the relative error of Phi_T and of the final
     image against the FP64 trajectory (the FP64 path is held to 1e-12 of the
@@ -343,8 +352,9 @@ def cg_compare(c, precs, iters=None, mode=None):
     T = iters or ds.cg_iters
     res = {}
     ref = None
+    reg = centred_region(ds.n, region) if region else None
     for prec in ["fp64"] + [p for p in precs if p != "fp64"]:
-        ctx = Context.from_dataset(ds, prec, mode=mode)
+        ctx = Context.from_dataset(ds, prec, mode=mode, region=reg)
         I = ctx.image()
         ctx.cg_init(I, init_to_floor=True)
         ctx.cg_run(I, 1, graph=True)          # capture (and one iteration)
@@ -359,7 +369,7 @@ def cg_compare(c, precs, iters=None, mode=None):
         ms = e0.elapsed_time(e1)
         phi = hist[-1, :, 0].double().sum().item()
         img = I.double().cpu().numpy()
-        row = {"config": f"c{c}", "mode": ctx.mode, "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
+        row = {"config": f"c{c}", "mode": ctx.mode, "region_side": region, "precision": prec, "iters": T, "ms": ms, "cg_iters_per_s": T / (ms / 1e3),
                "vis_pixel_evals_per_s": ds.pairs * T / (ms / 1e3), "phi_T": phi}
         if prec == "fp64":
             ref = (phi, img)
@@ -394,6 +404,8 @@ def main():
     ap.add_argument("--grid-cg", type=int, default=0, metavar="CONFIG",
                     help="only run CG with the exact and the gridded models and score the images exactly")
     ap.add_argument("--oversample", default="1,2,4", help="gridded-model oversampling factors")
+    ap.add_argument("--region", type=float, default=0.0,
+                    help="--cg-compare with a focus-of-attention region: centred square of this side fraction")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -413,7 +425,7 @@ def main():
         grid_cg(args.grid_cg, [int(x) for x in args.oversample.split(",")])
         return
     if args.cg_compare:
-        cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"], mode=args.mode)
+        cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"], mode=args.mode, region=args.region or None)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

@@ -171,7 +171,10 @@ int uvmem_set_forward_model(uvmem_ctx *ctx, int model, int oversample, int grad)
  * uint8[N][N] (host or device; nonzero = free pixel).  NULL (the default)
  * makes every pixel free.  Pixels outside the mask are not free parameters:
  * the CG keeps them at their current value and uvmem_phi_and_grad reports
- * grad Phi = 0 there; Phi, chi^2 and S still cover every pixel.  Call before
+ * grad Phi = 0 there; Phi, chi^2 and S still cover every pixel.  With the
+ * exact DFT, the CG's direction forward model visits only the image blocks
+ * that meet a mask, and gradients only the pixel tiles that meet one
+ * (work lists built at finalize for the union of the planes' masks).  Call before
  * finalize; UVMEM_EINVAL for a bad plane, UVMEM_ESTATE after finalize. */
 int uvmem_set_mask(uvmem_ctx *ctx, int img, const uint8_t *mask);
 /* Image floor M > 0 (the paper's G, Eq. minproblem) and entropy weight
@@ -257,8 +260,9 @@ int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *coun
  * tile side, adjoint split-K slots, forward workgroups, adjoint workgroups,
  * visibility items, device bytes held, pixel blocks per channel, pixels per
  * pixel block, visibilities per visibility item, image planes n_img, forward
- * model, gridded-model grid side L (0 for the DFT), gradient model.
- * uvmem_chan_range gives a channel's offset into the concatenated
+ * model, gridded-model grid side L (0 for the DFT), gradient model,
+ * forward and adjoint workgroups of the focus-of-attention region's work
+ * lists (0 without a region).  uvmem_chan_range gives a channel's offset into the concatenated
  * visibility arrays and its count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);
 int uvmem_chan_range(const uvmem_ctx *ctx, int chan, int64_t *offset, int64_t *nvis);

@@ -76,7 +76,7 @@ void free_all(uvmem_ctx *c) {
                     c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
                     c->d_flag, c->d_hist_ptr, c->d_iter_ctr, c->d_gtw, c->d_gx1, c->d_ggrid, c->d_gcell,
                     c->d_gperm, c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdlist, c->d_gdsum, c->d_wscale,
-                    c->d_mask};
+                    c->d_mask, c->d_fwdp_m, c->d_adj_m, c->d_slot_base_m};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -105,7 +105,9 @@ void harvest(uvmem_ctx *c) {
 
 // Launch the forward (which = 0) or adjoint (which = 1) DFT, bracketed by
 // events when timing is on.
-hipError_t timed_dft(uvmem_ctx *c, int which, const void *bop, const double2 *coef, const float *w) {
+// flag: the forward operand is a CG direction / the adjoint is a gradient
+// (region-restricted work lists under a focus-of-attention mask).
+hipError_t timed_dft(uvmem_ctx *c, int which, const void *bop, const double2 *coef, const float *w, int flag) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if (c->ev_pool.size() < 2) {
@@ -118,7 +120,7 @@ hipError_t timed_dft(uvmem_ctx *c, int which, const void *bop, const double2 *co
             (void)hipEventRecord(e0, c->stream);
         }
     }
-    hipError_t e = which == 0 ? launch_forward(c, bop, c->stream) : launch_adjoint(c, coef, w, c->stream);
+    hipError_t e = which == 0 ? launch_forward(c, bop, c->stream, flag) : launch_adjoint(c, coef, w, c->stream, flag);
     if (e0) {
         (void)hipEventRecord(e1, c->stream);
         c->pend[which].push_back({e0, e1});
@@ -454,77 +456,122 @@ int uvmem_finalize(uvmem_ctx *c) {
 
     // ---- work tables
     std::vector<VisItem> vis;
-    std::vector<AdjItem> adj;
-    c->h_slot_base.assign(C + 1, 0);
     c->h_vis_base.assign(C + 1, 0);
-    const int tiles = c->adj_nt * c->adj_nt;
-    // ---- adjoint: split-K chunks.  Resident slots: 256 CUs x (1 workgroup,
-    // or 2 for the split kernel on 128 x 128 tiles).  A channel of Z_c
-    // visibilities is cut into ceil(Z_c / klen) equal chunks (multiples of 16)
-    // and every chunk covers all pixel tiles; the split kernel's chunks are
-    // also bounded because it sums a chunk in FP32 only.
-    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
-    const int adj_slots = (split && c->adj_tt == 128) ? 512 : 256;
-    auto adj_klen = [&](int64_t target) {
-        int64_t klen = (c->ztot * tiles + target - 1) / target;
-        klen = std::max<int64_t>(klen, ADJ_KMIN);
-        if (split) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
-        return ((klen + 15) / 16) * 16;
-    };
-    auto chunks_of = [&](int64_t nv, int64_t klen, int64_t &len) {
-        const int64_t nch = (nv + klen - 1) / klen;
-        len = nch ? ((nv + nch - 1) / nch + 15) / 16 * 16 : 0;
-        return nch;
-    };
-    constexpr double ADJ_OVERHEAD = 64.0;   // per-workgroup set-up and tile store, in visibilities
-    int adj_m = pick_schedule(adj_slots, [&](int m) {
-        std::vector<double> w;
-        const int64_t klen = adj_klen((int64_t)adj_slots * m);
-        for (int ch = 0; ch < C; ++ch) {
-            int64_t len;
-            const int64_t nch = chunks_of(c->nvis[ch], klen, len);
-            for (int64_t x = 0; x < nch; ++x) {
-                const double z = (double)std::min<int64_t>(len, c->nvis[ch] - x * len);
-                for (int t = 0; t < tiles; ++t) w.push_back(z + ADJ_OVERHEAD);
-            }
-        }
-        return w;
-    });
-    int64_t klen = adj_klen((int64_t)adj_slots * adj_m);
-    if (const char *env = std::getenv("UVMEM_ADJ_WGS")) klen = adj_klen(std::max(1L, std::atol(env)));
-    // the gridded model's own adjoint writes one plane per channel
-    const bool grid_adj = c->fwd_model == UVMEM_FWD_GRIDDED && c->grad_model == UVMEM_GRAD_ADJOINT;
-    int slot = 0;
     for (int ch = 0; ch < C; ++ch) {
         const int64_t b = c->off[ch], e = c->off[ch + 1];
         c->h_vis_base[ch] = (int)vis.size();
         for (int64_t k = b; k < e; k += c->vis_blk)
             vis.push_back(VisItem{ch, 0, (long long)k, (long long)std::min<int64_t>(k + c->vis_blk, e)});
-        c->h_slot_base[ch] = slot;
-        if (grid_adj) {
-            ++slot;
-            continue;
-        }
-        int64_t len;
-        chunks_of(e - b, klen, len);
-        for (int64_t k = b; k < e; k += len, ++slot)
-            for (int ti = 0; ti < c->adj_nt; ++ti)
-                for (int tj = 0; tj < c->adj_nt; ++tj)
-                    adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k, (long long)std::min<int64_t>(k + len, e)});
     }
-    c->h_slot_base[C] = slot;
-    // longest chunks first (the slot of an item fixes its place in the
-    // split-K sum, so the order of the items is free)
-    std::stable_sort(adj.begin(), adj.end(), [](const AdjItem &x, const AdjItem &y) {
-        return x.kend - x.kbeg > y.kend - y.kbeg;
-    });
+    c->h_vis_base[C] = (int)vis.size();
+    // focus of attention: the union of the image planes' masks decides which
+    // forward image blocks and adjoint pixel tiles the CG's direction
+    // forward model and gradient adjoint visit (outside it the direction is
+    // zero and the gradient is not needed)
+    std::vector<unsigned char> umask;
+    bool region = false;
+    if (c->fwd_model == UVMEM_FWD_DFT) {
+        umask.assign((size_t)n * n, 0);
+        for (int m = 0; m < c->nimg; ++m) {
+            if (c->hmask[m].empty()) { umask.assign((size_t)n * n, 1); break; }
+            for (size_t p = 0; p < (size_t)n * n; ++p) umask[p] |= c->hmask[m][p];
+        }
+        for (size_t p = 0; p < umask.size() && !region; ++p) region = !umask[p];
+    }
+    auto rect_used = [&](int r0, int r1, int c0, int c1) {
+        for (int i = r0; i < std::min(r1, n); ++i)
+            for (int j = c0; j < std::min(c1, n); ++j)
+                if (umask[(size_t)i * n + j]) return true;
+        return false;
+    };
+    // ---- adjoint: split-K chunks.  Resident slots: 256 CUs x (1 workgroup,
+    // or 2 for the split kernel on 128 x 128 tiles).  A channel of Z_c
+    // visibilities is cut into ceil(Z_c / klen) equal chunks (multiples of 16)
+    // and every chunk covers the used pixel tiles; the split kernel's chunks
+    // are also bounded because it sums a chunk in FP32 only.
+    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
+    const int adj_slots = (split && c->adj_tt == 128) ? 512 : 256;
+    auto chunks_of = [&](int64_t nv, int64_t klen, int64_t &len) {
+        const int64_t nch = (nv + klen - 1) / klen;
+        len = nch ? ((nv + nch - 1) / nch + 15) / 16 * 16 : 0;
+        return nch;
+    };
+    // the gridded model's own adjoint writes one plane per channel
+    const bool grid_adj = c->fwd_model == UVMEM_FWD_GRIDDED && c->grad_model == UVMEM_GRAD_ADJOINT;
+    auto build_adj = [&](const std::vector<char> &tile_used, std::vector<AdjItem> &adj,
+                         std::vector<int> &slot_base) {
+        int tiles = 0;
+        for (char t : tile_used) tiles += t ? 1 : 0;
+        auto adj_klen = [&](int64_t target) {
+            int64_t klen = (c->ztot * std::max(tiles, 1) + target - 1) / target;
+            klen = std::max<int64_t>(klen, ADJ_KMIN);
+            if (split) klen = std::min<int64_t>(klen, ADJ_KMAX_SPLIT);
+            return ((klen + 15) / 16) * 16;
+        };
+        constexpr double ADJ_OVERHEAD = 64.0;   // per-workgroup set-up and tile store, in visibilities
+        const int adj_m = pick_schedule(adj_slots, [&](int m) {
+            std::vector<double> w;
+            const int64_t klen = adj_klen((int64_t)adj_slots * m);
+            for (int ch = 0; ch < C; ++ch) {
+                int64_t len;
+                const int64_t nch = chunks_of(c->nvis[ch], klen, len);
+                for (int64_t x = 0; x < nch; ++x) {
+                    const double z = (double)std::min<int64_t>(len, c->nvis[ch] - x * len);
+                    for (int t = 0; t < tiles; ++t) w.push_back(z + ADJ_OVERHEAD);
+                }
+            }
+            return w;
+        });
+        int64_t klen = adj_klen((int64_t)adj_slots * adj_m);
+        if (const char *env = std::getenv("UVMEM_ADJ_WGS")) klen = adj_klen(std::max(1L, std::atol(env)));
+        slot_base.assign(C + 1, 0);
+        int slot = 0;
+        for (int ch = 0; ch < C; ++ch) {
+            const int64_t b = c->off[ch], e = c->off[ch + 1];
+            slot_base[ch] = slot;
+            if (grid_adj) {
+                ++slot;
+                continue;
+            }
+            int64_t len;
+            chunks_of(e - b, klen, len);
+            for (int64_t k = b; k < e; k += len, ++slot)
+                for (int ti = 0; ti < c->adj_nt; ++ti)
+                    for (int tj = 0; tj < c->adj_nt; ++tj)
+                        if (tile_used[(size_t)ti * c->adj_nt + tj])
+                            adj.push_back(AdjItem{ch, ti, tj, slot, (long long)k,
+                                                  (long long)std::min<int64_t>(k + len, e)});
+        }
+        slot_base[C] = slot;
+        // longest chunks first (the slot of an item fixes its place in the
+        // split-K sum, so the order of the items is free)
+        std::stable_sort(adj.begin(), adj.end(), [](const AdjItem &x, const AdjItem &y) {
+            return x.kend - x.kbeg > y.kend - y.kbeg;
+        });
+        return slot;
+    };
+    std::vector<AdjItem> adj, adj_m;
+    std::vector<int> slot_base_m;
+    const int ntile = c->adj_nt * c->adj_nt;
+    int slot = build_adj(std::vector<char>(ntile, 1), adj, c->h_slot_base);
+    int slots_m = 0;
+    if (region) {
+        std::vector<char> used(ntile, 0);
+        for (int ti = 0; ti < c->adj_nt; ++ti)
+            for (int tj = 0; tj < c->adj_nt; ++tj)
+                used[(size_t)ti * c->adj_nt + tj] =
+                    rect_used(ti * c->adj_tt, (ti + 1) * c->adj_tt, tj * c->adj_tt, (tj + 1) * c->adj_tt);
+        slots_m = build_adj(used, adj_m, slot_base_m);
+    }
     // ---- persistent forward: one resident workgroup per CU; the
     // (channel, image block) pairs are shared by g_c workgroups each, with
     // g_c = ceil(Z_c / L) for the per-workgroup visibility count L chosen by
-    // the same simulation
-    std::vector<FwdPItem> fwdp;
-    if (c->ztot > 0 && c->fwd_model == UVMEM_FWD_DFT) {
-        const int nblk = c->n_ib * c->n_jb;
+    // the same simulation.  part_of[b] is the forward partial that block b
+    // writes, -1 for a block left out.
+    auto build_fwd = [&](const std::vector<int> &part_of, std::vector<FwdPItem> &fwdp) {
+        int nblk = 0;
+        for (int x : part_of) nblk += x >= 0 ? 1 : 0;
+        if (c->ztot == 0 || nblk == 0) return;
         constexpr double FWD_OVERHEAD = 256.0;   // image-block staging, in visibilities
         auto shares = [&](int64_t wgs, int ch) {
             const int64_t nv = c->nvis[ch];
@@ -548,17 +595,40 @@ int uvmem_finalize(uvmem_ctx *c) {
             if (c->nvis[ch] == 0) continue;
             const int64_t g = shares(wgs, ch);
             for (int ib = 0; ib < c->n_ib; ++ib)
-                for (int jb = 0; jb < c->n_jb; ++jb)
+                for (int jb = 0; jb < c->n_jb; ++jb) {
+                    const int part = part_of[(size_t)ib * c->n_jb + jb];
+                    if (part < 0) continue;
                     for (int64_t x = 0; x < g; ++x)
-                        fwdp.push_back(FwdPItem{ch, ib, jb, ib * c->n_jb + jb, (int)x, (int)g,
-                                                (long long)c->off[ch], (long long)c->off[ch + 1]});
+                        fwdp.push_back(FwdPItem{ch, ib, jb, part, (int)x, (int)g, (long long)c->off[ch],
+                                                (long long)c->off[ch + 1]});
+                }
         }
         std::stable_sort(fwdp.begin(), fwdp.end(), [&](const FwdPItem &x, const FwdPItem &y) {
             return (double)c->nvis[x.chan] / x.nwg > (double)c->nvis[y.chan] / y.nwg;
         });
+    };
+    std::vector<FwdPItem> fwdp, fwdp_m;
+    c->n_fparts_m = 0;
+    if (c->fwd_model == UVMEM_FWD_DFT) {
+        const int nblk = c->n_ib * c->n_jb;
+        std::vector<int> part_of(nblk);
+        for (int b = 0; b < nblk; ++b) part_of[b] = b;
+        build_fwd(part_of, fwdp);
+        if (region) {
+            for (int ib = 0; ib < c->n_ib; ++ib)
+                for (int jb = 0; jb < c->n_jb; ++jb)
+                    part_of[(size_t)ib * c->n_jb + jb] =
+                        rect_used(ib * c->ib_rows, (ib + 1) * c->ib_rows, jb * c->jb_cols, (jb + 1) * c->jb_cols)
+                            ? c->n_fparts_m++
+                            : -1;
+            build_fwd(part_of, fwdp_m);
+        }
     }
     c->n_fwdp = (int)fwdp.size();
-    c->h_vis_base[C] = (int)vis.size();
+    c->n_fwdp_m = (int)fwdp_m.size();
+    c->n_adj_m = (int)adj_m.size();
+    c->n_slots_m = slots_m;
+    c->has_region = region;
     // image planes: channel ranges, visibility-item ranges, channel -> image
     const int IMG = c->nimg;
     c->h_ichan_base.assign(IMG + 1, 0);
@@ -712,7 +782,13 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_R, c->ztot));
     ok(dalloc(c, &c->d_Vd, c->ztot));
     ok(dalloc(c, &c->d_vpart, (size_t)c->n_fparts * c->ztot));
-    ok(dalloc(c, (char **)&c->d_gpart, (size_t)c->n_slots * np * np * (split ? sizeof(float) : sizeof(double))));
+    ok(dalloc(c, (char **)&c->d_gpart,
+              (size_t)std::max(c->n_slots, c->n_slots_m) * np * np * (split ? sizeof(float) : sizeof(double))));
+    if (region) {
+        ok(dalloc(c, &c->d_fwdp_m, fwdp_m.size()));
+        ok(dalloc(c, &c->d_adj_m, adj_m.size()));
+        ok(dalloc(c, &c->d_slot_base_m, C + 1));
+    }
     ok(dalloc(c, (char **)&c->d_bop, (size_t)C * np * np * rs));
     ok(dalloc(c, (char **)&c->d_g, IMG * npix * rs));
     ok(dalloc(c, (char **)&c->d_gt, IMG * npix * rs));
@@ -763,6 +839,11 @@ int uvmem_finalize(uvmem_ctx *c) {
     up(c->d_ichan_base, c->h_ichan_base.data(), (IMG + 1) * sizeof(int));
     up(c->d_chan_img, c->h_chan_img.data(), C * sizeof(int));
     up(c->d_wscale, wscale.data(), wscale.size() * sizeof(double));
+    if (region) {
+        up(c->d_fwdp_m, fwdp_m.data(), fwdp_m.size() * sizeof(FwdPItem));
+        up(c->d_adj_m, adj_m.data(), adj_m.size() * sizeof(AdjItem));
+        up(c->d_slot_base_m, slot_base_m.data(), (C + 1) * sizeof(int));
+    }
     if (any_mask) up(c->d_mask, mask.data(), mask.size());
     if (gridded) {
         up(c->d_gtw, gtw.data(), gtw.size());
@@ -791,9 +872,9 @@ int uvmem_phi_and_grad(uvmem_ctx *c, const void *I, void *grad, double *scal) {
     if (s) return s;
     if (!I || !grad) return fail(c, UVMEM_EINVAL, "null image or gradient");
     HIPCHK(c, launch_prologue(c, I, 1, c->stream));
-    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr, 0));
     HIPCHK(c, launch_vis_sum(c, 1, nullptr, c->stream));
-    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w));
+    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w, 1));
     HIPCHK(c, launch_grad(c, I, grad, 1, c->stream));
     HIPCHK(c, launch_chan_phi(c, scal, c->stream));
     return UVMEM_OK;
@@ -804,7 +885,7 @@ int uvmem_forward(uvmem_ctx *c, const void *I, void *vis) {
     if (s) return s;
     if (!I || (!vis && c->ztot)) return fail(c, UVMEM_EINVAL, "null image or output");
     HIPCHK(c, launch_prologue(c, I, 0, c->stream));
-    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr, 0));
     HIPCHK(c, launch_vis_sum(c, 0, (double2 *)vis, c->stream));
     return UVMEM_OK;
 }
@@ -814,7 +895,7 @@ int uvmem_adjoint(uvmem_ctx *c, const void *coef, void *img) {
     if (s) return s;
     if ((!coef && c->ztot) || !img) return fail(c, UVMEM_EINVAL, "null coefficients or output");
     HIPCHK(c, launch_coef_max(c, (const double2 *)coef, c->stream));
-    HIPCHK(c, timed_dft(c, 1, nullptr, (const double2 *)coef, nullptr));
+    HIPCHK(c, timed_dft(c, 1, nullptr, (const double2 *)coef, nullptr, 0));
     HIPCHK(c, launch_grad(c, nullptr, img, 0, c->stream));
     return UVMEM_OK;
 }
@@ -962,9 +1043,9 @@ int uvmem_cg_step(uvmem_ctx *c, void *I, double *scal) {
     if (!c->cg_ready) return fail(c, UVMEM_ESTATE, "cg_step before cg_init");
     if (I != c->cg_I) return fail(c, UVMEM_EINVAL, "cg_step image differs from cg_init's");
     HIPCHK(c, launch_cg_phase(c, I, scal, 0, c->stream));
-    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr));
+    HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr, 1));
     HIPCHK(c, launch_cg_phase(c, I, scal, 1, c->stream));
-    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w));
+    HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w, 1));
     HIPCHK(c, launch_cg_phase(c, I, scal, 2, c->stream));
     return UVMEM_OK;
 }
@@ -1127,7 +1208,8 @@ int uvmem_info(const uvmem_ctx *c, int64_t *out, int nout) {
     const int64_t vals[] = {c->n, c->np, c->nchan, c->prec, c->ztot, c->n_fparts, c->adj_tt, c->n_slots,
                             c->n_fwdp, c->n_adj, c->n_visit, (int64_t)c->bytes_device, c->n_pb, c->pix_blk,
                             c->vis_blk, c->nimg, c->fwd_model,
-                            c->fwd_model == UVMEM_FWD_GRIDDED ? (int64_t)1 << c->grid_lg : 0, c->grad_model};
+                            c->fwd_model == UVMEM_FWD_GRIDDED ? (int64_t)1 << c->grid_lg : 0, c->grad_model,
+                            c->n_fwdp_m, c->n_adj_m};
     const int nv = (int)(sizeof vals / sizeof vals[0]);
     for (int i = 0; i < nout && i < nv; ++i) out[i] = vals[i];
     return UVMEM_OK;

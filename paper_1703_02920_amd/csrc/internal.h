@@ -150,6 +150,15 @@ struct uvmem_ctx {
     uvm::FwdPItem *d_fwdp = nullptr;
     int n_fwdp = 0;
     uvm::AdjItem *d_adj = nullptr;
+    // focus of attention: work lists restricted to the region (the CG's
+    // direction forward model and gradient adjoint), their partial count and
+    // split-K slot table
+    bool has_region = false;
+    uvm::FwdPItem *d_fwdp_m = nullptr;
+    int n_fwdp_m = 0, n_fparts_m = 0;
+    uvm::AdjItem *d_adj_m = nullptr;
+    int n_adj_m = 0, n_slots_m = 0;
+    int *d_slot_base_m = nullptr;
     uvm::VisItem *d_vis = nullptr;
     int *d_slot_base = nullptr, *d_vis_base = nullptr;
     int *d_ivis_base = nullptr, *d_ichan_base = nullptr, *d_chan_img = nullptr;
@@ -206,10 +215,14 @@ namespace uvm {
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error; every launch goes to `st`.
 
-// Forward DFT: vpart[ib][k] = sum over the i-block ib of E_v T (see k_dft.hip).
-hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st);
+// Forward DFT: vpart[part][k] = the image block's share of V_k (see
+// k_dft.hip).  dir != 0: the operand is a CG direction, zero outside a focus
+// region, and only the region's blocks are visited (compact partials).
+hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st, int dir = 0);
 // Adjoint: gpart[slot] tiles of Re F^H (w coef) without the beam factor.
-hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st);
+// grad != 0: a gradient, needed inside a focus region only (its own tiles
+// and split-K slot table).
+hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, int grad = 0);
 // Gridded forward model and its exact adjoint (k_grid.hip): the forward
 // writes the single forward partial vpart[0][k]; the adjoint writes the
 // channel's plane gpart[slot_base[c]] (one slot per channel).

@@ -786,12 +786,14 @@ hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipSt
 template <typename R, typename PT>
 void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
     const PT *gp = static_cast<const PT *>(c->d_gpart);
+    // gradients (modes 1, 2) follow the region-restricted adjoint and its slots
+    const int *slots = (mode == 1 || mode == 2) && c->has_region ? c->d_slot_base_m : c->d_slot_base;
     if (c->pix_blk >= 4 * NTHR)
-        hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
+        hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, slots,
                            c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
                            c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
     else
-        hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, c->d_slot_base,
+        hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, slots,
                            c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
                            c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
 }
@@ -915,9 +917,9 @@ hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase,
 hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
     hipError_t e;
     if ((e = launch_cg_phase(c, I, user, 0, st)) != hipSuccess) return e;
-    if ((e = launch_forward(c, c->d_bop, st)) != hipSuccess) return e;
+    if ((e = launch_forward(c, c->d_bop, st, 1)) != hipSuccess) return e;
     if ((e = launch_cg_phase(c, I, user, 1, st)) != hipSuccess) return e;
-    if ((e = launch_adjoint(c, c->d_R, c->d_w, st)) != hipSuccess) return e;
+    if ((e = launch_adjoint(c, c->d_R, c->d_w, st, 1)) != hipSuccess) return e;
     return launch_cg_phase(c, I, user, 2, st);
 }
 
@@ -929,7 +931,8 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
     if (phase == 1) {
         // 5. Vd and the quadratic coefficients a, b of chi^2 along d
         if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart, c->n_fparts,
+            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart,
+                               c->has_region ? c->n_fparts_m : c->n_fparts,
                                (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
                                c->d_scal, c->d_vispart, c->d_chan_img, 2, 0);
         // 6-7. line search: pass 0 initialises the state (from the visibility

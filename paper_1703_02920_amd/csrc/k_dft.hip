@@ -968,49 +968,50 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
 }
 
 template <typename T>
-hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st) {
-    if (c->n_fwdp == 0) return hipSuccess;
-    const dim3 grid(c->n_fwdp), blk(512);
+hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st, const FwdPItem *items, int nitems) {
+    if (nitems == 0) return hipSuccess;
+    const dim3 grid(nitems), blk(512);
     if constexpr (sizeof(T) == 4) {
         if (c->ib_rows == 128 && c->jb_cols == 256) {
-            hipLaunchKernelGGL((k_forward_p<T, 128, 256>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+            hipLaunchKernelGGL((k_forward_p<T, 128, 256>), grid, blk, 0, st, items, c->d_a, c->d_b,
                                (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
             return hipGetLastError();
         }
         if (c->ib_rows == 128 && c->jb_cols == 128) {
-            hipLaunchKernelGGL((k_forward_p<T, 128, 128>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b,
+            hipLaunchKernelGGL((k_forward_p<T, 128, 128>), grid, blk, 0, st, items, c->d_a, c->d_b,
                                (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, (const T *)bop,
+    hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, items, c->d_a, c->d_b, (const T *)bop,
                        c->d_vpart, c->n, c->np, (long long)c->ztot);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
-    if (c->n_adj == 0) return hipSuccess;
+hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st,
+                        const AdjItem *items, int nitems) {
+    if (nitems == 0) return hipSuccess;
     if (c->adj_tt == 128)
-        hipLaunchKernelGGL((k_adjoint<T, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
+        hipLaunchKernelGGL((k_adjoint<T, 64>), dim3(nitems), dim3(256), 0, st, items, c->d_a,
                            c->d_b, coef, w, (double *)c->d_gpart, c->n, c->np);
     else
-        hipLaunchKernelGGL((k_adjoint<T, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a,
+        hipLaunchKernelGGL((k_adjoint<T, 32>), dim3(nitems), dim3(256), 0, st, items, c->d_a,
                            c->d_b, coef, w, (double *)c->d_gpart, c->n, c->np);
     return hipGetLastError();
 }
 
 template <typename H, int NV>
-hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st) {
-    const dim3 grid(c->n_fwdp), blk(512);
+hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st, const FwdPItem *items, int nitems) {
+    const dim3 grid(nitems), blk(512);
     if (c->ib_rows == 128 && c->jb_cols == 256)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     else if (c->ib_rows == 128 && c->jb_cols == 128)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     else
-        hipLaunchKernelGGL((k_forward_h16p<H, 64, 64, NV>), grid, blk, 0, st, c->d_fwdp, c->d_a, c->d_b, B,
+        hipLaunchKernelGGL((k_forward_h16p<H, 64, 64, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     return hipGetLastError();
 }
@@ -1018,43 +1019,52 @@ hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st) {
 // One 16-visibility group per wave tile: two groups (one LDS image read for
 // twice the matrix-core work) measured slower on 256^2 (register pressure).
 template <typename H>
-hipError_t fwd_h16(const uvmem_ctx *c, const void *bop, hipStream_t st) {
-    if (c->n_fwdp == 0) return hipSuccess;
-    return fwd_h16_t<H, 1>(c, reinterpret_cast<const float *>(bop), st);
+hipError_t fwd_h16(const uvmem_ctx *c, const void *bop, hipStream_t st, const FwdPItem *items, int nitems) {
+    if (nitems == 0) return hipSuccess;
+    return fwd_h16_t<H, 1>(c, reinterpret_cast<const float *>(bop), st, items, nitems);
 }
 
 template <typename H>
-hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
-    if (c->n_adj == 0) return hipSuccess;
+hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, const AdjItem *items,
+                   int nitems) {
+    if (nitems == 0) return hipSuccess;
     if (c->adj_tt == 256)
-        hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(c->n_adj), dim3(512), 0, st, c->d_adj, c->d_a, c->d_b,
+        hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else if (c->adj_tt == 128)
-        hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+        hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(nitems), dim3(256), 0, st, items, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else
-        hipLaunchKernelGGL((k_adjoint_h16<H, 32>), dim3(c->n_adj), dim3(256), 0, st, c->d_adj, c->d_a, c->d_b,
+        hipLaunchKernelGGL((k_adjoint_h16<H, 32>), dim3(nitems), dim3(256), 0, st, items, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st) {
+hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st, int dir) {
     if (c->fwd_model == UVMEM_FWD_GRIDDED) return launch_grid_forward(c, bop, st);
-    if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st);
-    if (c->prec == UVMEM_BF16X3) return fwd_h16<__bf16>(c, bop, st);
-    if (c->prec == UVMEM_FP16X3) return fwd_h16<_Float16>(c, bop, st);
-    return fwd_dispatch<float>(c, bop, st);
+    // the direction of a region-restricted CG is zero outside the region
+    const bool rg = dir && c->has_region;
+    const FwdPItem *it = rg ? c->d_fwdp_m : c->d_fwdp;
+    const int ni = rg ? c->n_fwdp_m : c->n_fwdp;
+    if (c->prec == UVMEM_FP64) return fwd_dispatch<double>(c, bop, st, it, ni);
+    if (c->prec == UVMEM_BF16X3) return fwd_h16<__bf16>(c, bop, st, it, ni);
+    if (c->prec == UVMEM_FP16X3) return fwd_h16<_Float16>(c, bop, st, it, ni);
+    return fwd_dispatch<float>(c, bop, st, it, ni);
 }
 
-hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
+hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, int grad) {
     if (c->fwd_model == UVMEM_FWD_GRIDDED && c->grad_model == UVMEM_GRAD_ADJOINT)
         return launch_grid_adjoint(c, coef, w, st);
-    if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st);
-    if (c->prec == UVMEM_BF16X3) return adj_h16<__bf16>(c, coef, w, st);
-    if (c->prec == UVMEM_FP16X3) return adj_h16<_Float16>(c, coef, w, st);
-    return adj_dispatch<float>(c, coef, w, st);
+    // a gradient of a region-restricted problem is needed inside the region only
+    const bool rg = grad && c->has_region;
+    const AdjItem *it = rg ? c->d_adj_m : c->d_adj;
+    const int ni = rg ? c->n_adj_m : c->n_adj;
+    if (c->prec == UVMEM_FP64) return adj_dispatch<double>(c, coef, w, st, it, ni);
+    if (c->prec == UVMEM_BF16X3) return adj_h16<__bf16>(c, coef, w, st, it, ni);
+    if (c->prec == UVMEM_FP16X3) return adj_h16<_Float16>(c, coef, w, st, it, ni);
+    return adj_dispatch<float>(c, coef, w, st, it, ni);
 }
 
 }  // namespace uvm

@@ -218,9 +218,10 @@ class Context:
 
     @classmethod
     def from_dataset(cls, ds, precision: str = "fp32", mode: Optional[str] = None, forward: str = "dft",
-                     oversample: int = 1, grad: str = "adjoint", **kw) -> "Context":
+                     oversample: int = 1, grad: str = "adjoint", region=None, **kw) -> "Context":
         """Context for a synthetic data set (paper_1703_02920_amd.synth); the
-        mode defaults to "shared" for a mosaic data set, else "cube"."""
+        mode defaults to "shared" for a mosaic data set, else "cube".
+        `region` (boolean n x n) restricts every image plane's free pixels."""
         if mode is None:
             mode = "shared" if getattr(ds, "shared", False) else "cube"
         ctx = cls(ds.n, ds.n_chan, precision, mode=mode, **kw)
@@ -232,13 +233,16 @@ class Context:
             ctx.set_beam(c, ch.fwhm)
             if ch.x0 or ch.y0:
                 ctx.set_phase_centre(c, ch.x0, ch.y0)
+        if region is not None:
+            for m in range(ctx.n_img):
+                ctx.set_mask(m, region)
         ctx.set_prior(ds.prior_m, ds.lam)
         return ctx.finalize()
 
     def info(self) -> dict:
         keys = ["n", "np", "n_chan", "prec", "ztot", "n_fwd_parts", "adj_tile", "n_slots", "n_fwd_wgs",
                 "n_adj_items", "n_vis_items", "device_bytes", "n_pix_blocks", "pix_block", "vis_block",
-                "n_img", "fwd_model", "grid_side", "grad_model"]
+                "n_img", "fwd_model", "grid_side", "grad_model", "n_fwd_wgs_region", "n_adj_wgs_region"]
         out = (ctypes.c_int64 * len(keys))()
         self._call("uvmem_info", out, len(keys))
         return dict(zip(keys, [int(x) for x in out]))

@@ -134,3 +134,50 @@ def test_focus_of_attention_phi_grad_and_cg(prec):
     flush(f"focus of attention cg {prec}: max rel phi {e_phis.max():.2e}, final image {e_img:.2e}")
     bar = {"fp64": CG_TOL["fp64"]["phi"], "fp32": 5e-5}[prec]
     assert e_phis.max() < bar and e_img < CG_TOL[prec]["img"] and e_phis[0] < CG_TOL[prec]["first"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_focus_region_visits_fewer_tiles(prec):
+    """256^2 image, region inside one quarter: the CG's direction forward and
+    gradient adjoint visit only the region's blocks and tiles; Phi, the
+    gradient inside the region and the CG trajectory match the oracle's
+    region-restricted results, and the pixels outside stay at the floor."""
+    _cuda()
+    prob = Problem.random(256, [1800], seed=82, lam=0.02)
+    free = np.zeros((256, 256), bool)
+    free[20:100, 30:120] = True
+    from paper_1703_02920_amd.uvmem import Context
+    ctx = Context(256, 1, prec)
+    ch = prob.chans[0]
+    ctx.set_uv(0, ch["u"], ch["v"], prob.cell)
+    ctx.set_vis(0, ch["vis"])
+    ctx.set_weights(0, ch["w"])
+    ctx.set_beam(0, ch["fwhm"])
+    ctx.set_mask(0, free)
+    ctx.set_prior(prob.M, prob.lam)
+    ctx.finalize()
+    info = ctx.info()
+    flush(f"region lists {prec}: forward {info['n_fwd_wgs_region']} of {info['n_fwd_wgs']} workgroups, "
+          f"adjoint {info['n_adj_wgs_region']} of {info['n_adj_items']}")
+    assert info["n_fwd_wgs_region"] > 0 and info["n_adj_wgs_region"] > 0
+    I = torch.tensor(synth.random_image(256, 83, lo=1e-3, hi=1.0), dtype=ctx.dtype, device="cuda")
+    scal, g = ctx.phi_and_grad(I)
+    ref = prob.oracle_phi_grad(0, I.cpu().numpy()[0].astype(np.float64))
+    gg = g.cpu().numpy()[0]
+    assert np.all(gg[~free] == 0.0)
+    e_g = rel(gg[free], ref["grad"][free])
+    assert e_g < TOL[prec] and abs(float(scal[0, 0]) - ref["phi"]) < TOL[prec] * abs(ref["phi"])
+    op = ocg.Problem(256, prob.cell, ch["u"], ch["v"], ch["vis"], ch["w"], prob.beam(0), prob.M, prob.lam)
+    iters = 8
+    I_ref, traj = ocg.projected_cg(op, iters, free=free)
+    J = ctx.image()
+    ctx.cg_init(J, init_to_floor=True)
+    hist = ctx.cg_run(J, iters, graph=True).cpu().numpy()
+    ctx.check()
+    Jn = J.cpu().numpy()[0]
+    assert np.all(Jn[~free] == Jn[0, 0])
+    e_phis = np.abs(hist[:, 0, 0] - [t["phi"] for t in traj]) / np.abs([t["phi"] for t in traj])
+    e_img = rel(Jn, I_ref)
+    flush(f"  grad {e_g:.2e}, cg max rel phi {e_phis.max():.2e}, final image {e_img:.2e}")
+    bar = {"fp64": CG_TOL["fp64"]["phi"], "fp32": 5e-5, "bf16x3": CG_TOL["bf16x3"]["phi"]}[prec]
+    assert e_phis.max() < bar and e_img < CG_TOL[prec]["img"]
