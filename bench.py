@@ -28,7 +28,7 @@ METRIC = "vis·pixel evals/sec (fwd+adjoint ∇Φ); CG iters/sec, mixed vs FP32 
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "fp16x3": 2500.0}   # TFLOP/s, dense MFMA
 KERNEL_SRC = "paper_1703_02920_amd/csrc/k_dft.hip"
 # DFT kernel functions per precision: (forward, adjoint)
-KERNELS = {"fp32": ("k_forward_p", "k_adjoint"), "fp64": ("k_forward_p", "k_adjoint"),
+KERNELS = {"fp32": ("k_forward_p", "k_adjoint_w"), "fp64": ("k_forward_p", "k_adjoint"),
            "bf16x3": ("k_forward_h16p", "k_adjoint_h16w"), "fp16x3": ("k_forward_h16p", "k_adjoint_h16w")}
 
 
@@ -44,7 +44,7 @@ def kernel_hash(kernel: str) -> str:
         src = src[:cut]
     # a kernel definition runs from its template line to the closing brace at
     # column 0
-    pat = re.compile(r"^template <[^\n]*>\n__global__ [^\n]*? void (k_\w+)\(.*?^}\n", re.S | re.M)
+    pat = re.compile(r"^(?:template <[^\n]*>\n)?__global__ [^\n]*? void (k_\w+)\(.*?^}\n", re.S | re.M)
     if kernel not in {m.group(1) for m in pat.finditer(src)}:
         raise ValueError(f"no kernel {kernel} in {KERNEL_SRC}")
     kept = pat.sub(lambda m: m.group(0) if m.group(1) == kernel else "", src)

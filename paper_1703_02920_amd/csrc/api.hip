@@ -181,15 +181,16 @@ int build_layout(uvmem_ctx *c) {
     c->n_ib = c->np / c->ib_rows;
     c->n_jb = c->np / c->jb_cols;
     c->n_fparts = c->fwd_model == UVMEM_FWD_GRIDDED ? 1 : c->n_ib * c->n_jb;
-    // adjoint pixel tile: 256 x 256 for the split kernel where the padded
-    // side allows (halves its table work per product), else 128 x 128
-    // (FP32, split), 64 x 64 (FP64)
+    // adjoint pixel tile: 256 x 256 for the FP32 and split kernels where the
+    // padded side allows (halves their table work per product), else
+    // 128 x 128 (FP32, split), 64 x 64 (FP64)
     const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
-    if (split && c->np % 256 == 0) c->adj_tt = 256;
+    if (c->prec != UVMEM_FP64 && c->np % 256 == 0) c->adj_tt = 256;
     if (const char *env = std::getenv("UVMEM_ADJ_TILE")) {
         const int t = std::atoi(env);
-        if ((t == 64 || (t == 128 && c->prec != UVMEM_FP64) || (t == 256 && split)) && c->np % t == 0) c->adj_tt = t;
+        if ((t == 64 || (t == 128 && c->prec != UVMEM_FP64) || (t == 256 && c->prec != UVMEM_FP64)) && c->np % t == 0)
+            c->adj_tt = t;
     }
     c->adj_nt = c->np / c->adj_tt;
     c->ls_steps = LS_STEPS;

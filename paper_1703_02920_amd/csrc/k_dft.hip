@@ -368,6 +368,145 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
 
 
 // ----------------------------------------------------------------------------
+// Adjoint, FP32, 256 x 256 workgroup tile, eight waves of 64 (i) x 128 (j).
+// Same tables and products as k_adjoint, but one super-step's tables (16
+// visibilities: fine and coarse factors of both axes, 1024 correctly
+// rounded twiddles) now feed 2048 matrix instructions instead of 512, and
+// each wave forms 12 operands per 64 products instead of 8 per 32.  The FP32
+// sums (at most 512 visibilities each) are folded every FLUSH super-steps
+// into the workgroup's own FP64 partial tile in global memory
+// (read-modify-write of a region no other workgroup touches; 512 KiB would
+// not fit in LDS); a chunk of at most FLUSH super-steps writes it once.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict__ items,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ b,
+                                                      const double2 *__restrict__ coef,
+                                                      const float *__restrict__ w,
+                                                      double *__restrict__ gpart, int n, int np) {
+    typedef Mfma<float>::acc acc_t;
+    constexpr int TT = 256, NTI = 4, NTJ = 8, FLUSH = 32;
+    // [buf][table][k][q or t]: tables 0 Hv, 1 Fu (fine), 2 Gv, 3 Gu (coarse)
+    __shared__ float2 sT[2][4][16][16];
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int ci0 = (wave >> 1) * NTI;   // wave's first coarse i-tile (0, 4, 8, 12)
+    const int cj0 = (wave & 1) * NTJ;    // wave's first coarse j-tile (0, 8)
+    const int half = n / 2;
+
+    // table tasks: thread tid fills entry (k, e) = (tid >> 4 & 15, tid & 15)
+    // of the fine table (tid < 256: Hv, else Fu) and of the coarse table
+    // (tid < 256: Gv, else Gu) of the same axis
+    const int tk = (tid >> 4) & 15, te = tid & 15;
+    const bool vaxis = tid < 256;
+    const double *ab = vaxis ? b : a;
+    struct Pre {
+        double x;
+        double2 c;
+        float w;
+    };
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k = kb + tk;
+        const long long kl = k < it.kend ? k : it.kend - 1;
+        p.x = ab[kl];
+        p.c = vaxis ? coef[kl] : make_double2(0.0, 0.0);
+        const float wv = w ? w[kl] : 1.f;
+        p.w = k < it.kend ? wv : 0.f;
+    };
+    auto gen = [&](int buf, const Pre &p) {
+        float c, s;
+        cis2pi((float)phase(p.x, (vaxis ? i0 : j0) + te - half), c, s);
+        float2 fine;
+        if (vaxis) {
+            const double cr = (double)p.w * p.c.x, cim = (double)p.w * p.c.y;
+            fine.x = (float)(cr * (double)c - cim * (double)s);
+            fine.y = (float)(cr * (double)s + cim * (double)c);
+        } else {
+            fine.x = p.w != 0.f ? c : 0.f;
+            fine.y = p.w != 0.f ? s : 0.f;
+        }
+        sT[buf][vaxis ? 0 : 1][tk][te] = fine;
+        cis2pi((float)phase(p.x, 16 * te), c, s);
+        sT[buf][vaxis ? 2 : 3][tk][te] = float2{c, s};
+    };
+
+    acc_t acc[NTI][NTJ];
+#pragma unroll
+    for (int x = 0; x < NTI; ++x)
+#pragma unroll
+        for (int y = 0; y < NTJ; ++y) acc[x][y] = Mfma<float>::zero();
+    double *out = gpart + (size_t)it.slot * np * np;
+    bool first = true;
+    // fold the FP32 sums into the FP64 tile, one 16 x 16 tile (4 values per
+    // lane) at a time: the accumulators already hold 128 registers
+    auto fold = [&]() {
+#pragma unroll
+        for (int x = 0; x < NTI; ++x)
+#pragma unroll
+            for (int y = 0; y < NTJ; ++y) {
+                double *o = out + (size_t)(i0 + 16 * (ci0 + x) + 4 * g) * np + j0 + 16 * (cj0 + y) + q;
+                double v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = first ? 0.0 : o[(size_t)r * np];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[(size_t)r * np] = v[r] + (double)acc[x][y][r];
+                acc[x][y] = Mfma<float>::zero();
+            }
+        first = false;
+    };
+
+    Pre cur, nxt;
+    fetch(it.kbeg, cur);
+    gen(0, cur);
+    fetch(it.kbeg + 16, cur);
+    __syncthreads();
+    int buf = 0;
+    int steps = 0;
+    for (long long kb = it.kbeg; kb < it.kend; kb += 16) {
+        fetch(kb + 32, nxt);
+        gen(buf ^ 1, cur);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * g + s;
+            const float2 h = sT[buf][0][kk][q];
+            const float2 f = sT[buf][1][kk][q];
+            float pr[NTI], pn[NTI], ec[NTJ], es[NTJ];
+#pragma unroll
+            for (int x = 0; x < NTI; ++x) {
+                const float2 gv = sT[buf][2][kk][ci0 + x];
+                pr[x] = h.x * gv.x - h.y * gv.y;
+                pn[x] = -(h.x * gv.y + h.y * gv.x);
+            }
+#pragma unroll
+            for (int y = 0; y < NTJ; ++y) {
+                const float2 gu = sT[buf][3][kk][cj0 + y];
+                ec[y] = f.x * gu.x - f.y * gu.y;
+                es[y] = f.x * gu.y + f.y * gu.x;
+            }
+#pragma unroll
+            for (int x = 0; x < NTI; ++x)
+#pragma unroll
+                for (int y = 0; y < NTJ; ++y) {
+                    acc[x][y] = Mfma<float>::mma(pr[x], ec[y], acc[x][y]);
+                    acc[x][y] = Mfma<float>::mma(pn[x], es[y], acc[x][y]);
+                }
+        }
+        __syncthreads();
+        buf ^= 1;
+        cur = nxt;
+        if (++steps == FLUSH) {
+            fold();
+            steps = 0;
+        }
+    }
+    if (steps > 0 || first) fold();
+}
+
+// ----------------------------------------------------------------------------
 // Split precision (16-bit hi + lo, three products per real product):
 //   x y ~= x_h y_h + x_h y_l + x_l y_h,  x_h = RN_16(x), x_l = RN_16(x - x_h),
 // on v_mfma_f32_16x16x32_{bf16,f16} (lane l supplies A[l%16][8 (l/16) + e] and
@@ -992,6 +1131,13 @@ template <typename T>
 hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st,
                         const AdjItem *items, int nitems) {
     if (nitems == 0) return hipSuccess;
+    if constexpr (sizeof(T) == 4) {
+        if (c->adj_tt == 256) {
+            hipLaunchKernelGGL(k_adjoint_w, dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b, coef, w,
+                               (double *)c->d_gpart, c->n, c->np);
+            return hipGetLastError();
+        }
+    }
     if (c->adj_tt == 128)
         hipLaunchKernelGGL((k_adjoint<T, 64>), dim3(nitems), dim3(256), 0, st, items, c->d_a,
                            c->d_b, coef, w, (double *)c->d_gpart, c->n, c->np);

@@ -19,7 +19,7 @@ PRECS = ["fp64", "fp32", "bf16x3", "fp16x3"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,nvis", [(64, 1000), (128, 777), (100, 321)])
+@pytest.mark.parametrize("n,nvis", [(64, 1000), (128, 777), (100, 321), (256, 1203)])
 def test_forward_parity(prec, n, nvis):
     _cuda()
     flush(f"forward parity {prec} n={n} nvis={nvis}")
@@ -35,7 +35,7 @@ def test_forward_parity(prec, n, nvis):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,nvis", [(64, 1000), (128, 777), (100, 321)])
+@pytest.mark.parametrize("n,nvis", [(64, 1000), (128, 777), (100, 321), (256, 1203)])
 def test_adjoint_parity(prec, n, nvis):
     _cuda()
     flush(f"adjoint parity {prec} n={n} nvis={nvis}")
