@@ -68,8 +68,9 @@ template <> struct Vec4<double> { typedef double4 type; };
 
 
 // ----------------------------------------------------------------------------
-// Forward, FP32 / FP64, persistent.  A workgroup of eight waves keeps the image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams
-// 16-visibility tiles through its waves.  Twiddles are correctly rounded
+// Forward, FP32 / FP64, persistent.  A workgroup of eight waves keeps the
+// image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams 16-visibility
+// tiles through its waves.  Twiddles are correctly rounded
 // (sincospi of FP64-reduced phases): E_u[k][j0 + 16 m + 4 g + s] =
 // E(j0 + 16 m - N/2) E(4 g + s); the row dot uses E_v = E(i0 + q - N/2) E(16 t)
 // with the second factors in a per-wave LDS table, accumulated in FP64.
@@ -105,8 +106,10 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
     __syncthreads();
     const long long nk = it.kend - it.kbeg;
     const long long ntiles = (nk + 15) / 16;
+    // tile wave * nwg + wg of each round: a round's leftover tiles go to one
+    // wave of distinct workgroups, so no CU carries them on all its SIMDs
     const long long stride = 8LL * it.nwg;
-    for (long long tile = (long long)it.wg * 8 + wave; tile < ntiles; tile += stride) {
+    for (long long tile = (long long)wave * it.nwg + it.wg; tile < ntiles; tile += stride) {
         const long long k0 = it.kbeg + 16 * tile;
         const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
         const double ak = q < nvalid ? a[k0 + q] : 0.0;
@@ -580,7 +583,7 @@ __device__ __forceinline__ void cis2pi_hw(float f, float &c, float &s) {
 // image block rows [i0, i0 + IB) x columns [j0, j0 + JB) in LDS for its
 // whole life (16-bit hi and lo halves, fp16 scaled by a power of
 // two to the block's maximum) and streams 16-visibility tiles through its waves:
-// tile t of the block goes to workgroup-wave (t mod 8 nwg).  For a tile the
+// tile t of the block goes to wave (t mod 8 nwg) / nwg of workgroup t mod nwg.  For a tile the
 // wave forms the E_u operand of each 32-column step from a coarse factor and
 // eight fine factors (hardware sin/cos of FP64-reduced phases), contracts the
 // block on matrix cores, then does the row dot with E_v and writes the
@@ -650,8 +653,10 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
     constexpr int TV = 16 * NV;
     const long long nk = it.kend - it.kbeg;
     const long long ntiles = (nk + TV - 1) / TV;
+    // tile wave * nwg + wg of each round: a round's leftover tiles go to one
+    // wave of distinct workgroups, so no CU carries them on all its SIMDs
     const long long stride = 8LL * it.nwg;
-    for (long long tile = (long long)it.wg * 8 + wave; tile < ntiles; tile += stride) {
+    for (long long tile = (long long)wave * it.nwg + it.wg; tile < ntiles; tile += stride) {
         const long long k0 = it.kbeg + TV * tile;
         const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
         double ak[NV];
