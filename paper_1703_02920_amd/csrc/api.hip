@@ -625,6 +625,13 @@ int uvmem_finalize(uvmem_ctx *c) {
             build_fwd(part_of, fwdp_m);
         }
     }
+    // the 256-tile FP32 adjoint folds at most 512 visibilities per FP32 sum;
+    // when no chunk is longer, its partials are single FP32 sums and are
+    // stored as such (half the traffic of the split-K planes)
+    int64_t maxchunk = 0;
+    for (auto &x : adj) maxchunk = std::max<int64_t>(maxchunk, x.kend - x.kbeg);
+    for (auto &x : adj_m) maxchunk = std::max<int64_t>(maxchunk, x.kend - x.kbeg);
+    c->gpart_f32 = split || (c->prec == UVMEM_FP32 && c->adj_tt == 256 && !grid_adj && maxchunk <= 512);
     c->n_fwdp = (int)fwdp.size();
     c->n_fwdp_m = (int)fwdp_m.size();
     c->n_adj_m = (int)adj_m.size();
@@ -784,7 +791,7 @@ int uvmem_finalize(uvmem_ctx *c) {
     ok(dalloc(c, &c->d_Vd, c->ztot));
     ok(dalloc(c, &c->d_vpart, (size_t)c->n_fparts * c->ztot));
     ok(dalloc(c, (char **)&c->d_gpart,
-              (size_t)std::max(c->n_slots, c->n_slots_m) * np * np * (split ? sizeof(float) : sizeof(double))));
+              (size_t)std::max(c->n_slots, c->n_slots_m) * np * np * (c->gpart_f32 ? sizeof(float) : sizeof(double))));
     if (region) {
         ok(dalloc(c, &c->d_fwdp_m, fwdp_m.size()));
         ok(dalloc(c, &c->d_adj_m, adj_m.size()));

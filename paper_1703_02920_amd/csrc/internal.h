@@ -163,7 +163,9 @@ struct uvmem_ctx {
     int *d_slot_base = nullptr, *d_vis_base = nullptr;
     int *d_ivis_base = nullptr, *d_ichan_base = nullptr, *d_chan_img = nullptr;
     double2 *d_R = nullptr, *d_Vd = nullptr, *d_vpart = nullptr;
-    void *d_gpart = nullptr;                    // split-K adjoint partials [slots][Np][Np]: FP64, FP32 (split)
+    void *d_gpart = nullptr;                    // split-K adjoint partials [slots][Np][Np]: FP64 or FP32
+    bool gpart_f32 = false;                     // partials stored as FP32 (split paths; FP32 when every
+                                                // chunk is one FP32 sum of at most 512 visibilities)
     void *d_bop = nullptr;                      // operand image [C][np][np]
     void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [nimg][n][n]
     double *d_scal = nullptr;                   // [nimg][NSCAL]

@@ -800,7 +800,7 @@ void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, 
 
 template <typename R>
 void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
-    if (c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3)
+    if (c->gpart_f32)
         grad_launch_t<R, float>(c, I, out, ppart, mode, st);
     else
         grad_launch_t<R, double>(c, I, out, ppart, mode, st);

@@ -381,12 +381,15 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
 // (read-modify-write of a region no other workgroup touches; 512 KiB would
 // not fit in LDS); a chunk of at most FLUSH super-steps writes it once.
 // ----------------------------------------------------------------------------
+// F32OUT: every chunk is at most FLUSH super-steps, so the single fold stores
+// the FP32 sums directly into FP32 partial planes.
+template <bool F32OUT>
 __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict__ items,
                                                       const double *__restrict__ a,
                                                       const double *__restrict__ b,
                                                       const double2 *__restrict__ coef,
                                                       const float *__restrict__ w,
-                                                      double *__restrict__ gpart, int n, int np) {
+                                                      void *__restrict__ gpart_v, int n, int np) {
     typedef Mfma<float>::acc acc_t;
     constexpr int TT = 256, NTI = 4, NTJ = 8, FLUSH = 32;
     // [buf][table][k][q or t]: tables 0 Hv, 1 Fu (fine), 2 Gv, 3 Gu (coarse)
@@ -442,7 +445,8 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
     for (int x = 0; x < NTI; ++x)
 #pragma unroll
         for (int y = 0; y < NTJ; ++y) acc[x][y] = Mfma<float>::zero();
-    double *out = gpart + (size_t)it.slot * np * np;
+    double *out = reinterpret_cast<double *>(gpart_v) + (size_t)it.slot * np * np;
+    float *out32 = reinterpret_cast<float *>(gpart_v) + (size_t)it.slot * np * np;
     bool first = true;
     // fold the FP32 sums into the FP64 tile, one 16 x 16 tile (4 values per
     // lane) at a time: the accumulators already hold 128 registers
@@ -451,7 +455,14 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
         for (int x = 0; x < NTI; ++x)
 #pragma unroll
             for (int y = 0; y < NTJ; ++y) {
-                double *o = out + (size_t)(i0 + 16 * (ci0 + x) + 4 * g) * np + j0 + 16 * (cj0 + y) + q;
+                const size_t e0 = (size_t)(i0 + 16 * (ci0 + x) + 4 * g) * np + j0 + 16 * (cj0 + y) + q;
+                if constexpr (F32OUT) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) out32[e0 + (size_t)r * np] = acc[x][y][r];
+                    acc[x][y] = Mfma<float>::zero();
+                    continue;
+                }
+                double *o = out + e0;
                 double v[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = first ? 0.0 : o[(size_t)r * np];
@@ -1138,8 +1149,12 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
     if (nitems == 0) return hipSuccess;
     if constexpr (sizeof(T) == 4) {
         if (c->adj_tt == 256) {
-            hipLaunchKernelGGL(k_adjoint_w, dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b, coef, w,
-                               (double *)c->d_gpart, c->n, c->np);
+            if (c->gpart_f32)
+                hipLaunchKernelGGL(k_adjoint_w<true>, dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b, coef, w,
+                                   c->d_gpart, c->n, c->np);
+            else
+                hipLaunchKernelGGL(k_adjoint_w<false>, dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b, coef,
+                                   w, c->d_gpart, c->n, c->np);
             return hipGetLastError();
         }
     }

@@ -456,7 +456,7 @@ hipError_t launch_grid_forward(const uvmem_ctx *c, const void *bop, hipStream_t 
 
 hipError_t launch_grid_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st) {
     if (c->prec == UVMEM_FP64) return grid_adj_t<double, double>(c, coef, w, st);
-    if (c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3) return grid_adj_t<float, float>(c, coef, w, st);
+    if (c->gpart_f32) return grid_adj_t<float, float>(c, coef, w, st);
     return grid_adj_t<float, double>(c, coef, w, st);
 }
 
