@@ -184,7 +184,6 @@ int build_layout(uvmem_ctx *c) {
     // adjoint pixel tile: 256 x 256 for the FP32 and split kernels where the
     // padded side allows (halves their table work per product), else
     // 128 x 128 (FP32, split), 64 x 64 (FP64)
-    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
     c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
     if (c->prec != UVMEM_FP64 && c->np % 256 == 0) c->adj_tt = 256;
     if (const char *env = std::getenv("UVMEM_ADJ_TILE")) {

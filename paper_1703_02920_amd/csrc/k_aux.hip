@@ -245,16 +245,19 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
 #pragma unroll
             for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
             int s = s0;
-            for (; s + 8 <= s1; s += 8) {
-                double v[RP][8];
+            // UL slots x RP pixels of independent loads in flight (16 slots
+            // when a thread owns one pixel); the sum stays in slot order
+            constexpr int UL = RP == 1 ? 16 : 8;
+            for (; s + UL <= s1; s += UL) {
+                double v[RP][UL];
 #pragma unroll
                 for (int r = 0; r < RP; ++r)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
+                    for (int u = 0; u < UL; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
 #pragma unroll
                 for (int r = 0; r < RP; ++r)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) Gs[r] += v[r][u];
+                    for (int u = 0; u < UL; ++u) Gs[r] += v[r][u];
             }
             for (; s < s1; ++s) {
 #pragma unroll
@@ -411,6 +414,11 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
                                                   double M, double Mb) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
+    // the thread's first pixel, loaded ahead of the reduction below (pixel 0
+    // stands in past the end)
+    const long long p_1 = (long long)pb * pb_len + threadIdx.x;
+    const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
+    const R d_1 = dir[q_1], g_1 = gt[q_1], x_1 = I[q_1];
     // step 2, recomputed by every workgroup of the channel: restart with
     // d = -gt when gt.d >= 0; stop when the projected gradient is zero
     double gtd[1];
@@ -433,8 +441,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
-        double d = (double)dir[q];
-        if (restart) d = -(double)gt[q];
+        double d = r == 0 ? (double)d_1 : (double)dir[q];
+        if (restart) d = -(r == 0 ? (double)g_1 : (double)gt[q]);
         if (stop) d = 0.0;
         const R dr = (R)d;
         d = (double)dr;
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
             bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
-        const double x = (double)I[q];
+        const double x = r == 0 ? (double)x_1 : (double)I[q];
         if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
         acc[1] += d * d / x;
@@ -604,6 +612,11 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
                                                   int n, int n_pb, int pb_len, double M, double lam, int first) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
+    // the thread's first pixel, loaded ahead of the state and partial
+    // reductions so that the latencies overlap (pixel 0 stands in past the end)
+    const long long p_1 = (long long)pb * pb_len + threadIdx.x;
+    const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
+    const R d_1 = dir[q_1], x_1 = I[q_1];
     __shared__ double st[LSS_N];
     if (first) {
         double ab[2], ent[2];
@@ -637,9 +650,9 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
         const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
-        const double d = (double)dir[q];
+        const double d = r == 0 ? (double)d_1 : (double)dir[q];
         if (d == 0.0) continue;
-        const double x0 = (double)I[q];
+        const double x0 = r == 0 ? (double)x_1 : (double)I[q];
 #pragma unroll
         for (int m = 0; m < LS_K; ++m) {
             const double x = x0 + tr[m] * d;
@@ -674,6 +687,11 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
     const VisItem vit = visw ? vitems[vi] : VisItem{};
     const int c = visw ? chan_img[vit.chan] : (int)blockIdx.x / n_pb, pb = visw ? -1 : (int)blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
+    // the thread's first pixel, loaded ahead of the line-search reduction
+    // (pixel 0 of the image stands in for residual workgroups and past the end)
+    const long long p_1 = visw ? 0 : (long long)pb * pb_len + threadIdx.x;
+    const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
+    const R d_1 = dir[q_1], x_1 = I[q_1];
     __shared__ double st[LSS_N];
     if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
     __syncthreads();
@@ -703,9 +721,9 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
         const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
-        double x = (double)I[q];
+        double x = r == 0 ? (double)x_1 : (double)I[q];
         if (al != 0.0) {
-            x = fmax(x + al * (double)dir[q], Mb);
+            x = fmax(x + al * (r == 0 ? (double)d_1 : (double)dir[q]), Mb);
             const R xr = (R)x;
             I[q] = xr;
             x = (double)xr;
