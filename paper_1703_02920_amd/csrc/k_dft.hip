@@ -58,6 +58,30 @@ __device__ __forceinline__ double phase(double a, int m) {
     return t - rint(t);
 }
 
+// Sum over each 16-lane row of the wave with DPP lane moves instead of LDS
+// permutes: quad swaps (xor 1, xor 2), then the half-row and row mirrors,
+// which pair lanes in the same groups as an xor butterfly over 4 and 8, so
+// every lane of the row ends with the same, identically rounded sum.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+
 template <typename T> struct C2T;
 template <> struct C2T<float> { typedef float2 type; };
 template <> struct C2T<double> { typedef double2 type; };
@@ -180,11 +204,8 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
                 vr += cd * tr + sd * ti;
                 vi += cd * ti - sd * tr;
             }
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                vr += __shfl_xor(vr, o, 64);
-                vi += __shfl_xor(vi, o, 64);
-            }
+            vr = row16_sum(vr);
+            vi = row16_sum(vi);
             if (q == 0 && ok) vpart[(size_t)it.part * ztot + k0 + kk] = make_double2(vr, vi);
         }
         __builtin_amdgcn_wave_barrier();
@@ -747,11 +768,8 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
                     es = es * sc16 + ec * ss16;
                     ec = nc;
                 }
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) {
-                    vr += __shfl_xor(vr, o, 64);
-                    vi += __shfl_xor(vi, o, 64);
-                }
+                vr = row16_sum(vr);
+                vi = row16_sum(vi);
                 if (q == 0 && ok)
                     vpart[(size_t)it.part * ztot + k0 + kk] =
                         make_double2((double)vr * (double)unscale, (double)vi * (double)unscale);
