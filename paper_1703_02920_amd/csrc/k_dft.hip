@@ -91,6 +91,56 @@ template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
 
+// Column contraction of one 16-visibility tile of the forward against KT
+// 16-row slices of the LDS image block, starting at slice t0:
+//   acc[t][k][q'] = sum_j E_u[k][j] B[16 (t0 + t) + q'][j]  (real, imaginary)
+// with E_u[k][j0 + 16 m + 4 g + s] = E(j0 + 16 m - N/2) E(4 g + s).
+template <typename T, int KT, int JB, int LDB>
+__device__ __forceinline__ void fwd_contract(const T (*sB)[LDB], int t0, double ak, int j0, int half, int q,
+                                             int g, typename Mfma<T>::acc (&accR)[KT],
+                                             typename Mfma<T>::acc (&accI)[KT]) {
+    typedef typename Vec4<T>::type T4;
+    T fc[4], fs[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        accR[t] = Mfma<T>::zero();
+        accI[t] = Mfma<T>::zero();
+    }
+    // coarse factors E(a_k (j0 + js - N/2)) of four 16-column steps: lane
+    // group g computes step 4 u + g, the others read it by lane exchange
+    for (int js0 = 0; js0 < JB; js0 += 64) {
+        T cc4, sc4;
+        cis2pi((T)phase(ak, j0 + js0 + 16 * g - half), cc4, sc4);
+#pragma unroll 2
+        for (int m = 0; m < 4; ++m) {
+            const int js = js0 + 16 * m;
+            const T cc = __shfl(cc4, q + 16 * m, 64), sc = __shfl(sc4, q + 16 * m, 64);
+            T cr[4], ci[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                cr[s] = cc * fc[s] - sc * fs[s];
+                ci[s] = -(sc * fc[s] + cc * fs[s]);
+            }
+            T4 bv[KT];
+#pragma unroll
+            for (int t = 0; t < KT; ++t) bv[t] = *reinterpret_cast<const T4 *>(&sB[16 * (t0 + t) + q][js + 4 * g]);
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                accR[t] = Mfma<T>::mma(cr[0], bv[t].x, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[0], bv[t].x, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[1], bv[t].y, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[1], bv[t].y, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[2], bv[t].z, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[2], bv[t].z, accI[t]);
+                accR[t] = Mfma<T>::mma(cr[3], bv[t].w, accR[t]);
+                accI[t] = Mfma<T>::mma(ci[3], bv[t].w, accI[t]);
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Forward, FP32 / FP64, persistent.  A workgroup of eight waves keeps the
 // image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams 16-visibility
@@ -131,52 +181,21 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
     const long long nk = it.kend - it.kbeg;
     const long long ntiles = (nk + 15) / 16;
     // tile wave * nwg + wg of each round: a round's leftover tiles go to one
-    // wave of distinct workgroups, so no CU carries them on all its SIMDs
+    // wave of distinct workgroups, so no CU carries them on all its SIMDs.
+    // With eight 16-row slices per block and at most two leftover tiles per
+    // workgroup, the eight waves share each leftover tile instead, a slice
+    // each (a single wave would keep one SIMD busy for a whole tile after
+    // the others have finished).
     const long long stride = 8LL * it.nwg;
-    for (long long tile = (long long)wave * it.nwg + it.wg; tile < ntiles; tile += stride) {
+    const long long nfull = ntiles / stride * stride;
+    const bool share = NT == 8 && ntiles > nfull && (ntiles - nfull + it.nwg - 1) / it.nwg <= 2;
+    const long long tend = share ? nfull : ntiles;
+    for (long long tile = (long long)wave * it.nwg + it.wg; tile < tend; tile += stride) {
         const long long k0 = it.kbeg + 16 * tile;
         const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
         const double ak = q < nvalid ? a[k0 + q] : 0.0;
-        T fc[4], fs[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
         acc_t accR[NT], accI[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            accR[t] = Mfma<T>::zero();
-            accI[t] = Mfma<T>::zero();
-        }
-        // coarse factors E(a_k (j0 + js - N/2)) of four 16-column steps: lane
-        // group g computes step 4 u + g, the others read it by lane exchange
-        for (int js0 = 0; js0 < JB; js0 += 64) {
-        T cc4, sc4;
-        cis2pi((T)phase(ak, j0 + js0 + 16 * g - half), cc4, sc4);
-#pragma unroll 2
-        for (int m = 0; m < 4; ++m) {
-            const int js = js0 + 16 * m;
-            const T cc = __shfl(cc4, q + 16 * m, 64), sc = __shfl(sc4, q + 16 * m, 64);
-            T cr[4], ci[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                cr[s] = cc * fc[s] - sc * fs[s];
-                ci[s] = -(sc * fc[s] + cc * fs[s]);
-            }
-            T4 bv[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bv[t] = *reinterpret_cast<const T4 *>(&sB[16 * t + q][js + 4 * g]);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                accR[t] = Mfma<T>::mma(cr[0], bv[t].x, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[0], bv[t].x, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[1], bv[t].y, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[1], bv[t].y, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[2], bv[t].z, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[2], bv[t].z, accI[t]);
-                accR[t] = Mfma<T>::mma(cr[3], bv[t].w, accR[t]);
-                accI[t] = Mfma<T>::mma(ci[3], bv[t].w, accI[t]);
-            }
-        }
-        }
+        fwd_contract<T, NT, JB>(sB, 0, ak, j0, half, q, g, accR, accI);
         // per-wave coarse factors E(16 b_k t) of the tile's 16 rows
         for (int e = lane; e < 16 * NT; e += 64) {
             const int kk = e / NT, t = e % NT;
@@ -209,6 +228,43 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             if (q == 0 && ok) vpart[(size_t)it.part * ztot + k0 + kk] = make_double2(vr, vi);
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (NT == 8) {
+        if (!share) return;
+        // wave w contracts rows [i0 + 16 w, i0 + 16 w + 16) of the tile with
+        // the row twiddle E(b_k (i0 + 16 w + q - N/2)) formed directly; the
+        // eight slice sums are added in slice order
+        __shared__ double2 sSl[8][16];
+        for (long long tile = nfull + it.wg; tile < ntiles; tile += it.nwg) {
+            const long long k0 = it.kbeg + 16 * tile;
+            const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
+            const double ak = q < nvalid ? a[k0 + q] : 0.0;
+            acc_t accR[1], accI[1];
+            fwd_contract<T, 1, JB>(sB, wave, ak, j0, half, q, g, accR, accI);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int kk = Mfma<T>::drow(g, r);
+                const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
+                T ce, se;
+                cis2pi((T)phase(bk, i0 + 16 * wave + q - half), ce, se);
+                const double cd = (double)ce, sd = (double)se;
+                const double tr = (double)accR[0][r], ti = (double)accI[0][r];
+                const double vr = row16_sum(cd * tr + sd * ti);
+                const double vi = row16_sum(cd * ti - sd * tr);
+                if (q == 0) sSl[wave][kk] = make_double2(vr, vi);
+            }
+            __syncthreads();
+            if (tid < nvalid) {
+                double vr = 0.0, vi = 0.0;
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    vr += sSl[w][tid].x;
+                    vi += sSl[w][tid].y;
+                }
+                vpart[(size_t)it.part * ztot + k0 + tid] = make_double2(vr, vi);
+            }
+            __syncthreads();
+        }
     }
 }
 

@@ -71,3 +71,30 @@ def test_phi_grad_parity_c1(prec, which):
     assert e_phi < TOL[prec] and e_chi < TOL[prec] and e_g < TOL[prec] and e_r < TOL[prec]
     S_ref = ref["S"]
     assert abs(scal[0, 2] - S_ref) <= TOL[prec] * max(abs(S_ref), 1e-300) + 1e-12 * ds.n ** 2 * ds.prior_m
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_forward_parity_short_last_round(prec):
+    """256^2 x 20,001: the persistent forward's last round of 16-visibility
+    tiles is short (at most two tiles per workgroup), so its tiles are split
+    across the waves of their workgroups; the visibilities of that round, a
+    ragged last tile among them, match the oracle like the rest."""
+    _cuda()
+    n, nvis = 256, 20001
+    flush(f"forward short last round {prec} n={n} nvis={nvis}")
+    prob = Problem.random(n, [nvis], seed=91)
+    ctx = prob.context(prec)
+    info = ctx.info()
+    nwg = info["n_fwd_wgs"] // info["n_fwd_parts"]
+    tv = 16
+    ntiles = -(-nvis // tv)
+    nfull = ntiles // (8 * nwg) * (8 * nwg)
+    assert 0 < ntiles - nfull <= 2 * nwg, (nwg, ntiles, nfull)
+    img = synth.random_image(n, 6, lo=1e-3, hi=1.0)[0]
+    I = torch.tensor(img[None], dtype=ctx.dtype, device="cuda")
+    V = ctx.forward(I).cpu().numpy()
+    ref = prob.oracle_forward(0, I.cpu().numpy()[0].astype(np.float64))
+    tail = slice(nfull * tv, nvis)
+    e_all, e_tail = rel(V, ref), rel(V[tail], ref[tail])
+    flush(f"  rel err {e_all:.3e}, last round ({nvis - nfull * tv} visibilities) {e_tail:.3e}")
+    assert e_all < TOL[prec] and e_tail < TOL[prec]
