@@ -90,12 +90,16 @@ def cpu_baseline(ds, target_s: float = 12.0):
         dt = time.perf_counter() - t0
         return (n_vis * n * n + ch.nvis * n_pix) / 2.0, dt
 
-    # calibrate on a small sample, then size the real one to ~target_s
+    def sizes(rate, seconds):
+        pairs_goal = rate * seconds * 2.0
+        return (int(min(ch.nvis, max(64, pairs_goal / 2.0 / (n * n)))),
+                int(min(n * n, max(64, pairs_goal / 2.0 / ch.nvis))))
+
+    # calibrate on a tiny sample, then on one of ~1 s (the tiny one
+    # underestimates the rate), then size the real one to ~target_s
     p0, t0 = run(min(64, ch.nvis), 64)
-    rate0 = p0 / max(t0, 1e-6)
-    pairs_goal = rate0 * target_s * 2.0
-    n_vis = int(min(ch.nvis, max(64, pairs_goal / 2.0 / (n * n))))
-    n_pix = int(min(n * n, max(64, pairs_goal / 2.0 / ch.nvis)))
+    p1, t1 = run(*sizes(p0 / max(t0, 1e-6), 1.0))
+    n_vis, n_pix = sizes(p1 / max(t1, 1e-6), target_s)
     pairs, dt = run(n_vis, n_pix)
     return {"value": pairs / dt, "unit": "vis·pixel evals/s", "cores": oracle.num_threads(),
             "kind": "oracle",
