@@ -160,7 +160,9 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
     constexpr int NT = IB / 16;
     constexpr int PADC = 4;
     __shared__ __attribute__((aligned(16))) T sB[IB][JB + PADC];
-    __shared__ C2 sCo[8][16][NT];
+    // one pad entry per row: the four rows a read touches (4 g + r) then
+    // start in different banks
+    __shared__ C2 sCo[8][16][NT + 1];
 
     const FwdPItem it = items[blockIdx.x];
     const int i0 = it.ib * IB, j0 = it.jb * JB;
@@ -469,8 +471,10 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
                                                       void *__restrict__ gpart_v, int n, int np) {
     typedef Mfma<float>::acc acc_t;
     constexpr int TT = 256, NTI = 4, NTJ = 8, FLUSH = 32;
-    // [buf][table][k][q or t]: tables 0 Hv, 1 Fu (fine), 2 Gv, 3 Gu (coarse)
-    __shared__ float2 sT[2][4][16][16];
+    // [buf][table][k][q or t]: tables 0 Hv, 1 Fu (fine), 2 Gv, 3 Gu (coarse);
+    // rows padded to 20 entries so that the rows 4 g + s read by the four
+    // lane groups fall in different banks
+    __shared__ float2 sT[2][4][16][20];
 
     const AdjItem it = items[blockIdx.x];
     const int i0 = it.ti * TT, j0 = it.tj * TT;
