@@ -158,7 +158,10 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
     typedef typename Vec4<T>::type T4;
     typedef typename C2T<T>::type C2;
     constexpr int NT = IB / 16;
-    constexpr int PADC = 4;
+    // rows padded by 8 floats (row stride = 8 mod 128 words): the 128-bit
+    // operand reads of 32 lanes (16 rows x two 4-column groups) then cover
+    // distinct banks; a 4-float pad measured one bank conflict per read
+    constexpr int PADC = 8;
     __shared__ __attribute__((aligned(16))) T sB[IB][JB + PADC];
     // one pad entry per row: the four rows a read touches (4 g + r) then
     // start in different banks
