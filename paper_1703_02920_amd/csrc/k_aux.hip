@@ -9,6 +9,7 @@
 // (every workgroup of the channel gets the same bits), which keeps each CG
 // phase to one launch without atomics.
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -245,20 +246,26 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
 #pragma unroll
             for (int r = 0; r < RP; ++r) Gs[r] = 0.0;
             int s = s0;
-            // UL slots x RP pixels of independent loads in flight (16 slots
-            // when a thread owns one pixel); the sum stays in slot order
-            constexpr int UL = RP == 1 ? 16 : 8;
-            for (; s + UL <= s1; s += UL) {
-                double v[RP][UL];
+            // UL slots x RP pixels of independent loads in flight (32 slots
+            // when a thread owns one pixel), then batches of 8; the sum
+            // stays in slot order
+            constexpr int UL = RP == 1 ? 32 : 8;
+            auto batch = [&](auto ul) {
+                constexpr int B = decltype(ul)::value;
+                double v[RP][B];
 #pragma unroll
                 for (int r = 0; r < RP; ++r)
 #pragma unroll
-                    for (int u = 0; u < UL; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
+                    for (int u = 0; u < B; ++u) v[r][u] = (double)gpart[(size_t)(s + u) * np2 + off[r]];
 #pragma unroll
                 for (int r = 0; r < RP; ++r)
 #pragma unroll
-                    for (int u = 0; u < UL; ++u) Gs[r] += v[r][u];
-            }
+                    for (int u = 0; u < B; ++u) Gs[r] += v[r][u];
+                s += B;
+            };
+            while (s + UL <= s1) batch(std::integral_constant<int, UL>());
+            if constexpr (UL > 8)
+                while (s + 8 <= s1) batch(std::integral_constant<int, 8>());
             for (; s < s1; ++s) {
 #pragma unroll
                 for (int r = 0; r < RP; ++r) Gs[r] += (double)gpart[(size_t)s * np2 + off[r]];
