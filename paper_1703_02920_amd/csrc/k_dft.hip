@@ -58,6 +58,35 @@ __device__ __forceinline__ double phase(double a, int m) {
     return t - rint(t);
 }
 
+// cos and sin of 2 pi frac(a m).  FP64: sincospi of the reduced phase.
+// FP32: u = 4 a m quarter turns (FP64) splits into the quadrant j = rint(u)
+// and r = u - j in [-1/2, 1/2] (exact); cos and sin of (pi / 2) r come from
+// minimax polynomials in r^2 fitted on [0, 1/2] (the sine's leading
+// coefficient pi / 2 carried as a float plus a correction), then the result
+// is rotated by j quarter turns.  FP32 evaluation of the two polynomials
+// against FP64 sin and cos over 2.2 M arguments: within 0.76 ulp (sine) and
+// 1.01 ulp (cosine).  The quadrant needs |a m| < 2^29 turns.
+__device__ __forceinline__ void cisphase(double a, int m, double &c, double &s) { cis2pi(phase(a, m), c, s); }
+__device__ __forceinline__ void cisphase(double a, int m, float &c, float &s) {
+    const double u = a * (double)(4 * m);
+    const double jd = rint(u);
+    const float r = (float)(u - jd);
+    const int j = (int)jd;
+    const float z = r * r;
+    float q = fmaf(z, -0x1.2edef6p-8f, 0x1.466626p-4f);
+    q = fmaf(z, q, -0x1.4abbcep-1f);
+    q = fmaf(z, q, -0x1.777a5cp-25f);
+    const float sn = fmaf(r, 0x1.921fb6p+0f, r * q);
+    float p = fmaf(z, 0x1.d9de14p-11f, -0x1.55c6a0p-6f);
+    p = fmaf(z, p, 0x1.03c1e2p-2f);
+    p = fmaf(z, p, -0x1.3bd3ccp+0f);
+    const float cs = fmaf(z, p, 1.0f);
+    const bool odd = (j & 1) != 0;
+    const float cc = odd ? sn : cs, ss = odd ? cs : sn;
+    c = ((j + 1) & 2) ? -cc : cc;
+    s = (j & 2) ? -ss : ss;
+}
+
 // Sum over each 16-lane row of the wave with DPP lane moves instead of LDS
 // permutes: quad swaps (xor 1, xor 2), then the half-row and row mirrors,
 // which pair lanes in the same groups as an xor butterfly over 4 and 8, so
@@ -102,7 +131,7 @@ __device__ __forceinline__ void fwd_contract(const T (*sB)[LDB], int t0, double 
     typedef typename Vec4<T>::type T4;
     T fc[4], fs[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) cis2pi((T)phase(ak, 4 * g + s), fc[s], fs[s]);
+    for (int s = 0; s < 4; ++s) cisphase(ak, 4 * g + s, fc[s], fs[s]);
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
         accR[t] = Mfma<T>::zero();
@@ -112,7 +141,7 @@ __device__ __forceinline__ void fwd_contract(const T (*sB)[LDB], int t0, double 
     // group g computes step 4 u + g, the others read it by lane exchange
     for (int js0 = 0; js0 < JB; js0 += 64) {
         T cc4, sc4;
-        cis2pi((T)phase(ak, j0 + js0 + 16 * g - half), cc4, sc4);
+        cisphase(ak, j0 + js0 + 16 * g - half, cc4, sc4);
 #pragma unroll 2
         for (int m = 0; m < 4; ++m) {
             const int js = js0 + 16 * m;
@@ -206,7 +235,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             const int kk = e / NT, t = e % NT;
             const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
             T c, sn;
-            cis2pi((T)phase(bk, 16 * t), c, sn);
+            cisphase(bk, 16 * t, c, sn);
             sCo[wave][kk][t] = C2{c, sn};
         }
         __builtin_amdgcn_wave_barrier();
@@ -217,7 +246,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             const bool ok = kk < nvalid;
             const double bk = ok ? b[k0 + kk] : 0.0;
             T fcq, fsq;
-            cis2pi((T)phase(bk, i0 + q - half), fcq, fsq);
+            cisphase(bk, i0 + q - half, fcq, fsq);
             double vr = 0.0, vi = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -251,7 +280,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
                 const int kk = Mfma<T>::drow(g, r);
                 const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
                 T ce, se;
-                cis2pi((T)phase(bk, i0 + 16 * wave + q - half), ce, se);
+                cisphase(bk, i0 + 16 * wave + q - half, ce, se);
                 const double cd = (double)ce, sd = (double)se;
                 const double tr = (double)accR[0][r], ti = (double)accI[0][r];
                 const double vr = row16_sum(cd * tr + sd * ti);
@@ -356,19 +385,19 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
     // buffer `buf` (branch-free: entries past the chunk end are zero)
     auto gen = [&](int buf, long long kb, const Pre &p) {
         T c, s;
-        cis2pi((T)phase(p.b, i0 + fqq - half), c, s);
+        cisphase(p.b, i0 + fqq - half, c, s);
         const double cr = (double)p.w * p.c.x, cim = (double)p.w * p.c.y;
         C2 hv, fu;
         hv.x = (T)(cr * (double)c - cim * (double)s);
         hv.y = (T)(cr * (double)s + cim * (double)c);
-        cis2pi((T)phase(p.a, j0 + fqq - half), c, s);
+        cisphase(p.a, j0 + fqq - half, c, s);
         const bool live = kb + fkk < it.kend;
         fu.x = live ? c : (T)0;
         fu.y = live ? s : (T)0;
         sHv[buf][fkk][fqq] = hv;
         sFu[buf][fkk][fqq] = fu;
         if (has_c) {
-            cis2pi((T)phase(p.cab, 16 * ct2), c, s);
+            cisphase(p.cab, 16 * ct2, c, s);
             C2 *dst = which ? &sGu[buf][ck2][ct2] : &sGv[buf][ck2][ct2];
             *dst = C2{c, s};
         }
@@ -509,7 +538,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
     };
     auto gen = [&](int buf, const Pre &p) {
         float c, s;
-        cis2pi((float)phase(p.x, (vaxis ? i0 : j0) + te - half), c, s);
+        cisphase(p.x, (vaxis ? i0 : j0) + te - half, c, s);
         float2 fine;
         if (vaxis) {
             const double cr = (double)p.w * p.c.x, cim = (double)p.w * p.c.y;
@@ -520,7 +549,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
             fine.y = p.w != 0.f ? s : 0.f;
         }
         sT[buf][vaxis ? 0 : 1][tk][te] = fine;
-        cis2pi((float)phase(p.x, 16 * te), c, s);
+        cisphase(p.x, 16 * te, c, s);
         sT[buf][vaxis ? 2 : 3][tk][te] = float2{c, s};
     };
 
