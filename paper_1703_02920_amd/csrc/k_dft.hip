@@ -185,16 +185,16 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
                                                       int n, int np, long long ztot) {
     typedef typename Mfma<T>::acc acc_t;
     typedef typename Vec4<T>::type T4;
-    typedef typename C2T<T>::type C2;
     constexpr int NT = IB / 16;
     // rows padded by 8 floats (row stride = 8 mod 128 words): the 128-bit
     // operand reads of 32 lanes (16 rows x two 4-column groups) then cover
     // distinct banks; a 4-float pad measured one bank conflict per read
     constexpr int PADC = 8;
     __shared__ __attribute__((aligned(16))) T sB[IB][JB + PADC];
-    // one pad entry per row: the four rows a read touches (4 g + r) then
-    // start in different banks
-    __shared__ C2 sCo[8][16][NT + 1];
+    // coarse row factors in FP64 (converted once when stored); one pad
+    // entry per row, so that the four rows a read touches (4 g + r) start
+    // in different banks
+    __shared__ double2 sCo[8][16][NT + 1];
 
     const FwdPItem it = items[blockIdx.x];
     const int i0 = it.ib * IB, j0 = it.jb * JB;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
             T c, sn;
             cisphase(bk, 16 * t, c, sn);
-            sCo[wave][kk][t] = C2{c, sn};
+            sCo[wave][kk][t] = make_double2((double)c, (double)sn);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -247,16 +247,17 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
             const double bk = ok ? b[k0 + kk] : 0.0;
             T fcq, fsq;
             cisphase(bk, i0 + q - half, fcq, fsq);
-            double vr = 0.0, vi = 0.0;
+            // conj(E_v) T = conj(fine) sum_t conj(coarse_t) T_t, in FP64
+            double wr = 0.0, wi = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const C2 co = sCo[wave][kk][t];
-                const double cd = (double)(fcq * co.x - fsq * co.y);
-                const double sd = (double)(fsq * co.x + fcq * co.y);
+                const double2 co = sCo[wave][kk][t];
                 const double tr = (double)accR[t][r], ti = (double)accI[t][r];
-                vr += cd * tr + sd * ti;
-                vi += cd * ti - sd * tr;
+                wr += co.x * tr + co.y * ti;
+                wi += co.x * ti - co.y * tr;
             }
+            const double fc = (double)fcq, fs = (double)fsq;
+            double vr = fc * wr + fs * wi, vi = fc * wi - fs * wr;
             vr = row16_sum(vr);
             vi = row16_sum(vi);
             if (q == 0 && ok) vpart[(size_t)it.part * ztot + k0 + kk] = make_double2(vr, vi);
