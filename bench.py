@@ -34,14 +34,16 @@ KERNELS = {"fp32": ("k_forward_p", "k_adjoint_w"), "fp64": ("k_forward_p", "k_ad
 
 def kernel_hash(kernel: str) -> str:
     """Hash of the DFT source up to the launch code, with every other kernel's
-    definition removed: it changes when this kernel or a device helper it
-    may use changes."""
+    definition and all comments removed: it changes when the code of this
+    kernel or of a device helper it may use changes."""
     import re
     with open(os.path.join(ROOT, KERNEL_SRC)) as f:
         src = f.read()
     cut = src.find("hipError_t fwd_dispatch")
     if cut > 0:
         src = src[:cut]
+    src = re.sub(r"[ \t]*//[^\n]*", "", src)
+    src = re.sub(r"\n\s*\n", "\n", src)
     # a kernel definition runs from its template line to the closing brace at
     # column 0
     pat = re.compile(r"^(?:template <[^\n]*>\n)?__global__ [^\n]*? void (k_\w+)\(.*?^}\n", re.S | re.M)

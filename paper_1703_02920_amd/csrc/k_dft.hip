@@ -15,8 +15,10 @@
 // split over visibility chunks (split-K); chunk partials are summed in a fixed
 // order by the gradient kernel, so results are bitwise reproducible.
 //
-// Phases are formed and reduced modulo one cycle in FP64 (f = t - rint(t) with
-// t = a_k m), then the twiddle is sincospi(2 f) in the operand precision.
+// Phases are formed and reduced modulo one cycle in FP64 (t = a_k m); the FP64
+// kernels take sincospi of the reduced phase, the FP32 ones cos and sin from
+// the quadrant and remainder of 4 t (see cisphase), the split ones the
+// hardware sine and cosine.
 #include "internal.h"
 
 namespace uvm {
@@ -173,10 +175,10 @@ __device__ __forceinline__ void fwd_contract(const T (*sB)[LDB], int t0, double 
 // ----------------------------------------------------------------------------
 // Forward, FP32 / FP64, persistent.  A workgroup of eight waves keeps the
 // image block [i0, i0 + IB) x [j0, j0 + JB) in LDS and streams 16-visibility
-// tiles through its waves.  Twiddles are correctly rounded
-// (sincospi of FP64-reduced phases): E_u[k][j0 + 16 m + 4 g + s] =
-// E(j0 + 16 m - N/2) E(4 g + s); the row dot uses E_v = E(i0 + q - N/2) E(16 t)
-// with the second factors in a per-wave LDS table, accumulated in FP64.
+// tiles through its waves.  Twiddles come from FP64-reduced phases
+// (cisphase): E_u[k][j0 + 16 m + 4 g + s] = E(j0 + 16 m - N/2) E(4 g + s);
+// the row dot uses E_v = E(i0 + q - N/2) E(16 t), the second factors in a
+// per-wave FP64 LDS table, accumulated in FP64.
 template <typename T, int IB, int JB>
 __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict__ items,
                                                       const double *__restrict__ a,
@@ -309,8 +311,8 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
 //   Hv[k][q] = c_k w_k exp(+2 pi i b_k (i0 + q - N/2)),  Gv[k][t] = exp(+2 pi i b_k 16 t)
 //   Fu[k][q] = exp(+2 pi i a_k (j0 + q - N/2)),          Gu[k][t] = exp(+2 pi i a_k 16 t)
 // so that P[k][i0 + 16 t + q] = Hv[k][q] Gv[k][t] and the cos/sin operand at
-// column j0 + 16 t + q is Fu[k][q] Gu[k][t] (one product per operand, two
-// correctly rounded factors).  MFMA #s of lane group g contracts visibility
+// column j0 + 16 t + q is Fu[k][q] Gu[k][t] (one product per operand of two
+// factors from cisphase).  MFMA #s of lane group g contracts visibility
 // 4 g + s of the step.  FP32 accumulators are folded into FP64 ones every
 // FLUSH super-steps.
 // ----------------------------------------------------------------------------
