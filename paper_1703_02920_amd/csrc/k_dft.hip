@@ -65,9 +65,10 @@ __device__ __forceinline__ double phase(double a, int m) {
 // and r = u - j in [-1/2, 1/2] (exact); cos and sin of (pi / 2) r come from
 // minimax polynomials in r^2 fitted on [0, 1/2] (the sine's leading
 // coefficient pi / 2 carried as a float plus a correction), then the result
-// is rotated by j quarter turns.  FP32 evaluation of the two polynomials
-// against FP64 sin and cos over 2.2 M arguments: within 0.76 ulp (sine) and
-// 1.01 ulp (cosine).  The quadrant needs |a m| < 2^29 turns.
+// is rotated by j quarter turns.  Against FP64 cos and sin: within 1.01 ulp
+// of those of the float remainder (sine polynomial 0.76 ulp, cosine 1.01),
+// within 1.32 ulp of those of the FP64 phase (the float remainder's own
+// rounding adds up to half an ulp).  The quadrant needs |a m| < 2^29 turns.
 __device__ __forceinline__ void cisphase(double a, int m, double &c, double &s) { cis2pi(phase(a, m), c, s); }
 __device__ __forceinline__ void cisphase(double a, int m, float &c, float &s) {
     const double u = a * (double)(4 * m);
