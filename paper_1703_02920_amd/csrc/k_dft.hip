@@ -854,16 +854,16 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
                 float ec, es, sc16, ss16;
                 cis2pi_hw((float)phase(bk, i0 + q - half), ec, es);
                 cis2pi_hw((float)phase(bk, 16), sc16, ss16);
-                float vr = 0.f, vi = 0.f;
+                // W = sum_t conj(rho)^t T_t by Horner's rule (rho = E(16 b_k)),
+                // then V = conj(E(b_k (i0 + q - N/2))) W
+                float wr = accR[v][NT - 1][r], wi = accI[v][NT - 1][r];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const float tr = accR[v][t][r], ti = accI[v][t][r];
-                    vr += ec * tr + es * ti;
-                    vi += ec * ti - es * tr;
-                    const float nc = ec * sc16 - es * ss16;
-                    es = es * sc16 + ec * ss16;
-                    ec = nc;
+                for (int t = NT - 2; t >= 0; --t) {
+                    const float nr = accR[v][t][r] + sc16 * wr + ss16 * wi;
+                    wi = accI[v][t][r] + sc16 * wi - ss16 * wr;
+                    wr = nr;
                 }
+                float vr = ec * wr + es * wi, vi = ec * wi - es * wr;
                 vr = row16_sum(vr);
                 vi = row16_sum(vi);
                 if (q == 0 && ok)
