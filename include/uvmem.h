@@ -130,7 +130,9 @@ int uvmem_destroy(uvmem_ctx *ctx);
 /* Visibility coordinates of channel `chan` (Sec. 2.1): nvis >= 0 points,
  * u, v in wavelengths (double[nvis]).  cell_rad is the pixel size Delta x in
  * radians and must be the same for every channel (one pixel grid).  nvis = 0
- * is legal: the channel then contributes chi^2 = 0 and grad chi^2 = 0. */
+ * is legal: the channel then contributes chi^2 = 0 and grad chi^2 = 0.
+ * UVMEM_EINVAL for non-finite u, v or |u| cell_rad, |v| cell_rad above 4096
+ * cycles per pixel (8192 times the grid's Nyquist limit). */
 int uvmem_set_uv(uvmem_ctx *ctx, int chan, int64_t nvis, const double *u, const double *v,
                  double cell_rad);
 /* Observed visibilities V^o of the channel: float[nvis][2] (re, im). */

@@ -320,9 +320,17 @@ int uvmem_set_uv(uvmem_ctx *c, int chan, int64_t nvis, const double *u, const do
     }
     HIPCHK(c, fetch(c->hu[chan].data(), u, nvis * sizeof(double)));
     HIPCHK(c, fetch(c->hv[chan].data(), v, nvis * sizeof(double)));
-    for (int64_t k = 0; k < nvis; ++k)
-        if (!std::isfinite(c->hu[chan][k]) || !std::isfinite(c->hv[chan][k]))
+    // at most 4096 cycles per pixel (8192 times the grid's Nyquist limit):
+    // keeps the FP64 phases a m, and the FP32 twiddles' quarter-turn counts
+    // 4 a m, far inside their exact ranges for any image side
+    constexpr double UV_MAX_CYCLES = 4096.0;
+    for (int64_t k = 0; k < nvis; ++k) {
+        const double uk = c->hu[chan][k], vk = c->hv[chan][k];
+        if (!std::isfinite(uk) || !std::isfinite(vk))
             return fail(c, UVMEM_EINVAL, "non-finite u/v at %lld", (long long)k);
+        if (std::fabs(uk) * cell_rad > UV_MAX_CYCLES || std::fabs(vk) * cell_rad > UV_MAX_CYCLES)
+            return fail(c, UVMEM_EINVAL, "u/v at %lld is beyond %g cycles per pixel", (long long)k, UV_MAX_CYCLES);
+    }
     c->has_uv[chan] = 1;
     c->has_vis[chan] = nvis == 0;
     c->has_w[chan] = nvis == 0;

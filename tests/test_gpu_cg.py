@@ -200,3 +200,14 @@ def test_domain_flag_and_errors():
     with pytest.raises(UvmemError) as ei:
         ctx.cg_step(I)
     assert ei.value.code == ESTATE
+    # u beyond 4096 cycles per pixel is rejected before anything reaches the GPU
+    from paper_1703_02920_amd.uvmem import EINVAL, Context
+    c2 = Context(64, 1, "fp32")
+    ch = prob.chans[0]
+    u = ch["u"].copy()
+    u[7] = 4097.0 / prob.cell
+    with pytest.raises(UvmemError) as ei:
+        c2.set_uv(0, u, ch["v"], prob.cell)
+    assert ei.value.code == EINVAL and "cycles per pixel" in str(ei.value)
+    u[7] = 4095.0 / prob.cell
+    c2.set_uv(0, u, ch["v"], prob.cell)
