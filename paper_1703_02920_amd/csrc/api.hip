@@ -580,7 +580,11 @@ int uvmem_finalize(uvmem_ctx *c) {
         int nblk = 0;
         for (int x : part_of) nblk += x >= 0 ? 1 : 0;
         if (c->ztot == 0 || nblk == 0) return;
-        constexpr double FWD_OVERHEAD = 256.0;   // image-block staging, in visibilities
+        // image-block staging and start-up per workgroup, in visibilities: on
+        // 64 uneven channels 256 kept the lists at 1,536 workgroups while
+        // 3,072-4,096 ran the forward 4-5 % faster; 128 picks 3,072 there and
+        // leaves single-channel workloads at one workgroup per CU
+        constexpr double FWD_OVERHEAD = 128.0;
         auto shares = [&](int64_t wgs, int ch) {
             const int64_t nv = c->nvis[ch];
             const int64_t L = std::max<int64_t>(16, (c->ztot * nblk + wgs - 1) / wgs);
