@@ -636,13 +636,13 @@ int uvmem_finalize(uvmem_ctx *c) {
             build_fwd(part_of, fwdp_m);
         }
     }
-    // the 256-tile FP32 adjoint folds at most 512 visibilities per FP32 sum;
-    // when no chunk is longer, its partials are single FP32 sums and are
+    // the 256-tile FP32 adjoint folds at most ADJ_F32_SUM visibilities per
+    // FP32 sum; when no chunk is longer, its partials are single FP32 sums and are
     // stored as such (half the traffic of the split-K planes)
     int64_t maxchunk = 0;
     for (auto &x : adj) maxchunk = std::max<int64_t>(maxchunk, x.kend - x.kbeg);
     for (auto &x : adj_m) maxchunk = std::max<int64_t>(maxchunk, x.kend - x.kbeg);
-    c->gpart_f32 = split || (c->prec == UVMEM_FP32 && c->adj_tt == 256 && !grid_adj && maxchunk <= 512);
+    c->gpart_f32 = split || (c->prec == UVMEM_FP32 && c->adj_tt == 256 && !grid_adj && maxchunk <= ADJ_F32_SUM);
     c->n_fwdp = (int)fwdp.size();
     c->n_fwdp_m = (int)fwdp_m.size();
     c->n_adj_m = (int)adj_m.size();

@@ -24,6 +24,9 @@ constexpr int ADJ_KMIN = 256;
 // Maximum visibilities per split-K chunk of the split-precision adjoint,
 // whose chunk sums are FP32 only (bounds their rounding growth).
 constexpr int ADJ_KMAX_SPLIT = 32768;
+// visibilities per FP32 sum of the 256-tile FP32 adjoint before it is folded
+// into FP64 (and the chunk length up to which its partials stay FP32)
+constexpr int ADJ_F32_SUM = 2048;
 // Partial-sum slots per pixel / visibility item.
 constexpr int NPART = 8;
 // Trial steps evaluated per line-search pass.

@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
 // visibilities: fine and coarse factors of both axes, 1024 correctly
 // rounded twiddles) now feed 2048 matrix instructions instead of 512, and
 // each wave forms 12 operands per 64 products instead of 8 per 32.  The FP32
-// sums (at most 512 visibilities each) are folded every FLUSH super-steps
+// sums (at most ADJ_F32_SUM visibilities each) are folded every FLUSH super-steps
 // into the workgroup's own FP64 partial tile in global memory
 // (read-modify-write of a region no other workgroup touches; 512 KiB would
 // not fit in LDS); a chunk of at most FLUSH super-steps writes it once.
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_w(const AdjItem *__restrict_
                                                       const float *__restrict__ w,
                                                       void *__restrict__ gpart_v, int n, int np) {
     typedef Mfma<float>::acc acc_t;
-    constexpr int TT = 256, NTI = 4, NTJ = 8, FLUSH = 32;
+    constexpr int TT = 256, NTI = 4, NTJ = 8, FLUSH = ADJ_F32_SUM / 16;
     // [buf][table][k][q or t]: tables 0 Hv, 1 Fu (fine), 2 Gv, 3 Gu (coarse);
     // rows padded to 20 entries so that the rows 4 g + s read by the four
     // lane groups fall in different banks
