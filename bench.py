@@ -68,11 +68,40 @@ def traffic_from_profiles(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(ds, target_s: float = 12.0):
+# The paper's own timings (Sec. 4.1 timing table, abstract, conclusions):
+# one Tesla K80 die against one thread of a Xeon E5-2640 v2 at 2.0 GHz, the
+# FFT-gridded model with an exact direct-sum gradient, real ALMA data.
+PAPER_CONTEXT = {
+    "hardware": "one Tesla K80 GK210B die vs one thread of an Intel Xeon E5-2640 v2 (2.0 GHz)",
+    "speedup_range_abstract": "1,000x - 5,000x over the sequential version",
+    "largest_single_data_set": "2.1 min (GPU) vs 2.5 days (CPU), HD142527 CO(6-5), 107,494 visibilities, 1024^2",
+    "per_iteration_minutes_cpu_gpu_speedup": {
+        "CO(6-5) 1024^2": [131, 0.08, 1638], "CO(6-5) 2048^2": [349, 0.11, 3173],
+        "CO(6-5) 4096^2": [360, 0.13, 2769], "HL Tau SPW0 1024^2": [2645, 0.60, 4408],
+        "HL Tau SPW0 2048^2": [10339, 2.39, 4326], "HL Tau SPW0 4096^2": [55009, 9.86, 5579]},
+    "note": "context only: other hardware, another forward model (gridded) and real data",
+}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(ds, target_s: float = 12.0, single_s: float = 4.0):
     """FP64 oracle on a bounded sample: the forward model at a subset of the
     visibilities (all pixels) and the adjoint at a subset of the pixels (all
     visibilities).  One vis.pixel evaluation = one forward term + one adjoint
-    term, so the rate is (forward pairs + adjoint pairs) / 2 / time."""
+    term, so the rate is (forward pairs + adjoint pairs) / 2 / time.  Timed on
+    every host thread OpenMP uses, then on one thread (the paper's speedups
+    are against a single CPU thread)."""
     import numpy as np
 
     import oracle
@@ -94,20 +123,40 @@ def cpu_baseline(ds, target_s: float = 12.0):
 
     def sizes(rate, seconds):
         pairs_goal = rate * seconds * 2.0
-        return (int(min(ch.nvis, max(64, pairs_goal / 2.0 / (n * n)))),
-                int(min(n * n, max(64, pairs_goal / 2.0 / ch.nvis))))
+        return (int(min(ch.nvis, max(4, pairs_goal / 2.0 / (n * n)))),
+                int(min(n * n, max(4, pairs_goal / 2.0 / ch.nvis))))
 
-    # calibrate on a tiny sample, then on one of ~1 s (the tiny one
-    # underestimates the rate), then size the real one to ~target_s
-    p0, t0 = run(min(64, ch.nvis), 64)
-    p1, t1 = run(*sizes(p0 / max(t0, 1e-6), 1.0))
-    n_vis, n_pix = sizes(p1 / max(t1, 1e-6), target_s)
-    pairs, dt = run(n_vis, n_pix)
-    return {"value": pairs / dt, "unit": "vis·pixel evals/s", "cores": oracle.num_threads(),
+    def timed(seconds):
+        # calibrate on a tiny sample, then on one of ~1 s (the tiny one
+        # underestimates the rate), then size the real one
+        p0, t0 = run(min(4, ch.nvis), 4)
+        p1, t1 = run(*sizes(p0 / max(t0, 1e-6), min(1.0, seconds / 4)))
+        n_vis, n_pix = sizes(p1 / max(t1, 1e-6), seconds)
+        pairs, dt = run(n_vis, n_pix)
+        return pairs / dt, n_vis, n_pix, dt
+
+    threads = oracle.num_threads()
+    rate, n_vis, n_pix, dt = timed(target_s)
+    oracle.set_threads(1)
+    try:
+        rate1, n_vis1, n_pix1, dt1 = timed(single_s)
+    finally:
+        oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
+    return {"value": rate, "unit": "vis·pixel evals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"FP64 direct sums: forward at {n_vis} of {ch.nvis} visibilities x {n * n} pixels "
-                      f"+ adjoint at {n_pix} of {n * n} pixels x {ch.nvis} visibilities; {dt:.1f} s",
-            "seconds": dt}
+                      f"+ adjoint at {n_pix} of {n * n} pixels x {ch.nvis} visibilities; {dt:.1f} s on "
+                      f"{threads} threads",
+            "seconds": dt,
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(), "host_cpus_usable": affinity,
+            "single_thread": {"value": rate1, "unit": "vis·pixel evals/s", "cores": 1,
+                              "sample": f"forward at {n_vis1} visibilities + adjoint at {n_pix1} pixels; "
+                                        f"{dt1:.1f} s"},
+            "paper_context": PAPER_CONTEXT}
 
 
 def run_steps(ctx, steps, warmup, graph):
@@ -149,20 +198,32 @@ def run_steps(ctx, steps, warmup, graph):
     return ms, t_wall, kern
 
 
-def eval_error(ds, ctx_a, ctx_b):
-    """Relative differences of Phi and grad Phi between two precisions at the
-    P3 evaluation image (same inputs)."""
+def eval_error(ds, ctx, ref):
+    """Relative error of V^m, chi^2, Phi and grad Phi of `ctx` against the
+    FP64 context `ref` (the FP64 path that the full-size parity tests hold to
+    the oracle at 1e-12) at the P1 and P3 evaluation images (same inputs,
+    FP32-rounded images)."""
     import numpy as np
     import torch
     from paper_1703_02920_amd import synth
-    img = torch.tensor(synth.eval_images(ds, "P3"), dtype=torch.float32, device=ctx_a.device)
-    sa, ga = ctx_a.phi_and_grad(img)
-    sb, gb = ctx_b.phi_and_grad(img)
-    torch.cuda.synchronize()
-    phi_a, phi_b = float(sa[:, 0].sum()), float(sb[:, 0].sum())
-    ga, gb = ga.double().cpu().numpy(), gb.double().cpu().numpy()
-    return {"phi": abs(phi_a - phi_b) / abs(phi_b),
-            "grad": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb))}
+    out = {}
+    for which in ("P1", "P3"):
+        x = synth.eval_images(ds, which).astype(np.float32)
+        I = torch.tensor(x, dtype=ctx.dtype, device=ctx.device)
+        Ir = torch.tensor(x.astype(np.float64), dtype=torch.float64, device=ref.device)
+        V, Vr = ctx.forward(I).clone(), ref.forward(Ir).clone()
+        s, g = ctx.phi_and_grad(I)
+        sr, gr = ref.phi_and_grad(Ir)
+        torch.cuda.synchronize()
+
+        def rel(a, b):
+            return float(torch.linalg.vector_norm((a.double() - b.double())) / torch.linalg.vector_norm(b.double()))
+
+        out[which] = {"V": rel(V, Vr),
+                      "chi2": abs(float(s[:, 1].sum()) - float(sr[:, 1].sum())) / abs(float(sr[:, 1].sum())),
+                      "phi": abs(float(s[:, 0].sum()) - float(sr[:, 0].sum())) / abs(float(sr[:, 0].sum())),
+                      "grad": rel(g, gr)}
+    return out
 
 
 def _median_eval_ms(ctx, img, reps=20, warmup=3):
@@ -345,11 +406,11 @@ def centred_region(n, frac):
     return m
 
 
-def cg_compare(c, precs, iters=None, mode=None, region=None):
+def cg_compare(c, precs, iters=None, mode=None, region=None, quiet=False):
     """M2: T graph-replayed projected-CG iterations from I = M in each
     precision; iterations/s, and the relative error of Phi_T and of the final
-    image against the FP64 trajectory (the FP64 path is held to 1e-12 of the
-    oracle by the parity tests)."""
+    image against the FP64 trajectory (the FP64 forward and adjoint are held
+    to 1e-12 of the oracle at these sizes by the full-size parity tests)."""
     import numpy as np
     import torch
     from paper_1703_02920_amd import synth
@@ -383,7 +444,7 @@ def cg_compare(c, precs, iters=None, mode=None, region=None):
             row["rel_err_phi_T_vs_fp64"] = abs(phi - ref[0]) / abs(ref[0])
             row["rel_err_image_T_vs_fp64"] = float(np.linalg.norm(img - ref[1]) / np.linalg.norm(ref[1]))
         res[prec] = row
-        print(json.dumps(row), flush=True)
+        print(json.dumps(row), file=sys.stderr if quiet else sys.stdout, flush=True)
         ctx.close()
     return res
 
@@ -393,11 +454,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload configuration (1..6)")
+    ap.add_argument("--config", type=int, default=5, help="workload configuration (1..6)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
     ap.add_argument("--graph", action="store_true", help="replay the step as a HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision companion runs")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP64-referenced errors and the split-precision companion runs")
+    ap.add_argument("--no-cg", action="store_true",
+                    help="skip the full CG trajectories (FP64 reference, FP32, bf16x3, fp16x3)")
     ap.add_argument("--eval-sweep", default="", metavar="CONFIGS",
                     help="only time single Phi + grad evaluations on these configurations (e.g. 1,2,3,4,5)")
     ap.add_argument("--cg-compare", type=int, default=0, metavar="CONFIG",
@@ -448,9 +512,10 @@ def main():
     from paper_1703_02920_amd.uvmem import Context
 
     torch.cuda.set_device(0)
+    print(f"bench: generating workload c{args.config}", file=sys.stderr, flush=True)
     ds = synth.make_config(args.config)
     ctx = Context.from_dataset(ds, args.precision)
-    print(f"bench: {ds.description}", file=sys.stderr, flush=True)
+    print(f"bench: {ds.description}; {args.precision} CG steps", file=sys.stderr, flush=True)
     ms, t_wall, kern = run_steps(ctx, args.steps, args.warmup, args.graph)
     pairs = ds.pairs
     value = pairs * args.steps / (ms / 1e3)
@@ -464,22 +529,37 @@ def main():
                 "frac": achieved / PEAK[args.precision],
                 "traffic": traffic_from_profiles(KERNELS[args.precision][0 if dom == "forward" else 1],
                                                  workload),
-                "kernel": dom, "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
+                "kernel": KERNELS[args.precision][0 if dom == "forward" else 1], "direction": dom,
+                "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
                 "other_kernel_ms": {k: v for k, v in kern.items() if k != dom}}
-    mixed = None
-    if args.precision == "fp32" and not args.no_mixed:
-        mixed = {}
-        for mp in ("bf16x3", "fp16x3"):
-            print(f"bench: split-precision ({mp}) run", file=sys.stderr, flush=True)
-            mctx = Context.from_dataset(ds, mp)
-            mms, _, mkern = run_steps(mctx, args.steps, args.warmup, args.graph)
-            mixed[mp] = {"value": pairs * args.steps / (mms / 1e3),
-                         "ms_per_step": mms / args.steps, "cg_iters_per_s": args.steps / (mms / 1e3),
-                         "kernel_ms": mkern,
-                         "mfma_frac_16bit_algorithmic": {k: flops_per_launch / (v / 1e3) / 1e12 / PEAK[mp]
-                                                         for k, v in mkern.items()},
-                         "rel_err_vs_fp32_at_P3": eval_error(ds, mctx, ctx)}
-            mctx.close()
+    # errors against the FP64 path (held to the oracle at 1e-12 at this size
+    # by the full-size parity tests), and the split-precision companions
+    errors, mixed, cg = None, None, None
+    if not args.no_mixed and args.precision != "fp64":
+        print("bench: FP64 reference evaluations", file=sys.stderr, flush=True)
+        ref = Context.from_dataset(ds, "fp64")
+        errors = eval_error(ds, ctx, ref)
+        if args.precision == "fp32":
+            mixed = {}
+            for mp in ("bf16x3", "fp16x3"):
+                print(f"bench: split-precision ({mp}) CG steps", file=sys.stderr, flush=True)
+                mctx = Context.from_dataset(ds, mp)
+                mms, _, mkern = run_steps(mctx, args.steps, args.warmup, args.graph)
+                mixed[mp] = {"value": pairs * args.steps / (mms / 1e3),
+                             "ms_per_step": mms / args.steps, "cg_iters_per_s": args.steps / (mms / 1e3),
+                             "kernel_ms": mkern,
+                             "mfma_frac_16bit_algorithmic": {k: flops_per_launch / (v / 1e3) / 1e12 / PEAK[mp]
+                                                             for k, v in mkern.items()},
+                             "mfma_frac_3_product_issued": {k: 3 * flops_per_launch / (v / 1e3) / 1e12 / PEAK[mp]
+                                                            for k, v in mkern.items()},
+                             "rel_err_vs_fp64": eval_error(ds, mctx, ref)}
+                mctx.close()
+        ref.close()
+    if not args.no_cg and args.precision == "fp32":
+        print(f"bench: {ds.cg_iters}-iteration CG trajectories, FP64 reference and each precision",
+              file=sys.stderr, flush=True)
+        ctx.close()
+        cg = cg_compare(args.config, ["fp32", "bf16x3", "fp16x3"], quiet=True)
     cpu = None
     if not args.no_cpu:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -505,7 +585,9 @@ def main():
         "wall_s": t_wall,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rel_err_vs_fp64": errors,
         "mixed": mixed,
+        "cg_trajectories": cg,
     }
     print(json.dumps(out), flush=True)
 

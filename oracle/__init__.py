@@ -60,6 +60,8 @@ def lib():
                                      dp, dp, dp, dp, dp]
         L.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp, dp,
                                  ctypes.c_int64, i64p, dp]
+        L.or_forward_pix.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, dp, dp, dp,
+                                     ctypes.c_int64, i64p, dp, dp]
         L.or_chi2.argtypes = [ctypes.c_int64, dp, dp, dp, dp]
         L.or_chi2.restype = ctypes.c_double
         L.or_entropy.argtypes = [ctypes.c_int64, dp, ctypes.c_double, dp]
@@ -117,6 +119,38 @@ def forward_sel(n: int, cell: float, idx, u, v, A, I) -> np.ndarray:
                          _d(u), _d(v), _d(Ak) if Ak is not None else None, _d(I),
                          _d(V.view(np.float64)))
     return V
+
+
+def forward_pix(n: int, cell: float, u, v, A: Optional[np.ndarray], pix, vals) -> np.ndarray:
+    """Forward model (Eq. fft) of an image that is zero except vals[q] at
+    linear pixel pix[q]: V_k = sum_q A[pix_q] vals_q exp(-2 pi i (u_k x + v_k y))."""
+    u, v = _f64(u), _f64(v)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    vals = _f64(vals)
+    assert pix.shape == vals.shape and pix.ndim == 1
+    Ak = None if A is None else _f64(A)
+    V = np.empty(u.shape[0], dtype=np.complex128)
+    lib().or_forward_pix(n, cell, u.shape[0], _d(u), _d(v), _d(Ak) if Ak is not None else None,
+                         pix.shape[0], pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(vals),
+                         _d(V.view(np.float64)))
+    return V
+
+
+def phi_at_pixel_steps(n, cell, u, v, A, I, V_I, Vo, w, M, lam, pix, h):
+    """Phi (Eq. phi3) at the images I + h_q e_{p_q}, one pixel changed at a
+    time, for q = 0..len(pix)-1: the model visibilities are V(I) + h_q V(e_p)
+    (the forward model is linear), chi^2 and S are then evaluated from their
+    definitions.  V_I = forward(I) is passed in so that it is computed once."""
+    I = _f64(I)
+    out = np.empty(len(pix))
+    for q, (p, hq) in enumerate(zip(pix, h)):
+        Vp = forward_pix(n, cell, u, v, A, [p], [hq])
+        x2, _ = chi2(V_I + Vp, Vo, w)
+        Ip = I.copy()
+        Ip.flat[p] += hq
+        S, _ = entropy(Ip, M)
+        out[q] = x2 + lam * S
+    return out
 
 
 def adjoint(n: int, cell: float, u, v, A: Optional[np.ndarray], c, pix=None) -> np.ndarray:

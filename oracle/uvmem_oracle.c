@@ -154,6 +154,32 @@ void or_forward_sel(int n, double cell, int64_t nsel, const int64_t *idx,
     }
 }
 
+/* Forward model of an image that is zero except at the listed pixels
+ * (Eq. fft with the sum restricted to its nonzero terms):
+ *   V_k = sum_q A_{p_q} val_q exp(-2 pi i (u_k x_{j_q} + v_k y_{i_q})),
+ * p_q = N i_q + j_q.  Used to evaluate the model at a one-pixel change of an
+ * image by linearity, V(I + h e_p) = V(I) + h V(e_p). */
+void or_forward_pix(int n, double cell, int64_t nvis, const double *u, const double *v,
+                    const double *A, int64_t npix, const int64_t *pix, const double *val, double *V) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nvis; ++k) {
+        nsum re = {0, 0}, im = {0, 0};
+        for (int64_t q = 0; q < npix; ++q) {
+            int64_t p = pix[q];
+            int i = (int)(p / n), j = (int)(p % n);
+            double x = (double)(j - n / 2) * cell;
+            double y = (double)(i - n / 2) * cell;
+            double b = (A ? A[p] : 1.0) * val[q];
+            double c, s;
+            cis(u[k] * x + v[k] * y, &c, &s);
+            nadd(&re, b * c);
+            nadd(&im, -b * s);
+        }
+        V[2 * k] = nval(&re);
+        V[2 * k + 1] = nval(&im);
+    }
+}
+
 /* chi^2 = 1/2 sum_k w_k |V_k - Vo_k|^2  (Eq. phi2; Alg. 2 gives the per-term
  * residual V^R = V^m - V^o).  R (may be NULL) receives the residuals. */
 double or_chi2(int64_t nvis, const double *V, const double *Vo, const double *w, double *R) {

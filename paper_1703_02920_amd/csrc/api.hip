@@ -61,6 +61,9 @@ hipError_t fetch(void *dst, const void *src, size_t n) {
 template <typename T>
 hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
     size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    // test hook: UVMEM_TEST_FAIL_ALLOC=k makes the k-th allocation of a
+    // finalize fail as if the device were out of memory
+    if (c->fail_alloc_at >= 0 && c->n_alloc++ == c->fail_alloc_at) return hipErrorOutOfMemory;
     hipError_t e = hipMalloc((void **)p, bytes);
     if (e == hipSuccess) {
         c->bytes_device += bytes;
@@ -69,22 +72,42 @@ hipError_t dalloc(uvmem_ctx *c, T **p, size_t count) {
     return e;
 }
 
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// Release every device buffer, graph, stream and event of the context and
+// reset the handles, so that a second call (destroy after a failed finalize)
+// frees nothing twice.
 void free_all(uvmem_ctx *c) {
-    void *ptrs[] = {c->d_a, c->d_b, c->d_vo, c->d_w, c->d_beam, c->d_fwdp, c->d_adj, c->d_vis,
-                    c->d_slot_base, c->d_vis_base, c->d_ivis_base, c->d_ichan_base, c->d_chan_img, c->d_R,
-                    c->d_Vd, c->d_vpart, c->d_gpart, c->d_bop,
-                    c->d_g, c->d_gt, c->d_dir, c->d_scal, c->d_chan, c->d_ls, c->d_ppart, c->d_vispart,
-                    c->d_flag, c->d_hist_ptr, c->d_iter_ctr, c->d_gtw, c->d_gx1, c->d_ggrid, c->d_gcell,
-                    c->d_gperm, c->d_gfxy, c->d_gsc, c->d_gdidx, c->d_gdlist, c->d_gdsum, c->d_wscale,
-                    c->d_mask, c->d_fwdp_m, c->d_adj_m, c->d_slot_base_m};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    dfree(c->d_a); dfree(c->d_b); dfree(c->d_vo); dfree(c->d_w); dfree(c->d_beam);
+    dfree(c->d_fwdp); dfree(c->d_adj); dfree(c->d_vis);
+    dfree(c->d_slot_base); dfree(c->d_vis_base); dfree(c->d_ivis_base); dfree(c->d_ichan_base);
+    dfree(c->d_chan_img);
+    dfree(c->d_R); dfree(c->d_Vd); dfree(c->d_vpart); dfree(c->d_gpart); dfree(c->d_bop);
+    dfree(c->d_g); dfree(c->d_gt); dfree(c->d_dir);
+    dfree(c->d_scal); dfree(c->d_chan); dfree(c->d_ls); dfree(c->d_ppart); dfree(c->d_vispart);
+    dfree(c->d_flag); dfree(c->d_hist_ptr); dfree(c->d_iter_ctr);
+    dfree(c->d_gtw); dfree(c->d_gx1); dfree(c->d_ggrid); dfree(c->d_gcell); dfree(c->d_gperm);
+    dfree(c->d_gfxy); dfree(c->d_gsc); dfree(c->d_gdidx); dfree(c->d_gdlist); dfree(c->d_gdsum);
+    dfree(c->d_wscale); dfree(c->d_mask);
+    dfree(c->d_fwdp_m); dfree(c->d_adj_m); dfree(c->d_slot_base_m);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_I = nullptr;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     for (auto &pr : c->pend[0]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
     for (auto &pr : c->pend[1]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    c->pend[0].clear();
+    c->pend[1].clear();
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     c->ev_pool.clear();
+    c->bytes_device = 0;
 }
 
 // ---------------------------------------------------------------- timing
@@ -309,28 +332,36 @@ int uvmem_set_uv(uvmem_ctx *c, int chan, int64_t nvis, const double *u, const do
     if (!(cell_rad > 0.0) || !std::isfinite(cell_rad)) return fail(c, UVMEM_EINVAL, "bad cell");
     if (c->cell_set && cell_rad != c->cell)
         return fail(c, UVMEM_EINVAL, "cell differs between channels (one pixel grid)");
-    c->cell = cell_rad;
-    c->cell_set = true;
-    c->nvis[chan] = nvis;
+    // validate into temporaries: the channel's staged data change only on success
+    std::vector<double> hu, hv;
     try {
-        c->hu[chan].resize(nvis);
-        c->hv[chan].resize(nvis);
+        hu.resize(nvis);
+        hv.resize(nvis);
     } catch (...) {
         return fail(c, UVMEM_ENOMEM, "host staging");
     }
-    HIPCHK(c, fetch(c->hu[chan].data(), u, nvis * sizeof(double)));
-    HIPCHK(c, fetch(c->hv[chan].data(), v, nvis * sizeof(double)));
+    HIPCHK(c, fetch(hu.data(), u, nvis * sizeof(double)));
+    HIPCHK(c, fetch(hv.data(), v, nvis * sizeof(double)));
     // at most 4096 cycles per pixel (8192 times the grid's Nyquist limit):
     // keeps the FP64 phases a m, and the FP32 twiddles' quarter-turn counts
     // 4 a m, far inside their exact ranges for any image side
     constexpr double UV_MAX_CYCLES = 4096.0;
     for (int64_t k = 0; k < nvis; ++k) {
-        const double uk = c->hu[chan][k], vk = c->hv[chan][k];
+        const double uk = hu[k], vk = hv[k];
         if (!std::isfinite(uk) || !std::isfinite(vk))
             return fail(c, UVMEM_EINVAL, "non-finite u/v at %lld", (long long)k);
         if (std::fabs(uk) * cell_rad > UV_MAX_CYCLES || std::fabs(vk) * cell_rad > UV_MAX_CYCLES)
             return fail(c, UVMEM_EINVAL, "u/v at %lld is beyond %g cycles per pixel", (long long)k, UV_MAX_CYCLES);
     }
+    c->cell = cell_rad;
+    c->cell_set = true;
+    // new coordinates invalidate the channel's visibilities and weights
+    // (their length may have changed): they must be set again
+    c->nvis[chan] = nvis;
+    c->hu[chan].swap(hu);
+    c->hv[chan].swap(hv);
+    std::vector<float>().swap(c->hvis[chan]);
+    std::vector<float>().swap(c->hw[chan]);
     c->has_uv[chan] = 1;
     c->has_vis[chan] = nvis == 0;
     c->has_w[chan] = nvis == 0;
@@ -344,8 +375,12 @@ int uvmem_set_vis(uvmem_ctx *c, int chan, const float *vis) {
     if (!c->has_uv[chan]) return fail(c, UVMEM_ESTATE, "set_vis before set_uv");
     const int64_t nv = c->nvis[chan];
     if (nv > 0 && !vis) return fail(c, UVMEM_EINVAL, "null vis");
-    try { c->hvis[chan].resize(2 * nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
-    HIPCHK(c, fetch(c->hvis[chan].data(), vis, 2 * nv * sizeof(float)));
+    std::vector<float> hvis;
+    try { hvis.resize(2 * nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(hvis.data(), vis, 2 * nv * sizeof(float)));
+    for (int64_t k = 0; k < 2 * nv; ++k)
+        if (!std::isfinite(hvis[k])) return fail(c, UVMEM_EINVAL, "visibility %lld is not finite", (long long)(k / 2));
+    c->hvis[chan].swap(hvis);
     c->has_vis[chan] = 1;
     return UVMEM_OK;
 }
@@ -357,11 +392,13 @@ int uvmem_set_weights(uvmem_ctx *c, int chan, const float *w) {
     if (!c->has_uv[chan]) return fail(c, UVMEM_ESTATE, "set_weights before set_uv");
     const int64_t nv = c->nvis[chan];
     if (nv > 0 && !w) return fail(c, UVMEM_EINVAL, "null weights");
-    try { c->hw[chan].resize(nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
-    HIPCHK(c, fetch(c->hw[chan].data(), w, nv * sizeof(float)));
+    std::vector<float> hw;
+    try { hw.resize(nv); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(hw.data(), w, nv * sizeof(float)));
     for (int64_t k = 0; k < nv; ++k)
-        if (!(c->hw[chan][k] >= 0.0f) || !std::isfinite(c->hw[chan][k]))
+        if (!(hw[k] >= 0.0f) || !std::isfinite(hw[k]))
             return fail(c, UVMEM_EINVAL, "weight %lld is negative or not finite", (long long)k);
+    c->hw[chan].swap(hw);
     c->has_w[chan] = 1;
     return UVMEM_OK;
 }
@@ -383,10 +420,12 @@ int uvmem_set_beam_image(uvmem_ctx *c, int chan, const float *A) {
     if (!valid_chan(c, chan)) return fail(c, UVMEM_EINVAL, "channel %d out of range", chan);
     if (!A) return fail(c, UVMEM_EINVAL, "null beam image");
     const size_t npix = (size_t)c->n * c->n;
-    try { c->hbeam[chan].resize(npix); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
-    HIPCHK(c, fetch(c->hbeam[chan].data(), A, npix * sizeof(float)));
+    std::vector<float> hb;
+    try { hb.resize(npix); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(hb.data(), A, npix * sizeof(float)));
     for (size_t p = 0; p < npix; ++p)
-        if (!std::isfinite(c->hbeam[chan][p])) return fail(c, UVMEM_EINVAL, "non-finite beam value");
+        if (!std::isfinite(hb[p])) return fail(c, UVMEM_EINVAL, "non-finite beam value");
+    c->hbeam[chan].swap(hb);
     c->fwhm[chan] = 0.0;
     c->has_beam[chan] = 1;
     return UVMEM_OK;
@@ -410,9 +449,11 @@ int uvmem_set_mask(uvmem_ctx *c, int img, const uint8_t *mask) {
         std::vector<unsigned char>().swap(c->hmask[img]);
         return UVMEM_OK;
     }
-    c->hmask[img].resize((size_t)c->n * c->n);
-    HIPCHK(c, fetch(c->hmask[img].data(), mask, (size_t)c->n * c->n));
-    for (auto &x : c->hmask[img]) x = x ? 1 : 0;
+    std::vector<unsigned char> hm;
+    try { hm.resize((size_t)c->n * c->n); } catch (...) { return fail(c, UVMEM_ENOMEM, "host staging"); }
+    HIPCHK(c, fetch(hm.data(), mask, (size_t)c->n * c->n));
+    for (auto &x : hm) x = x ? 1 : 0;
+    c->hmask[img].swap(hm);
     return UVMEM_OK;
 }
 
@@ -436,9 +477,30 @@ int uvmem_set_prior(uvmem_ctx *c, double M, double lambda) {
     return UVMEM_OK;
 }
 
+extern "C++" {
+namespace {
+int finalize_impl(uvmem_ctx *c);
+}
+}
+
 int uvmem_finalize(uvmem_ctx *c) {
     if (!c) return UVMEM_EINVAL;
     if (c->finalized) return fail(c, UVMEM_ESTATE, "finalize called twice");
+    // host-side tables may not fit in memory: no exception crosses the ABI
+    try {
+        return finalize_impl(c);
+    } catch (const std::bad_alloc &) {
+        free_all(c);
+        return fail(c, UVMEM_ENOMEM, "host memory for the finalize tables");
+    } catch (...) {
+        free_all(c);
+        return fail(c, UVMEM_EINVAL, "finalize failed");
+    }
+}
+
+extern "C++" {
+namespace {
+int finalize_impl(uvmem_ctx *c) {
     const int C = c->nchan;
     for (int ch = 0; ch < C; ++ch) {
         if (!c->has_uv[ch]) return fail(c, UVMEM_ESTATE, "channel %d has no uv", ch);
@@ -457,6 +519,9 @@ int uvmem_finalize(uvmem_ctx *c) {
                         (long long)L);
     }
     HIPCHK(c, hipSetDevice(c->device));
+    c->fail_alloc_at = -1;
+    c->n_alloc = 0;
+    if (const char *env = std::getenv("UVMEM_TEST_FAIL_ALLOC")) c->fail_alloc_at = std::atoi(env);
     build_layout(c);
     const int n = c->n, np = c->np;
     const size_t npix = (size_t)n * n;
@@ -836,7 +901,6 @@ int uvmem_finalize(uvmem_ctx *c) {
     }
     if (e != hipSuccess) {
         free_all(c);
-        c->d_a = nullptr;
         (void)hipGetLastError();
         return fail(c, e == hipErrorOutOfMemory ? UVMEM_ENOMEM : UVMEM_EDEVICE, "device allocation: %s",
                     hipGetErrorString(e));
@@ -872,8 +936,18 @@ int uvmem_finalize(uvmem_ctx *c) {
         up(c->d_gdidx, gdidx.data(), gdidx.size() * sizeof(int));
         up(c->d_gdlist, gdlist.data(), gdlist.size() * sizeof(int));
     }
-    if (e != hipSuccess) return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
-    HIPCHK(c, hipDeviceSynchronize());
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_all(c);
+        (void)hipGetLastError();
+        return fail(c, UVMEM_EDEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(c);
+        (void)hipGetLastError();
+        return fail(c, UVMEM_EDEVICE, "finalize: %s", hipGetErrorString(e));
+    }
     // release host staging
     for (int ch = 0; ch < C; ++ch) {
         std::vector<double>().swap(c->hu[ch]);
@@ -885,6 +959,8 @@ int uvmem_finalize(uvmem_ctx *c) {
     c->finalized = true;
     return UVMEM_OK;
 }
+}  // namespace
+}  // extern "C++"
 
 int uvmem_phi_and_grad(uvmem_ctx *c, const void *I, void *grad, double *scal) {
     int s = check_ready(c);
@@ -1084,12 +1160,14 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
         return UVMEM_OK;
     }
     if (!c->graph_exec || c->graph_I != I) {
+        // first graph call on this image: capture one step (and the history
+        // copy) on the capture stream made at finalize and instantiate it
         if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
         if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
-        hipStream_t cap;
-        HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        // the capture stream must not start before work already queued on the
-        // context's stream: graph launches go to that stream, so ordering holds.
+        c->graph_I = nullptr;
+        hipStream_t cap = c->cap_stream;
+        // graph launches go to the context's stream, so a replay still runs
+        // after the work queued there before it
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) e = launch_cg_step(c, I, nullptr, cap);
         if (e == hipSuccess) e = launch_copy_scal(c, nullptr, c->d_iter_ctr, cap);
@@ -1097,7 +1175,6 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
         hipError_t e2 = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
-        (void)hipStreamDestroy(cap);
         if (e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             c->graph_exec = nullptr;
@@ -1106,12 +1183,9 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
         c->graph = g;
         c->graph_I = I;
     }
-    // point the history copy at the caller's buffer and reset the counter
-    long long hp[2] = {(long long)(uintptr_t)hist, 0};
-    HIPCHK(c, hipMemcpyAsync(c->d_hist_ptr, &hp[0], sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_iter_ctr, &hp[1], sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    // the two copies read host stack memory: let them finish before returning
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // point the history copy at the caller's buffer and reset the counter:
+    // a kernel argument carries the pointer, so nothing waits for the host
+    HIPCHK(c, launch_set_hist(c, hist, c->stream));
     for (int t = 0; t < iters; ++t) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
     return UVMEM_OK;
 }

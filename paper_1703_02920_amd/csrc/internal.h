@@ -168,7 +168,7 @@ struct uvmem_ctx {
     double2 *d_R = nullptr, *d_Vd = nullptr, *d_vpart = nullptr;
     void *d_gpart = nullptr;                    // split-K adjoint partials [slots][Np][Np]: FP64 or FP32
     bool gpart_f32 = false;                     // partials stored as FP32 (split paths; FP32 when every
-                                                // chunk is one FP32 sum of at most 512 visibilities)
+                                                // chunk is one FP32 sum of at most ADJ_F32_SUM visibilities)
     void *d_bop = nullptr;                      // operand image [C][np][np]
     void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [nimg][n][n]
     double *d_scal = nullptr;                   // [nimg][NSCAL]
@@ -204,8 +204,12 @@ struct uvmem_ctx {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     void *graph_I = nullptr;
+    hipStream_t cap_stream = nullptr;           // capture stream of the CG graph (made at finalize)
     long long *d_hist_ptr = nullptr;            // device copy of the cg_run history pointer
     long long *d_iter_ctr = nullptr;
+    // test hook (UVMEM_TEST_FAIL_ALLOC): index of the finalize allocation
+    // that fails, -1 for none; allocations counted so far
+    int fail_alloc_at = -1, n_alloc = 0;
 
     // timing
     bool timing = false;
@@ -251,5 +255,8 @@ hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user_scal, hipStr
 // model, 1: between forward and adjoint, 2: after the adjoint).
 hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user_scal, int phase, hipStream_t st);
 hipError_t launch_copy_scal(const uvmem_ctx *c, double *dst, long long *ctr, hipStream_t st);
+// Point the graph's history copy at `hist` (may be null) and reset its
+// counter, by a one-thread kernel on `st` (no host memory involved).
+hipError_t launch_set_hist(const uvmem_ctx *c, double *hist, hipStream_t st);
 
 }  // namespace uvm

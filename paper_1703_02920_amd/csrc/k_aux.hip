@@ -785,6 +785,13 @@ __global__ void k_copy_hist(const double *__restrict__ scal, const long long *__
     if (threadIdx.x == 0) ctr[0] = t + 1;
 }
 
+__global__ void k_set_hist(long long *__restrict__ hist_ptr, long long *__restrict__ ctr, long long hist) {
+    if (threadIdx.x == 0) {
+        hist_ptr[0] = hist;
+        ctr[0] = 0;
+    }
+}
+
 template <typename R> inline R *P(void *p) { return reinterpret_cast<R *>(p); }
 template <typename R> inline const R *CP(const void *p) { return reinterpret_cast<const R *>(p); }
 
@@ -913,6 +920,12 @@ hipError_t launch_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st)
 hipError_t launch_copy_scal(const uvmem_ctx *c, double *, long long *ctr, hipStream_t st) {
     hipLaunchKernelGGL(k_copy_hist, dim3(1), dim3(NTHR), 0, st, c->d_scal,
                        reinterpret_cast<const long long *>(c->d_hist_ptr), ctr, c->nimg * UVMEM_NSCAL);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_hist(const uvmem_ctx *c, double *hist, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_hist, dim3(1), dim3(64), 0, st, c->d_hist_ptr, c->d_iter_ctr,
+                       (long long)(uintptr_t)hist);
     return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ class Context:
         if code != OK:
             raise UvmemError(code, self._lib.uvmem_strerror(code).decode())
         self._h = h
-        self._nvis = [0] * self.n_chan
+        self._nvis = [None] * self.n_chan   # visibility count per channel once set_uv succeeded
         self._keep = []
 
     # ------------------------------------------------------------ plumbing
@@ -159,25 +159,49 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------ setup
+    def _chan(self, chan: int) -> int:
+        chan = int(chan)
+        if not 0 <= chan < self.n_chan:
+            raise ValueError(f"channel {chan} out of range [0, {self.n_chan})")
+        return chan
+
+    def _staged(self, chan: int, a: np.ndarray, what: str) -> np.ndarray:
+        """Check that a per-visibility array matches the channel's count (the
+        C side reads exactly that many elements from the pointer)."""
+        if self._nvis[chan] is None:
+            return a    # no coordinates yet: the library reports the call order
+        if a.ndim != 1 or a.shape[0] != self._nvis[chan]:
+            raise ValueError(f"{what} of channel {chan} must be 1-D with {self._nvis[chan]} elements "
+                             f"(got shape {a.shape})")
+        return a
+
     def set_uv(self, chan: int, u, v, cell: float):
+        chan = self._chan(chan)
         u = np.ascontiguousarray(u, np.float64)
         v = np.ascontiguousarray(v, np.float64)
-        self._nvis[chan] = int(u.shape[0])
+        if u.ndim != 1 or v.shape != u.shape:
+            raise ValueError(f"u and v must be 1-D arrays of the same length (got {u.shape}, {v.shape})")
         self._call("uvmem_set_uv", chan, u.shape[0], _ptr(u), _ptr(v), float(cell))
+        self._nvis[chan] = int(u.shape[0])
 
     def set_vis(self, chan: int, vis):
-        vis = np.ascontiguousarray(vis, np.complex64)
+        chan = self._chan(chan)
+        vis = self._staged(chan, np.ascontiguousarray(vis, np.complex64), "visibilities")
         self._call("uvmem_set_vis", chan, _ptr(vis))
 
     def set_weights(self, chan: int, w):
-        w = np.ascontiguousarray(w, np.float32)
+        chan = self._chan(chan)
+        w = self._staged(chan, np.ascontiguousarray(w, np.float32), "weights")
         self._call("uvmem_set_weights", chan, _ptr(w))
 
     def set_beam(self, chan: int, fwhm: float):
-        self._call("uvmem_set_beam", chan, float(fwhm))
+        self._call("uvmem_set_beam", self._chan(chan), float(fwhm))
 
     def set_beam_image(self, chan: int, A):
+        chan = self._chan(chan)
         A = np.ascontiguousarray(A, np.float32)
+        if A.shape != (self.n, self.n):
+            raise ValueError(f"beam image must be {self.n} x {self.n} (got shape {A.shape})")
         self._call("uvmem_set_beam_image", chan, _ptr(A))
 
     def set_phase_centre(self, chan: int, x0: float, y0: float):

@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 output for the profiles folder.
 
-    python -m paper_1703_02920_amd.rocprof_summary stats DIR OUT.md --cmd "..." [--note "..."]
+    python rocprof_summary.py stats DIR OUT.md --cmd "..." [--note "..."]
         kernel statistics (``--kernel-trace --stats --output-format csv``) as a
         markdown table, with the command that produced them.
-    python -m paper_1703_02920_amd.rocprof_summary traffic --workload W --fetch DIR --write DIR \\
+    python rocprof_summary.py traffic --workload W --fetch DIR --write DIR \\
             --copy-fetch DIR --copy-write DIR --copy-bytes B --kernels k_forward k_adjoint --out OUT.md
         HBM traffic per launch from two counter runs (FETCH_SIZE, then
         WRITE_SIZE, KiB per dispatch), each scaled by the same counter's
@@ -22,7 +22,7 @@ import re
 import statistics
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def _demangle(name: str) -> str:

@@ -17,18 +17,20 @@ from paper_1703_02920_amd import synth  # noqa: E402
 TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-4, "fp16x3": 1e-4}
 
 
-# CG trajectory tolerances: FP64 rounding and the fixed-count line search
-# leave ~1e-10 differences that the iteration propagates; the FP32 path
-# carries its 1e-7-level evaluation error through the same iteration.  On
-# this problem every step after the first ends on alpha_max (one more pixel
-# reaches the floor), and alpha_max = min (I - M)/(-d) is decided by pixels
-# just above the floor: the split path's ~1e-5 evaluation error changes
-# which pixel binds, so its trajectory is held to the first step tightly and
-# to the whole run and final image loosely.
+# CG trajectory tolerances (relative: max over the iterations of Phi, the
+# final image in l2, the first step's Phi).  FP64 rounding and the
+# fixed-count line search leave ~1e-10 differences that the iteration
+# propagates.  The FP32 and split paths carry their evaluation errors (~1e-7
+# and ~1e-5) through the same iteration; every step after the first ends on
+# alpha_max = min (I - M)/(-d), decided by pixels just above the floor, so a
+# small evaluation error can change which pixel binds and move alpha.  The
+# bars are small multiples of the largest errors observed on the GPU over the
+# CG tests that use them (c1: FP32 image 4.8e-7; bf16x3 Phi 2.3e-5, image
+# 3.0e-6), not the slack a broken split-precision step would need.
 CG_TOL = {"fp64": {"phi": 1e-9, "img": 1e-7, "first": 1e-12},
-          "fp32": {"phi": 1e-5, "img": 1e-3, "first": 1e-6},
-          "bf16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4},
-          "fp16x3": {"phi": 5e-2, "img": 5e-2, "first": 1e-4}}
+          "fp32": {"phi": 1e-5, "img": 1e-5, "first": 1e-6},
+          "bf16x3": {"phi": 1e-3, "img": 1e-3, "first": 1e-4},
+          "fp16x3": {"phi": 1e-3, "img": 1e-3, "first": 1e-4}}
 
 
 def rel(a, b) -> float:

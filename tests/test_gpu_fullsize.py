@@ -2,7 +2,9 @@
 benchmark uses.
 
 256^2 x 99,840 visibilities: Phi, chi^2, V^m, R and grad Phi compared element
-by element with the FP64 oracle over every visibility and pixel.
+by element with the FP64 oracle over every visibility and pixel, at the
+images P1, P2 and P3; the FP32 autograd gradient against central differences
+of the oracle's Phi at 64 seeded pixels.
 512^2 x 999,600, 64 x 256^2 (uneven channels) and 1024^2 x 5,000,250: the
 model visibilities at seeded samples of visibilities and the adjoint at
 seeded samples of pixels (each computed one by one by the oracle), plus
@@ -35,124 +37,204 @@ def _ds(c):
     return synth.make_config(c)
 
 
+IMAGES = ("P1", "P2", "P3")
+
+
+def _img(ds, which, prec):
+    """Evaluation image P1 / P2 / P3 rounded to FP32 (the FP32 and split paths
+    take FP32 images; the FP64 path takes the same values in FP64, so that
+    one oracle evaluation serves every precision)."""
+    return synth.eval_images(ds, which).astype(np.float32).astype(np.float64)
+
+
 @functools.lru_cache(maxsize=None)
-def _oracle_c2_P3():
+def _oracle_c2(which):
     ds = _ds(2)
     prob = Problem.from_dataset(ds)
-    img = synth.eval_images(ds, "P3")[0].astype(np.float32).astype(np.float64)
+    img = _img(ds, which, "fp32")[0]
+    flush(f"  oracle: c2 full evaluation at {which}")
     return img, prob.oracle_phi_grad(0, img)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def _kappa(V, R, w):
+    """kappa = ||V||_w / ||R||_w: forward errors enter R, chi^2 and grad chi^2
+    amplified by about this factor where the model fits the data."""
+    return float(np.sqrt(np.sum(w * np.abs(V) ** 2) / np.sum(w * np.abs(R) ** 2)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_c2_full_phi_grad(prec):
-    """Every visibility and pixel of the 256^2 x 99,840 workload at P3."""
+    """Every visibility and pixel of the 256^2 x 99,840 workload at P1 = M,
+    P2 = max(sky, M) and P3 = M + U[0, 1).  The bars hold at P1 and P3; at P2
+    (near a fit, R ~ noise) V^m keeps the bar and R, chi^2 and grad Phi are
+    held to the bar times 4 kappa, kappa = ||V||_w / ||R||_w."""
     _cuda()
-    flush(f"c2 full parity {prec}")
     ds = _ds(2)
-    img, ref = _oracle_c2_P3()
     prob = Problem.from_dataset(ds)
     ctx = prob.context(prec)
-    I = torch.tensor(img[None], dtype=torch.float32, device="cuda")
-    scal, grad = ctx.phi_and_grad(I)
-    scal = scal.cpu().numpy()
-    e = dict(phi=abs(scal[0, 0] - ref["phi"]) / abs(ref["phi"]),
-             chi2=abs(scal[0, 1] - ref["chi2"]) / abs(ref["chi2"]),
-             S=abs(scal[0, 2] - ref["S"]) / abs(ref["S"]),
-             R=rel(ctx.residual().cpu().numpy(), ref["R"]),
-             grad=rel(grad.cpu().numpy()[0], ref["grad"]))
-    flush("  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
-    for k, v in e.items():
-        assert v < TOL[prec], (k, v)
+    w = prob.chans[0]["w"].astype(np.float64)
+    for which in IMAGES:
+        img, ref = _oracle_c2(which)
+        flush(f"c2 full parity {prec} at {which}")
+        I = torch.tensor(img[None], dtype=ctx.dtype, device="cuda")
+        V = ctx.forward(I).cpu().numpy()
+        scal, grad = ctx.phi_and_grad(I)
+        scal = scal.cpu().numpy()
+        e = dict(V=rel(V, ref["V"]),
+                 phi=abs(scal[0, 0] - ref["phi"]) / abs(ref["phi"]),
+                 chi2=abs(scal[0, 1] - ref["chi2"]) / abs(ref["chi2"]),
+                 S=abs(scal[0, 2] - ref["S"]) / abs(ref["S"]),
+                 R=rel(ctx.residual().cpu().numpy(), ref["R"]),
+                 grad=rel(grad.cpu().numpy()[0], ref["grad"]))
+        kappa = _kappa(ref["V"], ref["R"], w)
+        flush(f"  kappa {kappa:.1f}  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+        for k, v in e.items():
+            bar = TOL[prec] if which != "P2" or k in ("V", "S") else 4.0 * max(kappa, 1.0) * TOL[prec]
+            assert v < bar, (which, k, v, bar)
 
 
-def _sampled(prec, c, n_vis=96, n_pix=96, channels=None):
+def test_c2_autograd_fp32_vs_central_differences():
+    """The 256^2 x 99,840 workload in FP32 through PhiFunction: its backward
+    (grad Phi from the HIP adjoint) at 64 seeded pixels against central
+    differences of the FP64 oracle's Phi with steps h_p = 1e-3 I_p, and
+    against the oracle's analytic gradient, at P3."""
     _cuda()
+    from paper_1703_02920_amd.uvmem import PhiFunction
+    flush("c2 FP32 autograd vs central differences of the oracle Phi, 64 pixels")
+    ds = _ds(2)
+    prob = Problem.from_dataset(ds)
+    ch = prob.chans[0]
+    img, ref = _oracle_c2("P3")
+    rng = np.random.default_rng(2024)
+    pix = np.sort(rng.choice(ds.n * ds.n, size=64, replace=False))
+    h = 1e-3 * img.ravel()[pix]
+    vo, w = ch["vis"].astype(np.complex128), ch["w"].astype(np.float64)
+    args = (ds.n, ds.cell, ch["u"], ch["v"], prob.beam(0), img, ref["V"], vo, w, ds.prior_m, ds.lam, pix)
+    fd = (oracle.phi_at_pixel_steps(*args, h) - oracle.phi_at_pixel_steps(*args, -h)) / (2 * h)
+    g_or = ref["grad"].ravel()[pix]
+    e_fd_or = rel(fd, g_or)
+    ctx = prob.context("fp32")
+    I = torch.tensor(img[None], dtype=torch.float32, device="cuda", requires_grad=True)
+    phi = PhiFunction.apply(I, ctx)
+    phi.backward()
+    g = I.grad.detach().cpu().numpy().ravel()[pix].astype(np.float64)
+    e_phi = abs(float(phi) - ref["phi"]) / abs(ref["phi"])
+    e_fd, e_or = rel(g, fd), rel(g, g_or)
+    flush(f"  Phi rel err {e_phi:.2e}; grad vs FD {e_fd:.2e}, vs oracle gradient {e_or:.2e} "
+          f"(FD vs oracle gradient {e_fd_or:.2e})")
+    assert e_fd_or < 1e-7
+    assert e_phi < TOL["fp32"] and e_fd < TOL["fp32"] and e_or < TOL["fp32"]
+
+
+def _chan_samples(prob, rng, n_vis, channels):
+    out = {}
+    for ch in channels:
+        nv = len(prob.chans[ch]["u"])
+        if nv:
+            out[ch] = np.sort(rng.choice(nv, size=min(n_vis, nv), replace=False))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_sampled(c, n_vis, n_pix, channels):
+    """Oracle values at seeded samples of a full-size workload, computed one
+    by one: V^m at sampled visibilities for P1, P2, P3; the adjoint of
+    c = w V^o at sampled pixels; the point-source property's gradient."""
     ds = _ds(c)
     prob = Problem.from_dataset(ds)
-    ctx = prob.context(prec)
     rng = np.random.default_rng(1000 + c)
-    img = synth.eval_images(ds, "P3").astype(np.float32)
-    I = torch.tensor(img, dtype=torch.float32, device="cuda")
-    V = ctx.forward(I).cpu().numpy()
-    offs = prob.offsets()
-    chans = range(prob.n_chan) if channels is None else channels
-    worst = 0.0
-    for ch in chans:
-        nv = len(prob.chans[ch]["u"])
-        if nv == 0:
-            continue
-        idx = np.sort(rng.choice(nv, size=min(n_vis, nv), replace=False))
-        A = prob.beam(ch)
-        ref = oracle.forward_sel(ds.n, ds.cell, idx, prob.chans[ch]["u"], prob.chans[ch]["v"], A,
-                                 img[ch].astype(np.float64))
-        got = V[offs[ch] + idx]
-        worst = max(worst, rel(got, ref))
-    flush(f"  forward, sampled visibilities: worst channel rel err {worst:.2e}")
-    assert worst < TOL[prec]
-    # adjoint of a fixed coefficient vector at sampled pixels
-    coef = np.concatenate([prob.chans[ch]["w"].astype(np.float64) * prob.chans[ch]["vis"].astype(np.complex128)
-                           for ch in range(prob.n_chan)])
-    G = ctx.adjoint(torch.tensor(coef, dtype=torch.complex128, device="cuda")).cpu().numpy()
-    worst = 0.0
-    for ch in chans:
-        pix = np.sort(rng.choice(ds.n * ds.n, size=n_pix, replace=False))
-        ref = prob.oracle_adjoint(ch, coef[offs[ch]:offs[ch + 1]], pix=pix)
-        worst = max(worst, rel(G[ch].ravel()[pix], ref))
-    flush(f"  adjoint, sampled pixels: worst channel rel err {worst:.2e}")
-    assert worst < TOL[prec]
-    return ds, prob, ctx
-
-
-def _point_source_property(ds, prob, ctx, prec):
-    """Point of flux F at the phase centre: V_k = F exactly (A = 1 there), so
-    R = F - V^o, chi^2 = 1/2 sum w |F - V^o|^2 over all visibilities, and
-    grad chi^2 = A o Re F^H(w R) at sampled pixels."""
+    vis_idx = _chan_samples(prob, rng, n_vis, channels)
+    fwd = {}
+    for which in IMAGES:
+        img = _img(ds, which, "fp32")
+        for ch, idx in vis_idx.items():
+            flush(f"  oracle: c{c} channel {ch} forward at {len(idx)} visibilities, {which}")
+            fwd[which, ch] = oracle.forward_sel(ds.n, ds.cell, idx, prob.chans[ch]["u"], prob.chans[ch]["v"],
+                                                prob.beam(ch), img[ch])
+    coef = [prob.chans[ch]["w"].astype(np.float64) * prob.chans[ch]["vis"].astype(np.complex128)
+            for ch in range(prob.n_chan)]
+    pix = {ch: np.sort(rng.choice(ds.n * ds.n, size=n_pix, replace=False)) for ch in channels}
+    adj = {}
+    for ch in channels:
+        flush(f"  oracle: c{c} channel {ch} adjoint at {n_pix} pixels")
+        adj[ch] = prob.oracle_adjoint(ch, coef[ch], pix=pix[ch])
+    # point of flux F at the phase centre: V_k = F exactly (A = 1 there)
     F = 0.75
-    img = np.full((prob.n_chan, ds.n, ds.n), 1e-30, dtype=np.float32)
-    img[:, ds.n // 2, ds.n // 2] = F
-    I = torch.tensor(img, dtype=torch.float32, device="cuda")
-    scal, grad = ctx.phi_and_grad(I)
-    scal = scal.cpu().numpy()
-    grad = grad.cpu().numpy()
-    offs = prob.offsets()
-    rng = np.random.default_rng(7)
-    worst_x2 = worst_g = 0.0
-    for ch in range(prob.n_chan):
+    pt = {}
+    for ch in channels:
         vo = prob.chans[ch]["vis"].astype(np.complex128)
         w = prob.chans[ch]["w"].astype(np.float64)
         if len(vo) == 0:
             continue
+        x2, R = oracle.chi2(np.full(len(vo), F + 0j), vo, w)
+        flush(f"  oracle: c{c} channel {ch} point-source gradient at {n_pix} pixels")
+        pt[ch] = (x2, prob.oracle_adjoint(ch, w * R, pix=pix[ch]))
+    return vis_idx, fwd, np.concatenate(coef) if coef else None, pix, adj, F, pt
+
+
+def _sampled(prec, c, n_vis, n_pix, channels=None):
+    """Sampled parity of the forward model at P1, P2, P3 (bar at P1 and P3
+    and on V^m at P2; kappa of the sample reported), the adjoint at sampled
+    pixels, and the point-source property (chi^2 in closed form over every
+    visibility, grad chi^2 at the sampled pixels)."""
+    _cuda()
+    ds = _ds(c)
+    prob = Problem.from_dataset(ds)
+    chans = tuple(range(prob.n_chan) if channels is None else channels)
+    vis_idx, fwd, coef, pix, adj, F, pt = _oracle_sampled(c, n_vis, n_pix, chans)
+    ctx = prob.context(prec)
+    offs = prob.offsets()
+    for which in IMAGES:
+        I = torch.tensor(_img(ds, which, prec), dtype=ctx.dtype, device="cuda")
+        V = ctx.forward(I).cpu().numpy()
+        got = np.concatenate([V[offs[ch] + idx] for ch, idx in vis_idx.items()])
+        ref = np.concatenate([fwd[which, ch] for ch in vis_idx])
+        worst = max(rel(V[offs[ch] + idx], fwd[which, ch]) for ch, idx in vis_idx.items())
+        vo = np.concatenate([prob.chans[ch]["vis"][idx].astype(np.complex128) for ch, idx in vis_idx.items()])
+        w = np.concatenate([prob.chans[ch]["w"][idx].astype(np.float64) for ch, idx in vis_idx.items()])
+        kappa = _kappa(ref, ref - vo, w)
+        e_R = rel(got - vo, ref - vo)
+        flush(f"  forward at {which}: pooled rel err {rel(got, ref):.2e}, worst channel {worst:.2e}; "
+              f"R {e_R:.2e}, kappa of the sample {kappa:.1f}")
+        assert rel(got, ref) < TOL[prec] and worst < TOL[prec]
+    G = ctx.adjoint(torch.tensor(coef, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    worst = max(rel(G[ch].ravel()[pix[ch]], adj[ch]) for ch in chans)
+    flush(f"  adjoint at {n_pix} sampled pixels: worst channel rel err {worst:.2e}")
+    assert worst < TOL[prec]
+    img = np.full((prob.n_chan, ds.n, ds.n), 1e-30)
+    img[:, ds.n // 2, ds.n // 2] = F
+    scal, grad = ctx.phi_and_grad(torch.tensor(img, dtype=ctx.dtype, device="cuda"))
+    scal, grad = scal.cpu().numpy(), grad.cpu().numpy()
+    worst_x2 = worst_g = 0.0
+    for ch, (x2, gref) in pt.items():
         # model visibilities of the image: F exactly plus the 1e-30 floor's
         # contribution (bounded by N^2 1e-30, far below any tolerance)
-        x2, R = oracle.chi2(np.full(len(vo), F + 0j), vo, w)
         worst_x2 = max(worst_x2, abs(scal[ch, 1] - x2) / x2)
-        pix = np.sort(rng.choice(ds.n * ds.n, size=48, replace=False))
-        gref = prob.oracle_adjoint(ch, w * R, pix=pix)
-        lam_part = ds.lam * (np.log(img[ch].ravel()[pix].astype(np.float64) / ds.prior_m) + 1.0)
-        worst_g = max(worst_g, rel(grad[ch].ravel()[pix] - lam_part, gref))
+        x = img[ch].ravel()[pix[ch]]
+        if ctx.dtype == torch.float32:
+            x = x.astype(np.float32).astype(np.float64)
+        lam_part = ds.lam * (np.log(x / ds.prior_m) + 1.0)
+        worst_g = max(worst_g, rel(grad[ch].ravel()[pix[ch]] - lam_part, gref))
     flush(f"  point-source property: chi2 rel err {worst_x2:.2e}, grad chi2 rel err {worst_g:.2e}")
     assert worst_x2 < TOL[prec] and worst_g < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_c3_sampled_and_point_source(prec):
     flush(f"c3 512^2 x 999,600 sampled parity {prec}")
-    ds, prob, ctx = _sampled(prec, 3)
-    _point_source_property(ds, prob, ctx, prec)
+    _sampled(prec, 3, n_vis=256, n_pix=256)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_c4_batched_sampled_and_point_source(prec):
     flush(f"c4 64 x 256^2 batched sampled parity {prec}")
-    ds, prob, ctx = _sampled(prec, 4, n_vis=48, n_pix=32, channels=[0, 17, 40, 63])
-    _point_source_property(ds, prob, ctx, prec)
+    _sampled(prec, 4, n_vis=128, n_pix=128, channels=(0, 9, 17, 26, 40, 48, 55, 63))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_c5_sampled_and_point_source(prec):
     flush(f"c5 1024^2 x 5,000,250 sampled parity {prec}")
-    ds, prob, ctx = _sampled(prec, 5, n_vis=48, n_pix=48)
-    _point_source_property(ds, prob, ctx, prec)
+    _sampled(prec, 5, n_vis=512, n_pix=512)
 
 
 def test_all_channels_empty():

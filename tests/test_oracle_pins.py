@@ -128,6 +128,41 @@ def test_forward_sel_matches_full():
     assert np.array_equal(oracle.forward_sel(N, CELL, idx, u, v, A, x), V[idx])
 
 
+def test_forward_pix_equals_dense_image_with_those_pixels():
+    """The sparse-image forward equals the dense direct sum of an image that
+    is zero except at the listed pixels (brute force), and a single pixel at
+    the phase centre gives A-weighted constant visibilities."""
+    u, v = _uv(250, 17)
+    A = oracle.beam(N, CELL, 11 * CELL)
+    rng = np.random.default_rng(17)
+    pix = np.array([0, 37, 500, N * N - 1, N * (N // 2) + N // 2 + 3])
+    vals = rng.uniform(-1, 1, len(pix))
+    img = np.zeros((N, N))
+    img.flat[pix] = vals
+    assert rel(oracle.forward_pix(N, CELL, u, v, A, pix, vals), oracle.forward(N, CELL, u, v, A, img)) < 1e-13
+    c = N * (N // 2) + N // 2
+    assert np.array_equal(oracle.forward_pix(N, CELL, u, v, A, [c], [0.75]), np.full(len(u), 0.75 + 0j))
+
+
+def test_phi_at_pixel_steps_equals_phi_of_changed_images():
+    """Phi at one-pixel changes I + h e_p evaluated through linearity of the
+    model equals the full evaluation of Phi at the changed image."""
+    n, cell = 16, 3.0e-6
+    u, v, vis, w = synth.random_problem(n, 120, 19, cell=cell)
+    A = oracle.beam(n, cell, 7 * cell)
+    img = synth.random_image(n, 19, lo=0.05, hi=1.0)[0]
+    M, lam = 1e-2, 0.2
+    V_I = oracle.forward(n, cell, u, v, A, img)
+    pix = np.array([3, 100, 255])
+    h = np.array([1e-3, -2e-3, 5e-4]) * img.flat[pix]
+    got = oracle.phi_at_pixel_steps(n, cell, u, v, A, img, V_I, vis, w, M, lam, pix, h)
+    for q, p in enumerate(pix):
+        x = img.copy()
+        x.flat[p] += h[q]
+        ref = oracle.phi_grad(n, cell, u, v, A, x, vis, w, M, lam)["phi"]
+        assert abs(got[q] - ref) < 1e-13 * abs(ref)
+
+
 # ---------------------------------------------------------------- adjoint
 
 def test_adjoint_dot_test():
