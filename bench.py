@@ -29,7 +29,7 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "fp16x3": 2500.0}   # TFL
 KERNEL_SRC = "paper_1703_02920_amd/csrc/k_dft.hip"
 # DFT kernel functions per precision: (forward, adjoint)
 KERNELS = {"fp32": ("k_forward_p", "k_adjoint_w"), "fp64": ("k_forward_p", "k_adjoint"),
-           "bf16x3": ("k_forward_h16p", "k_adjoint_h16w"), "fp16x3": ("k_forward_h16p", "k_adjoint_h16w")}
+           "bf16x3": ("k_forward_h16m", "k_adjoint_h16s"), "fp16x3": ("k_forward_h16m", "k_adjoint_h16s")}
 
 
 def kernel_hash(kernel: str) -> str:
@@ -159,6 +159,35 @@ def cpu_baseline(ds, target_s: float = 12.0, single_s: float = 4.0):
             "paper_context": PAPER_CONTEXT}
 
 
+MFMA_KINDS = {"fp32": (0, "v_mfma_f32_16x16x4_f32"), "fp64": (1, "v_mfma_f64_16x16x4_f64"),
+              "bf16": (2, "v_mfma_f32_16x16x32_bf16"), "fp16": (3, "v_mfma_f32_16x16x32_f16"),
+              "bf16_32x32": (4, "v_mfma_f32_32x32x16_bf16")}
+SPEC_PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16_32x32": 2500.0}
+
+
+def mfma_peak(kinds=None, target_ms=20.0):
+    """Measured matrix-core rate per instruction form (libmfma_peak.so built
+    from mfma_peak.hip): 1,024 workgroups of four waves issuing independent
+    matrix instructions; best of 5 launches of ~target_ms."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "libmfma_peak.so"))
+    lib.mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    blocks = 1024
+    flops = {0: 2048.0 * 8, 1: 2048.0 * 8, 2: 16384.0 * 8, 3: 16384.0 * 8, 4: 32768.0 * 4}
+    for name in (kinds or MFMA_KINDS):
+        kind, inst = MFMA_KINDS[name]
+        iters = int(target_ms * 1e-3 * SPEC_PEAK[name] * 1e12 / (4 * blocks * flops[kind]))
+        tf, ms = ctypes.c_double(), ctypes.c_double()
+        code = lib.mfma_peak(kind, blocks, max(iters, 1), 5, ctypes.byref(tf), ctypes.byref(ms))
+        if code != 0:
+            raise RuntimeError(f"mfma_peak({name}) failed: {code}")
+        out[name] = {"instruction": inst, "tflops": tf.value, "spec_tflops": SPEC_PEAK[name],
+                     "frac_of_spec": tf.value / SPEC_PEAK[name], "ms": ms.value, "iters": iters}
+    return out
+
+
 def run_steps(ctx, steps, warmup, graph):
     """cg_init, warm-up steps, then `steps` timed CG iterations; returns
     (ms for the timed region, wall seconds, per-kernel average ms)."""
@@ -217,7 +246,9 @@ def eval_error(ds, ctx, ref):
         torch.cuda.synchronize()
 
         def rel(a, b):
-            return float(torch.linalg.vector_norm((a.double() - b.double())) / torch.linalg.vector_norm(b.double()))
+            dt = torch.complex128 if a.is_complex() else torch.float64
+            a, b = a.to(dt), b.to(dt)
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
         out[which] = {"V": rel(V, Vr),
                       "chi2": abs(float(s[:, 1].sum()) - float(sr[:, 1].sum())) / abs(float(sr[:, 1].sum())),
@@ -374,26 +405,72 @@ def eval_sweep(configs, precs, reps=20, warmup=3, mode=None):
                 continue
             ctx = Context.from_dataset(ds, prec, mode=md)
             img = torch.tensor(img_np, dtype=ctx.dtype, device=ctx.device)
-            scal, grad = ctx.scalars(), torch.empty_like(img)
-            for _ in range(warmup):
-                ctx.phi_and_grad(img, grad, scal)
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(ctx.stream)
-                ctx.phi_and_grad(img, grad, scal)
-                e1.record(ctx.stream)
-                e1.synchronize()
-                ts.append(e0.elapsed_time(e1))
-            ctx.check()
-            ms = float(np.median(ts))
+            ms, fwd_ms, adj_ms = _median_eval_ms(ctx, img, reps=reps, warmup=warmup)
+            ctx.close()
             rows.append({"config": f"c{c}", "mode": md, "precision": prec, "ms_per_eval": ms,
+                         "ms_forward": fwd_ms, "ms_adjoint": adj_ms,
+                         "forward_tflops": 4.0 * ds.pairs / (fwd_ms / 1e3) / 1e12,
+                         "adjoint_tflops": 4.0 * ds.pairs / (adj_ms / 1e3) / 1e12,
                          "vis_pixel_evals_per_s": ds.pairs / (ms / 1e3),
                          "algorithmic_tflops": 8.0 * ds.pairs / (ms / 1e3) / 1e12,
                          "frac_of_peak": 8.0 * ds.pairs / (ms / 1e3) / 1e12 / PEAK[prec]})
             print(json.dumps(rows[-1]), flush=True)
-            ctx.close()
+    return rows
+
+
+SCHED_CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16)
+
+
+def schedule_sweep(configs, precs, reps=10):
+    """The work-list sizes the library's makespan model picks at finalize
+    against the measured best of the same candidate sizes: for each
+    candidate m (the model's candidates: 256 m forward workgroups, 256 m
+    adjoint split-K workgroups -- 512 m for the 128-tile split adjoint) the
+    forward and adjoint launch times of a Phi + grad evaluation at P3, then
+    the model's own choice.  Reported per direction: the model's time over
+    the best candidate's."""
+    import torch
+    from paper_1703_02920_amd import synth
+    from paper_1703_02920_amd.uvmem import Context
+    rows = []
+    for c in configs:
+        ds = synth.make_config(c)
+        img_np = synth.eval_images(ds, "P3")
+        md = "shared" if ds.shared else "cube"
+        if md == "shared":
+            img_np = img_np[:1]
+        for prec in precs:
+            def run(env):
+                old = {k: os.environ.get(k) for k in ("UVMEM_FWD_WGS", "UVMEM_ADJ_WGS")}
+                os.environ.update(env)
+                try:
+                    ctx = Context.from_dataset(ds, prec, mode=md)
+                finally:
+                    for k, v in old.items():
+                        if v is None:
+                            os.environ.pop(k, None)
+                        else:
+                            os.environ[k] = v
+                img = torch.tensor(img_np, dtype=ctx.dtype, device=ctx.device)
+                ev, fwd, adj = _median_eval_ms(ctx, img, reps=reps)
+                info = ctx.info()
+                ctx.close()
+                return {"ms_eval": ev, "ms_forward": fwd, "ms_adjoint": adj, "fwd_wgs": info["n_fwd_wgs"],
+                        "adj_wgs": info["n_adj_items"], "adj_tile": info["adj_tile"]}
+            model = run({})
+            slots = 512 if prec in ("bf16x3", "fp16x3") and model["adj_tile"] == 128 else 256
+            cands = {}
+            for m in SCHED_CANDIDATES:
+                cands[m] = run({"UVMEM_FWD_WGS": str(256 * m), "UVMEM_ADJ_WGS": str(slots * m)})
+            best_f = min(cands.values(), key=lambda r: r["ms_forward"])
+            best_a = min(cands.values(), key=lambda r: r["ms_adjoint"])
+            row = {"config": f"c{c}", "precision": prec, "model": model,
+                   "candidates": {str(m): {k: v for k, v in r.items() if k != "adj_tile"} for m, r in cands.items()},
+                   "forward_model_over_best": model["ms_forward"] / best_f["ms_forward"],
+                   "adjoint_model_over_best": model["ms_adjoint"] / best_a["ms_adjoint"],
+                   "best_forward_wgs": best_f["fwd_wgs"], "best_adjoint_wgs": best_a["adj_wgs"]}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
     return rows
 
 
@@ -462,6 +539,8 @@ def main():
                     help="skip the FP64-referenced errors and the split-precision companion runs")
     ap.add_argument("--no-cg", action="store_true",
                     help="skip the full CG trajectories (FP64 reference, FP32, bf16x3, fp16x3)")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,fp16x3",
+                    help="precisions of --eval-sweep")
     ap.add_argument("--eval-sweep", default="", metavar="CONFIGS",
                     help="only time single Phi + grad evaluations on these configurations (e.g. 1,2,3,4,5)")
     ap.add_argument("--cg-compare", type=int, default=0, metavar="CONFIG",
@@ -476,6 +555,10 @@ def main():
     ap.add_argument("--oversample", default="1,2,4", help="gridded-model oversampling factors")
     ap.add_argument("--region", type=float, default=0.0,
                     help="--cg-compare with a focus-of-attention region: centred square of this side fraction")
+    ap.add_argument("--schedule-sweep", default="", metavar="CONFIGS",
+                    help="only compare the finalize-time schedule choice with the measured best candidate")
+    ap.add_argument("--mfma-peak", action="store_true",
+                    help="only measure the matrix-core rate of each instruction form used (microbenchmark)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -485,8 +568,7 @@ def main():
 
     import torch
     if args.eval_sweep:
-        eval_sweep([int(x) for x in args.eval_sweep.split(",")], ["fp64", "fp32", "bf16x3", "fp16x3"],
-                   mode=args.mode)
+        eval_sweep([int(x) for x in args.eval_sweep.split(",")], args.precisions.split(","), mode=args.mode)
         return
     if args.grid_error:
         grid_error([int(x) for x in args.grid_error.split(",")], [int(x) for x in args.oversample.split(",")])
@@ -496,6 +578,13 @@ def main():
         return
     if args.cg_compare:
         cg_compare(args.cg_compare, ["fp32", "bf16x3", "fp16x3"], mode=args.mode, region=args.region or None)
+        return
+    if args.schedule_sweep:
+        schedule_sweep([int(x) for x in args.schedule_sweep.split(",")], ["fp32", "bf16x3"])
+        return
+    if args.mfma_peak:
+        for k, v in mfma_peak().items():
+            print(json.dumps({"form": k, **v}), flush=True)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -532,6 +621,16 @@ def main():
                 "kernel": KERNELS[args.precision][0 if dom == "forward" else 1], "direction": dom,
                 "kernel_ms": kern[dom], "flops_per_launch": flops_per_launch,
                 "other_kernel_ms": {k: v for k, v in kern.items() if k != dom}}
+    if roof is not None:
+        try:
+            pk = mfma_peak([{"fp32": "fp32", "fp64": "fp64", "bf16x3": "bf16", "fp16x3": "fp16"}[args.precision]])
+            pk = next(iter(pk.values()))
+            roof["measured_peak"] = pk["tflops"]
+            roof["frac_of_measured_peak"] = roof["achieved"] / pk["tflops"]
+            roof["measured_peak_instruction"] = pk["instruction"]
+        except (OSError, RuntimeError) as exc:
+            roof["measured_peak"] = None
+            print(f"bench: no matrix-core microbenchmark ({exc})", file=sys.stderr, flush=True)
     # errors against the FP64 path (held to the oracle at 1e-12 at this size
     # by the full-size parity tests), and the split-precision companions
     errors, mixed, cg = None, None, None

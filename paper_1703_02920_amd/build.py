@@ -36,6 +36,22 @@ def _compile(src: str) -> str:
     return obj
 
 
+# matrix-core peak microbenchmark used by bench.py (measurement only; not
+# part of the library)
+PEAK_SRC = os.path.join(os.path.dirname(HERE), "mfma_peak.hip")
+PEAK_OUT = os.path.join(os.path.dirname(HERE), "libmfma_peak.so")
+
+
+def build_peak() -> str:
+    tmp = PEAK_OUT + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *FLAGS, "-shared", "-o", tmp, PEAK_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for mfma_peak.hip:\n" + r.stdout + r.stderr)
+    os.replace(tmp, PEAK_OUT)
+    return PEAK_OUT
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
@@ -46,8 +62,9 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, OUT)
+    build_peak()
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PEAK_OUT)
     return OUT
 
 

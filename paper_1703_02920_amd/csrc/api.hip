@@ -88,7 +88,7 @@ void free_all(uvmem_ctx *c) {
     dfree(c->d_chan_img);
     dfree(c->d_R); dfree(c->d_Vd); dfree(c->d_vpart); dfree(c->d_gpart); dfree(c->d_bop);
     dfree(c->d_g); dfree(c->d_gt); dfree(c->d_dir);
-    dfree(c->d_scal); dfree(c->d_chan); dfree(c->d_ls); dfree(c->d_ppart); dfree(c->d_vispart);
+    dfree(c->d_scal); dfree(c->d_chan); dfree(c->d_ls); dfree(c->d_ctr); dfree(c->d_ppart); dfree(c->d_vispart);
     dfree(c->d_flag); dfree(c->d_hist_ptr); dfree(c->d_iter_ctr);
     dfree(c->d_gtw); dfree(c->d_gx1); dfree(c->d_ggrid); dfree(c->d_gcell); dfree(c->d_gperm);
     dfree(c->d_gfxy); dfree(c->d_gsc); dfree(c->d_gdidx); dfree(c->d_gdlist); dfree(c->d_gdsum);
@@ -879,7 +879,8 @@ int finalize_impl(uvmem_ctx *c) {
     ok(dalloc(c, (char **)&c->d_dir, IMG * npix * rs));
     ok(dalloc(c, &c->d_scal, (size_t)IMG * UVMEM_NSCAL));
     ok(dalloc(c, &c->d_chan, (size_t)IMG * CH_N));
-    ok(dalloc(c, &c->d_ls, (size_t)2 * IMG * LSS_N));
+    ok(dalloc(c, &c->d_ls, (size_t)IMG * LSS_N));
+    ok(dalloc(c, &c->d_ctr, (size_t)CTR_N * IMG));
     ok(dalloc(c, &c->d_ppart, (size_t)2 * IMG * c->n_pb * NPART));
     ok(dalloc(c, &c->d_vispart, (size_t)std::max(c->n_visit, 1) * NPART));
     ok(dalloc(c, &c->d_flag, 4));
@@ -970,8 +971,7 @@ int uvmem_phi_and_grad(uvmem_ctx *c, const void *I, void *grad, double *scal) {
     HIPCHK(c, timed_dft(c, 0, c->d_bop, nullptr, nullptr, 0));
     HIPCHK(c, launch_vis_sum(c, 1, nullptr, c->stream));
     HIPCHK(c, timed_dft(c, 1, nullptr, c->d_R, c->d_w, 1));
-    HIPCHK(c, launch_grad(c, I, grad, 1, c->stream));
-    HIPCHK(c, launch_chan_phi(c, scal, c->stream));
+    HIPCHK(c, launch_grad(c, I, grad, 1, scal, c->stream));
     return UVMEM_OK;
 }
 
@@ -991,7 +991,7 @@ int uvmem_adjoint(uvmem_ctx *c, const void *coef, void *img) {
     if ((!coef && c->ztot) || !img) return fail(c, UVMEM_EINVAL, "null coefficients or output");
     HIPCHK(c, launch_coef_max(c, (const double2 *)coef, c->stream));
     HIPCHK(c, timed_dft(c, 1, nullptr, (const double2 *)coef, nullptr, 0));
-    HIPCHK(c, launch_grad(c, nullptr, img, 0, c->stream));
+    HIPCHK(c, launch_grad(c, nullptr, img, 0, nullptr, c->stream));
     return UVMEM_OK;
 }
 
@@ -1010,13 +1010,13 @@ int uvmem_dirty_image(uvmem_ctx *c, void *dirty, void *psf) {
     if (dirty) {
         HIPCHK(c, launch_coef_max(c, c->d_vo, c->stream));
         HIPCHK(c, launch_adjoint(c, c->d_vo, c->d_w, c->stream));
-        HIPCHK(c, launch_grad(c, nullptr, dirty, 3, c->stream));
+        HIPCHK(c, launch_grad(c, nullptr, dirty, 3, nullptr, c->stream));
     }
     if (psf) {
         HIPCHK(c, launch_fill_c(c, c->d_Vd, 1.0, 0.0, c->stream));
         HIPCHK(c, launch_coef_max(c, c->d_Vd, c->stream));
         HIPCHK(c, launch_adjoint(c, c->d_Vd, c->d_w, c->stream));
-        HIPCHK(c, launch_grad(c, nullptr, psf, 3, c->stream));
+        HIPCHK(c, launch_grad(c, nullptr, psf, 3, nullptr, c->stream));
     }
     return UVMEM_OK;
 }
@@ -1197,7 +1197,7 @@ struct StateHeader {
     int32_t fwd_model, grid_lg, grad_model, pad;
     int64_t ztot;
 };
-const uint64_t STATE_MAGIC = 0x32534d454d5655ull;  // "UVMEMS2"
+const uint64_t STATE_MAGIC = 0x33534d454d5655ull;  // "UVMEMS3"
 }  // namespace
 
 int uvmem_cg_get_state(uvmem_ctx *c, void *blob, size_t *bytes) {

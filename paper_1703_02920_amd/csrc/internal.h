@@ -90,13 +90,30 @@ enum {
     LSS_N = 24
 };
 
-// Per-channel flags / CG bookkeeping kept on the device (double).
+// Per-image flags / CG bookkeeping kept on the device (double).
 enum {
     CH_GTD = 0,      // gt . d after projection
     CH_RESTART,      // 1 if the direction was reset to -gt this step
     CH_GG_OLD,       // |gt_old|^2
     CH_STOP,         // 1 once the channel has stopped (zero gradient or zero step)
-    CH_N = 4
+    CH_E1,           // sum d (ln(I/M) + 1) of the step's direction
+    CH_E2,           // sum d^2 / I
+    CH_AMAX,         // alpha_max = min over d < 0 of (I - M)/(-d) (INFINITY if none)
+    CH_PAD,
+    CH_N = 8
+};
+
+// Arrival counters of the per-image reductions finished by the last
+// workgroup to arrive ([CTR_N][nimg] unsigned, zero between launches).
+enum {
+    CTR_DIR = 0,     // k_cg_dir: gt . d
+    CTR_DIR2,        // k_cg_dir2: alpha_max and the entropy parts of phi', phi''
+    CTR_VIS,         // k_vis (direction): a, b; line-search start
+    CTR_LS,          // k_ls_step: phi', phi'' at the trial steps
+    CTR_UPD,         // k_cg_update: S and chi^2 of the new image
+    CTR_GRAD,        // k_grad: the Polak-Ribiere sums / Phi of an evaluation
+    CTR_INIT,        // k_cg_init: |gt|^2
+    CTR_N
 };
 
 }  // namespace uvm
@@ -173,7 +190,8 @@ struct uvmem_ctx {
     void *d_g = nullptr, *d_gt = nullptr, *d_dir = nullptr;  // real [nimg][n][n]
     double *d_scal = nullptr;                   // [nimg][NSCAL]
     double *d_chan = nullptr;                   // [nimg][CH_N]
-    double *d_ls = nullptr;                     // [2][nimg][LSS_N] (ping-pong)
+    double *d_ls = nullptr;                     // [nimg][LSS_N] line-search state
+    unsigned *d_ctr = nullptr;                  // [CTR_N][nimg] arrival counters
     double *d_ppart = nullptr;                  // [2][nimg][n_pb][NPART] (ping-pong)
     double *d_vispart = nullptr;                // [n_visit][NPART]
     int *d_flag = nullptr;                      // [4]: domain flag, ...
@@ -238,6 +256,17 @@ hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *
 hipError_t launch_grid_forward(const uvmem_ctx *c, const void *bop, hipStream_t st);
 hipError_t launch_grid_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st);
 
+// The FP32 forward on explicit buffers (the allocation-free entry point):
+// image blocks ib_rows x jb_cols (128 x 256, 128 x 128 or 64 x 64), work
+// items in device memory.
+hipError_t launch_forward_f32_raw(int ib_rows, int jb_cols, const FwdPItem *items, int nitems, const double *a,
+                                  const double *b, const float *bop, double2 *vpart, int n, int np,
+                                  long long ztot, hipStream_t st);
+// out[k] = sum over the n_parts forward partials of visibility k, for the
+// visibility items in device memory.
+hipError_t launch_vis_sum_raw(const VisItem *items, int n_items, const double2 *vpart, int n_parts, long long ztot,
+                              double2 *out, hipStream_t st);
+
 // Auxiliary kernels (k_aux.hip).
 hipError_t launch_fill(const uvmem_ctx *c, void *img, double value, hipStream_t st);
 // Fill a sum-Z complex visibility buffer with (re, im).
@@ -247,8 +276,9 @@ hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_
 // Per-item max |coef| (slot 2 of the visibility partials) for the scaled
 // fp16 adjoint; no-op for the other precisions.
 hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t st);
-hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st);
-hipError_t launch_chan_phi(const uvmem_ctx *c, double *user_scal, hipStream_t st);
+// mode 1 (grad Phi of an evaluation) also writes Phi, chi^2 and S of every
+// image to the context's scalars and to user_scal (may be null).
+hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, double *user_scal, hipStream_t st);
 hipError_t launch_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st);
 hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user_scal, hipStream_t st);
 // The CG step in three phases around the DFT launches (0: before the forward

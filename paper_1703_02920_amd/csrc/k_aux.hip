@@ -68,6 +68,29 @@ __device__ __forceinline__ double min_partials(const double *base, int n_items, 
     return block_min(m);
 }
 
+// Arrival at the end of a partial-sum pass, once thread 0 has stored this
+// workgroup's partial record: returns true (in every thread) in exactly one
+// workgroup per image and launch, the last to arrive at `ctr`, which may then
+// read every record of the image and finish the image's reduction in a fixed
+// order.  The counter only elects that workgroup (the sums never depend on
+// arrival order) and is left at zero for the next launch; no workgroup waits
+// for another.
+__device__ __forceinline__ bool arrive_last(unsigned *ctr, unsigned expected) {
+    __shared__ unsigned s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // this workgroup's record before its arrival
+        const unsigned t = atomicAdd(ctr, 1u);
+        const bool last = t + 1 == expected;
+        if (last) atomicExch(ctr, 0u);
+        s_last = last ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last == 0) return false;
+    __threadfence();       // every other record after the last arrival
+    return true;
+}
+
 // ---------------------------------------------------------------- fill
 template <typename R>
 __global__ void k_fill(R *__restrict__ x, R value, long long count) {
@@ -189,16 +212,34 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
     }
 }
 
+__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop);
+
+// mode 2 (the CG direction's visibilities): the last visibility workgroup of
+// an image sums a, b and starts the image's line search from them and from
+// the direction pass's totals in `chan`.
 __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
                                               const double2 *__restrict__ vpart, int n_parts, long long ztot,
                                               const double2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
                                               double *__restrict__ vispart, const int *__restrict__ chan_img,
-                                              int mode, int with_max) {
+                                              int mode, int with_max, unsigned *__restrict__ ctr,
+                                              const int *__restrict__ ivis_base, const double *__restrict__ chan,
+                                              double *__restrict__ ls, double lam) {
     const VisItem it = items[blockIdx.x];
-    const double alpha = mode == 3 ? scal[(size_t)chan_img[it.chan] * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
+    const int img = chan_img ? chan_img[it.chan] : 0;
+    const double alpha = mode == 3 ? scal[(size_t)img * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
     vis_item(it, blockIdx.x, vpart, n_parts, ztot, vo, w, R, Vd, out, vispart, mode, with_max, alpha);
+    if (mode != 2) return;
+    const int v0 = ivis_base[img], v1 = ivis_base[img + 1];
+    if (!arrive_last(ctr + img, (unsigned)(v1 - v0))) return;
+    double ab[2];
+    sum_partials<2>(vispart + (size_t)v0 * NPART, v1 - v0, 0, ab);
+    if (threadIdx.x == 0) {
+        const double *ch = chan + (size_t)img * CH_N;
+        ls_init(ls + (size_t)img * LSS_N, ab[0], ab[1], lam * ch[CH_E1], lam * ch[CH_E2], ch[CH_AMAX],
+                ch[CH_STOP] != 0.0);
+    }
 }
 
 // ---------------------------------------------------------------- gradient
@@ -210,6 +251,21 @@ __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
 // mode 3: out = scale_img x G without the attenuation (dirty image / PSF).
 // With a focus-of-attention mask, pixels outside it are not free: modes 1
 // and 2 write 0 there (gradient and projected gradient).
+// Image totals finished by the last workgroup of an image (modes 1 and 2):
+//   mode 1: Phi, chi^2 (from the visibility pass's partials) and S (from the
+//           prologue's partials) into the scalars and, if given, `user`;
+//   mode 2: the Polak-Ribiere beta (clipped at 0), |gt|^2 and the iteration
+//           count; all scalars copied to `user`.
+struct GradTail {
+    unsigned *ctr;
+    const double *vispart;
+    const int *ivis_base;
+    const double *pp_S;
+    double *scal;
+    double *chan;
+    double *user;
+};
+
 template <typename R, int RP, typename PT>
 __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, const int *__restrict__ slot_base,
                                                const int *__restrict__ ichan_base,
@@ -217,7 +273,8 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
                                                R *__restrict__ out, R *__restrict__ gt,
                                                double *__restrict__ ppart, const double *__restrict__ img_scale,
                                                const unsigned char *__restrict__ mask, int n, int np, int n_pb,
-                                               int pb_len, double M, double Mb, double lam, int mode) {
+                                               int pb_len, double M, double Mb, double lam, int mode,
+                                               GradTail tail) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
@@ -308,37 +365,53 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
             ppart[((size_t)c * n_pb + pb) * NPART + 1] = acc[1];
         }
     }
-}
-
-// ---------------------------------------------------------------- per-channel scalars
-// Phi, chi^2, S of a plain evaluation.
-__global__ __launch_bounds__(NTHR) void k_chan_phi(const double *__restrict__ vispart, const int *__restrict__ vis_base,
-                                                   const double *__restrict__ ppart, int n_pb, double lam,
-                                                   double *__restrict__ scal, double *__restrict__ user) {
-    const int c = blockIdx.x;
-    double x2[1], S[1];
-    sum_partials<1>(vispart + (size_t)vis_base[c] * NPART, vis_base[c + 1] - vis_base[c], 0, x2);
-    sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, S);
+    if ((mode != 1 && mode != 2) || !arrive_last(tail.ctr + c, (unsigned)n_pb)) return;
+    double *sc = tail.scal + (size_t)c * UVMEM_NSCAL;
+    if (mode == 1) {
+        double x2[1], S[1];
+        const int v0 = tail.ivis_base[c], v1 = tail.ivis_base[c + 1];
+        sum_partials<1>(tail.vispart + (size_t)v0 * NPART, v1 - v0, 0, x2);
+        sum_partials<1>(tail.pp_S + (size_t)c * n_pb * NPART, n_pb, 0, S);
+        if (threadIdx.x == 0) {
+            const double chi2 = 0.5 * x2[0];
+            sc[UVMEM_S_PHI] = chi2 + lam * S[0];
+            sc[UVMEM_S_CHI2] = chi2;
+            sc[UVMEM_S_S] = S[0];
+            if (tail.user) {
+                double *u = tail.user + (size_t)c * UVMEM_NSCAL;
+                u[UVMEM_S_PHI] = sc[UVMEM_S_PHI];
+                u[UVMEM_S_CHI2] = chi2;
+                u[UVMEM_S_S] = S[0];
+            }
+        }
+        return;
+    }
+    double gg[2];
+    sum_partials<2>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gg);
     if (threadIdx.x == 0) {
-        const double chi2 = 0.5 * x2[0];
-        double *sc = scal + (size_t)c * UVMEM_NSCAL;
-        sc[UVMEM_S_PHI] = chi2 + lam * S[0];
-        sc[UVMEM_S_CHI2] = chi2;
-        sc[UVMEM_S_S] = S[0];
-        if (user) {
-            user[(size_t)c * UVMEM_NSCAL + UVMEM_S_PHI] = sc[UVMEM_S_PHI];
-            user[(size_t)c * UVMEM_NSCAL + UVMEM_S_CHI2] = chi2;
-            user[(size_t)c * UVMEM_NSCAL + UVMEM_S_S] = S[0];
+        double *ch = tail.chan + (size_t)c * CH_N;
+        const double gold = ch[CH_GG_OLD];
+        const bool stop = ch[CH_STOP] != 0.0;
+        double beta = 0.0;
+        if (!stop && gold > 0.0) beta = fmax(0.0, (gg[0] - gg[1]) / gold);
+        sc[UVMEM_S_BETA] = beta;
+        sc[UVMEM_S_GNORM2] = gg[0];
+        if (sc[UVMEM_S_ALPHA] != 0.0) sc[UVMEM_S_ITER] += 1.0;
+        if (tail.user) {
+            for (int x = 0; x < UVMEM_NSCAL; ++x) tail.user[(size_t)c * UVMEM_NSCAL + x] = sc[x];
         }
     }
 }
 
 // ---------------------------------------------------------------- CG
-// Initial projected gradient gt = g off the active set, partial |gt|^2.
+// Initial projected gradient gt = g off the active set, partial |gt|^2; the
+// last workgroup of an image starts its CG bookkeeping.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const R *__restrict__ g,
                                                   R *__restrict__ gt, R *__restrict__ dir,
-                                                  double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb) {
+                                                  double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb,
+                                                  unsigned *__restrict__ ctr, double *__restrict__ scal,
+                                                  double *__restrict__ chan) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     double acc[1] = {0.0};
@@ -355,11 +428,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const
     }
     block_sum<1>(acc);
     if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
-}
-
-__global__ __launch_bounds__(NTHR) void k_chan_cg_init(const double *__restrict__ ppart, int n_pb,
-                                                       double *__restrict__ scal, double *__restrict__ chan) {
-    const int c = blockIdx.x;
+    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double gg[1];
     sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gg);
     if (threadIdx.x == 0) {
@@ -370,8 +439,7 @@ __global__ __launch_bounds__(NTHR) void k_chan_cg_init(const double *__restrict_
         sc[UVMEM_S_ALPHA_MAX] = 0.0;
         sc[UVMEM_S_ITER] = 0.0;
         double *ch = chan + (size_t)c * CH_N;
-        ch[CH_GTD] = 0.0;
-        ch[CH_RESTART] = 0.0;
+        for (int x = 0; x < CH_N; ++x) ch[x] = 0.0;
         ch[CH_GG_OLD] = gg[0];
         ch[CH_STOP] = gg[0] == 0.0 ? 1.0 : 0.0;
     }
@@ -379,12 +447,14 @@ __global__ __launch_bounds__(NTHR) void k_chan_cg_init(const double *__restrict_
 
 // Step 1: d <- -gt + beta d, projected onto the feasible directions at the
 // bound (d = 0 on the active set, d >= 0 on the other bound pixels); partial
-// gt . d.
+// gt . d.  The last workgroup of an image takes step 2: restart with d = -gt
+// when gt . d >= 0, stop when the projected gradient is zero.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const R *__restrict__ g,
                                                  const R *__restrict__ gt, R *__restrict__ dir,
-                                                 const double *__restrict__ scal, const double *__restrict__ chan,
-                                                 double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb) {
+                                                 const double *__restrict__ scal, double *__restrict__ chan,
+                                                 double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb,
+                                                 unsigned *__restrict__ ctr) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const double beta = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_BETA];
@@ -406,41 +476,38 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
     }
     block_sum<1>(acc);
     if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
-}
-
-// Step 3: apply the restart, stage B = A o d for the forward model, and the
-// partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts).
-template <typename R>
-__global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
-                                                  R *__restrict__ dir, const R *__restrict__ beam,
-                                                  R *__restrict__ bop, const int *__restrict__ ichan_base,
-                                                  const double *__restrict__ pp_gtd,
-                                                  const double *__restrict__ scal,
-                                                  double *__restrict__ chan,
-                                                  double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
-                                                  double M, double Mb) {
-    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
-    const long long npix = (long long)n * n;
-    // the thread's first pixel, loaded ahead of the reduction below (pixel 0
-    // stands in past the end)
-    const long long p_1 = (long long)pb * pb_len + threadIdx.x;
-    const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
-    const R d_1 = dir[q_1], g_1 = gt[q_1], x_1 = I[q_1];
-    // step 2, recomputed by every workgroup of the channel: restart with
-    // d = -gt when gt.d >= 0; stop when the projected gradient is zero
+    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double gtd[1];
-    sum_partials<1>(pp_gtd + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
-    const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
-    const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0 || gg == 0.0;
-    const bool restart = gtd[0] >= 0.0;
-    __syncthreads();
-    if (pb == 0 && threadIdx.x == 0) {
+    sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
+    if (threadIdx.x == 0) {
+        const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
         double *ch = chan + (size_t)c * CH_N;
-        if (stop) ch[CH_STOP] = 1.0;
+        const bool restart = gtd[0] >= 0.0;
+        if (stop || gg == 0.0) ch[CH_STOP] = 1.0;
         ch[CH_RESTART] = restart ? 1.0 : 0.0;
         ch[CH_GTD] = restart ? -gg : gtd[0];
         ch[CH_GG_OLD] = gg;
     }
+}
+
+// Step 3: apply the restart, stage B = A o d for the forward model, and the
+// partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts); the
+// last workgroup of an image stores their totals (and starts the line search
+// of an image that has no visibilities).
+template <typename R>
+__global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
+                                                  R *__restrict__ dir, const R *__restrict__ beam,
+                                                  R *__restrict__ bop, const int *__restrict__ ichan_base,
+                                                  double *__restrict__ chan,
+                                                  double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
+                                                  double M, double Mb, unsigned *__restrict__ ctr,
+                                                  const int *__restrict__ ivis_base, double *__restrict__ ls,
+                                                  double lam) {
+    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
+    const long long npix = (long long)n * n;
+    const double *chc = chan + (size_t)c * CH_N;
+    const bool stop = chc[CH_STOP] != 0.0;
+    const bool restart = chc[CH_RESTART] != 0.0;
     const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
     double amax = INFINITY;
     double acc[2] = {0.0, 0.0};
@@ -448,8 +515,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
-        double d = r == 0 ? (double)d_1 : (double)dir[q];
-        if (restart) d = -(r == 0 ? (double)g_1 : (double)gt[q]);
+        double d = restart ? -(double)gt[q] : (double)dir[q];
         if (stop) d = 0.0;
         const R dr = (R)d;
         d = (double)dr;
@@ -457,7 +523,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
             bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
-        const double x = r == 0 ? (double)x_1 : (double)I[q];
+        const double x = (double)I[q];
         if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
         acc[0] += d * (log(x / M) + 1.0);
         acc[1] += d * d / x;
@@ -469,6 +535,19 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         pp[0] = acc[0];
         pp[1] = acc[1];
         pp[2] = amax;
+    }
+    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
+    double e[2];
+    sum_partials<2>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, e);
+    const double am = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 2);
+    if (threadIdx.x == 0) {
+        double *ch = chan + (size_t)c * CH_N;
+        ch[CH_E1] = e[0];
+        ch[CH_E2] = e[1];
+        ch[CH_AMAX] = am;
+        // no visibility workgroup will start this image's line search
+        if (ivis_base[c + 1] == ivis_base[c])
+            ls_init(ls + (size_t)c * LSS_N, 0.0, 0.0, lam * e[0], lam * e[1], am, ch[CH_STOP] != 0.0);
     }
 }
 
@@ -606,46 +685,27 @@ __device__ __forceinline__ void ls_eval(const double *st, const double *pp, int 
     }
 }
 
-// Pass of the line search: pass 0 initialises the state; later passes
-// advance it with the previous pass's partials.  Every workgroup of the
-// channel computes the same state; workgroup 0 stores it.  Then each
-// workgroup evaluates the phi', phi'' partials at the LS_K trial steps.
+// Pass of the line search: every workgroup of an image reads the state and
+// evaluates the phi', phi'' partials at its LS_K trial steps; the last
+// workgroup to arrive advances the state with the totals (in the last pass,
+// a search that has not converged takes its fallback step).  A converged
+// search makes the whole image skip the pass.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const R *__restrict__ dir,
-                                                  const double *__restrict__ ls_prev, double *__restrict__ ls_next,
-                                                  const double *__restrict__ pp_prev, double *__restrict__ pp_next,
-                                                  const double *__restrict__ vispart, const int *__restrict__ vis_base,
-                                                  const double *__restrict__ chan,
-                                                  int n, int n_pb, int pb_len, double M, double lam, int first) {
+                                                  double *__restrict__ ls, double *__restrict__ ppart,
+                                                  int n, int n_pb, int pb_len, double M, double lam, int last_pass,
+                                                  unsigned *__restrict__ ctr) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
-    // the thread's first pixel, loaded ahead of the state and partial
-    // reductions so that the latencies overlap (pixel 0 stands in past the end)
+    // the thread's first pixel, loaded ahead of the state (pixel 0 stands in
+    // past the end)
     const long long p_1 = (long long)pb * pb_len + threadIdx.x;
     const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
     const R d_1 = dir[q_1], x_1 = I[q_1];
     __shared__ double st[LSS_N];
-    if (first) {
-        double ab[2], ent[2];
-        sum_partials<2>(vispart + (size_t)vis_base[c] * NPART, vis_base[c + 1] - vis_base[c], 0, ab);
-        sum_partials<2>(pp_prev + (size_t)c * n_pb * NPART, n_pb, 0, ent);
-        const double amax = min_partials(pp_prev + (size_t)c * n_pb * NPART, n_pb, 2);
-        if (threadIdx.x == 0) {
-            const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
-            ls_init(st, ab[0], ab[1], lam * ent[0], lam * ent[1], amax, stop);
-        }
-        __syncthreads();
-    } else {
-        if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
-        __syncthreads();
-        if ((int)st[LSS_PHASE] != PH_DONE) {
-            double f[LS_K], h[LS_K];
-            ls_eval(st, pp_prev + (size_t)c * n_pb * NPART, n_pb, lam, f, h);
-            if (threadIdx.x == 0) ls_update(st, f, h);
-        }
-        __syncthreads();
-    }
-    if (pb == 0 && threadIdx.x < LSS_N) ls_next[(size_t)c * LSS_N + threadIdx.x] = st[threadIdx.x];
+    double *lsc = ls + (size_t)c * LSS_N;
+    if (threadIdx.x < LSS_N) st[threadIdx.x] = lsc[threadIdx.x];
+    __syncthreads();
     if ((int)st[LSS_PHASE] == PH_DONE) return;
     double tr[LS_K];
 #pragma unroll
@@ -670,106 +730,78 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
     block_sum<2 * LS_K>(acc);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int m = 0; m < 2 * LS_K; ++m) pp_next[((size_t)c * n_pb + pb) * NPART + m] = acc[m];
+        for (int m = 0; m < 2 * LS_K; ++m) ppart[((size_t)c * n_pb + pb) * NPART + m] = acc[m];
     }
+    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
+    double f[LS_K], h[LS_K];
+    ls_eval(st, ppart + (size_t)c * n_pb * NPART, n_pb, lam, f, h);
+    if (threadIdx.x == 0) {
+        ls_update(st, f, h);
+        if (last_pass && (int)st[LSS_PHASE] != PH_DONE) ls_finish(st, ls_fallback(st));
+    }
+    __syncthreads();
+    if (threadIdx.x < LSS_N) lsc[threadIdx.x] = st[threadIdx.x];
 }
 
-// Step 8: final line-search update, then I <- max(I + alpha d, M) and the
-// entropy partial of the new image.
+// Step 8: I <- max(I + alpha d, M) with the accepted step and the entropy
+// partial of the new image (pixel workgroups); R <- R + alpha Vd and its
+// chi^2 partials (visibility workgroups, one item each).  The last
+// workgroup of an image stores Phi, chi^2, S, alpha and alpha_max.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *__restrict__ dir,
-                                                    const double *__restrict__ ls_prev, const double *__restrict__ pp_prev,
-                                                    double *__restrict__ pp_out, double *__restrict__ scal,
-                                                    double *__restrict__ chan, int *__restrict__ flag,
+                                                    const double *__restrict__ ls, double *__restrict__ pp_out,
+                                                    double *__restrict__ scal, double *__restrict__ chan,
+                                                    int *__restrict__ flag,
                                                     int n, int n_pb, int pb_len, double M, double Mb, double lam,
                                                     const VisItem *__restrict__ vitems, const float *__restrict__ w,
                                                     double2 *__restrict__ Rv, const double2 *__restrict__ Vd,
                                                     double *__restrict__ vispart, const int *__restrict__ chan_img,
-                                                    int n_pixwg, int with_max) {
-    // workgroups past the pixel grid update the residuals of one visibility
-    // item each (step 9); every workgroup derives the channel's final alpha
-    // from the line-search state itself
+                                                    const int *__restrict__ ivis_base, int n_pixwg, int with_max,
+                                                    unsigned *__restrict__ ctr) {
     const bool visw = (int)blockIdx.x >= n_pixwg;
     const int vi = (int)blockIdx.x - n_pixwg;
     const VisItem vit = visw ? vitems[vi] : VisItem{};
     const int c = visw ? chan_img[vit.chan] : (int)blockIdx.x / n_pb, pb = visw ? -1 : (int)blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
-    // the thread's first pixel, loaded ahead of the line-search reduction
-    // (pixel 0 of the image stands in for residual workgroups and past the end)
-    const long long p_1 = visw ? 0 : (long long)pb * pb_len + threadIdx.x;
-    const size_t q_1 = (size_t)c * npix + (p_1 < npix ? p_1 : 0);
-    const R d_1 = dir[q_1], x_1 = I[q_1];
-    __shared__ double st[LSS_N];
-    if (threadIdx.x < LSS_N) st[threadIdx.x] = ls_prev[(size_t)c * LSS_N + threadIdx.x];
-    __syncthreads();
-    if ((int)st[LSS_PHASE] != PH_DONE) {
-        double f[LS_K], h[LS_K];
-        ls_eval(st, pp_prev + (size_t)c * n_pb * NPART, n_pb, lam, f, h);
-        if (threadIdx.x == 0) {
-            ls_update(st, f, h);
-            if ((int)st[LSS_PHASE] != PH_DONE) ls_finish(st, ls_fallback(st));
-        }
-    }
-    __syncthreads();
-    const double al = st[LSS_ALPHA];
+    const double *lsc = ls + (size_t)c * LSS_N;
+    const double al = lsc[LSS_ALPHA];
     if (visw) {
         vis_item(vit, vi, nullptr, 0, 0, nullptr, w, Rv, const_cast<double2 *>(Vd), nullptr, vispart, 3, with_max, al);
-        return;
-    }
-    if (pb == 0 && threadIdx.x == 0) {
-        double *sc = scal + (size_t)c * UVMEM_NSCAL;
-        sc[UVMEM_S_ALPHA] = al;
-        sc[UVMEM_S_ALPHA_MAX] = st[LSS_AMAX] < 0.0 ? INFINITY : st[LSS_AMAX];
-        if (al == 0.0) chan[(size_t)c * CH_N + CH_STOP] = 1.0;
-    }
-    double acc[1] = {0.0};
-    int bad = 0;
-    for (int r = 0; r < pb_len / NTHR; ++r) {
-        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
-        if (p >= npix) break;
-        const size_t q = (size_t)c * npix + p;
-        double x = r == 0 ? (double)x_1 : (double)I[q];
-        if (al != 0.0) {
-            x = fmax(x + al * (r == 0 ? (double)d_1 : (double)dir[q]), Mb);
-            const R xr = (R)x;
-            I[q] = xr;
-            x = (double)xr;
+    } else {
+        double acc[1] = {0.0};
+        int bad = 0;
+        for (int r = 0; r < pb_len / NTHR; ++r) {
+            const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
+            if (p >= npix) break;
+            const size_t q = (size_t)c * npix + p;
+            double x = (double)I[q];
+            if (al != 0.0) {
+                x = fmax(x + al * (double)dir[q], Mb);
+                const R xr = (R)x;
+                I[q] = xr;
+                x = (double)xr;
+            }
+            if (!(x > 0.0)) bad = 1;
+            else acc[0] += x * log(x / M);
         }
-        if (!(x > 0.0)) bad = 1;
-        else acc[0] += x * log(x / M);
+        if (bad) atomicOr(flag, 1);
+        block_sum<1>(acc);
+        if (threadIdx.x == 0) pp_out[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
     }
-    if (bad) atomicOr(flag, 1);
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) pp_out[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
-}
-
-// Step 12: Polak-Ribiere beta (clipped at 0) and the per-channel scalars.
-__global__ __launch_bounds__(NTHR) void k_chan_beta(const double *__restrict__ vispart, const int *__restrict__ vis_base,
-                                                    const double *__restrict__ pp_S, const double *__restrict__ pp_g,
-                                                    int n_pb, double lam, double *__restrict__ scal,
-                                                    double *__restrict__ chan, double *__restrict__ user) {
-    const int c = blockIdx.x;
-    double x2[1], S[1], gg[2];
-    sum_partials<1>(vispart + (size_t)vis_base[c] * NPART, vis_base[c + 1] - vis_base[c], 0, x2);
-    sum_partials<1>(pp_S + (size_t)c * n_pb * NPART, n_pb, 0, S);
-    sum_partials<2>(pp_g + (size_t)c * n_pb * NPART, n_pb, 0, gg);
+    const int v0 = ivis_base[c], v1 = ivis_base[c + 1];
+    if (!arrive_last(ctr + c, (unsigned)(n_pb + v1 - v0))) return;
+    double x2[1], S[1];
+    sum_partials<1>(vispart + (size_t)v0 * NPART, v1 - v0, 0, x2);
+    sum_partials<1>(pp_out + (size_t)c * n_pb * NPART, n_pb, 0, S);
     if (threadIdx.x == 0) {
         double *sc = scal + (size_t)c * UVMEM_NSCAL;
-        double *ch = chan + (size_t)c * CH_N;
         const double chi2 = 0.5 * x2[0];
-        const double gold = ch[CH_GG_OLD];
-        const bool stop = ch[CH_STOP] != 0.0;
-        double beta = 0.0;
-        if (!stop && gold > 0.0) beta = fmax(0.0, (gg[0] - gg[1]) / gold);
         sc[UVMEM_S_PHI] = chi2 + lam * S[0];
         sc[UVMEM_S_CHI2] = chi2;
         sc[UVMEM_S_S] = S[0];
-        sc[UVMEM_S_BETA] = beta;
-        sc[UVMEM_S_GNORM2] = gg[0];
-        if (sc[UVMEM_S_ALPHA] != 0.0) sc[UVMEM_S_ITER] += 1.0;
-        if (user) {
-            for (int x = 0; x < UVMEM_NSCAL; ++x) user[(size_t)c * UVMEM_NSCAL + x] = sc[x];
-        }
+        sc[UVMEM_S_ALPHA] = al;
+        sc[UVMEM_S_ALPHA_MAX] = lsc[LSS_AMAX] < 0.0 ? INFINITY : lsc[LSS_AMAX];
+        if (al == 0.0) chan[(size_t)c * CH_N + CH_STOP] = 1.0;
     }
 }
 
@@ -796,13 +828,16 @@ template <typename R> inline R *P(void *p) { return reinterpret_cast<R *>(p); }
 template <typename R> inline const R *CP(const void *p) { return reinterpret_cast<const R *>(p); }
 
 inline int pix_grid(const uvmem_ctx *c) { return c->nimg * c->n_pb; }
+// Partial records of the pixel passes: buffer 0 holds the prologue's entropy
+// partials until the evaluation's gradient pass has read them; every CG pass
+// writes buffer 1 and its last workgroups read it in the same launch.
 inline double *pp(const uvmem_ctx *c, int buf) {
     return c->d_ppart + (size_t)buf * c->nimg * c->n_pb * NPART;
 }
+inline unsigned *ctr(const uvmem_ctx *c, int site) { return c->d_ctr + (size_t)site * c->nimg; }
 // The fp16 split adjoint scales its coefficients by the channel's max |w R|,
 // which the visibility pass leaves in slot 2 of its partial records.
 inline int adj_scaled(const uvmem_ctx *c) { return c->prec == UVMEM_FP16X3 ? 1 : 0; }
-inline double *lsb(const uvmem_ctx *c, int buf) { return c->d_ls + (size_t)buf * c->nimg * LSS_N; }
 
 template <typename R>
 hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipStream_t st) {
@@ -816,45 +851,81 @@ hipError_t t_prologue(const uvmem_ctx *c, const void *I, int with_entropy, hipSt
 // enough, else 1 (more workgroups, fewer loads in flight per thread); the
 // split-K partials are FP32 for the split precisions, else FP64
 template <typename R, typename PT>
-void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, double *user,
+                   hipStream_t st) {
     const PT *gp = static_cast<const PT *>(c->d_gpart);
     // gradients (modes 1, 2) follow the region-restricted adjoint and its slots
     const int *slots = (mode == 1 || mode == 2) && c->has_region ? c->d_slot_base_m : c->d_slot_base;
+    const GradTail tail{ctr(c, CTR_GRAD), c->d_vispart, c->d_ivis_base, pp(c, 0), c->d_scal, c->d_chan, user};
     if (c->pix_blk >= 4 * NTHR)
         hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, slots,
                            c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
-                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode, tail);
     else
         hipLaunchKernelGGL((k_grad<R, 1, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, slots,
                            c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,
-                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode);
+                           c->d_wscale, c->d_mask, c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, mode, tail);
 }
 
 template <typename R>
-void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, hipStream_t st) {
+void grad_launch(const uvmem_ctx *c, const void *I, void *out, double *ppart, int mode, double *user,
+                 hipStream_t st) {
     if (c->gpart_f32)
-        grad_launch_t<R, float>(c, I, out, ppart, mode, st);
+        grad_launch_t<R, float>(c, I, out, ppart, mode, user, st);
     else
-        grad_launch_t<R, double>(c, I, out, ppart, mode, st);
-}
-
-template <typename R>
-hipError_t t_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st) {
-    grad_launch<R>(c, I, out, pp(c, 1), mode, st);
-    return hipGetLastError();
+        grad_launch_t<R, double>(c, I, out, ppart, mode, user, st);
 }
 
 template <typename R>
 hipError_t t_cg_init_dir(const uvmem_ctx *c, const void *I, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init<R>, dim3(pix_grid(c)), dim3(NTHR), 0, st, CP<R>(I), CP<R>(c->d_g),
-                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
-    hipLaunchKernelGGL(k_chan_cg_init, dim3(c->nimg), dim3(NTHR), 0, st, pp(c, 0), c->n_pb, c->d_scal,
-                       c->d_chan);
+                       P<R>(c->d_gt), P<R>(c->d_dir), pp(c, 1), c->n, c->n_pb, c->pix_blk, c->Mb,
+                       ctr(c, CTR_INIT), c->d_scal, c->d_chan);
     return hipGetLastError();
 }
 
+// The CG step in three phases around the DFT launches (phase 0: before the
+// forward model, 1: between forward and adjoint, 2: after the adjoint).
 template <typename R>
-hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st);
+hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
+    const dim3 gp(pix_grid(c)), blk(NTHR);
+    if (phase == 0) {
+        // 1-2. direction update and projection; restart test and stop
+        hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
+                           c->d_scal, c->d_chan, pp(c, 1), c->n, c->n_pb, c->pix_blk, c->Mb, ctr(c, CTR_DIR));
+        // 3. restart applied, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
+        hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
+                           CP<R>(c->d_beam), P<R>(c->d_bop), c->d_ichan_base, c->d_chan, pp(c, 1), c->n, c->np,
+                           c->n_pb, c->pix_blk, c->M, c->Mb, ctr(c, CTR_DIR2), c->d_ivis_base, c->d_ls, c->lam);
+        return hipGetLastError();
+    }
+    if (phase == 1) {
+        // 5. Vd and the quadratic coefficients a, b of chi^2 along d; the
+        // line search starts from them
+        if (c->n_visit)
+            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart,
+                               c->has_region ? c->n_fparts_m : c->n_fparts,
+                               (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
+                               c->d_scal, c->d_vispart, c->d_chan_img, 2, 0, ctr(c, CTR_VIS), c->d_ivis_base,
+                               c->d_chan, c->d_ls, c->lam);
+        // 6-7. line-search passes (the last one accepts a step)
+        const int L = c->ls_steps;
+        for (int t = 0; t < L; ++t)
+            hipLaunchKernelGGL(k_ls_step<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_dir), c->d_ls, pp(c, 1), c->n,
+                               c->n_pb, c->pix_blk, c->M, c->lam, t == L - 1 ? 1 : 0, ctr(c, CTR_LS));
+        // 8-9. I <- max(I + alpha d, M) and its entropy partial (pixel
+        // workgroups); R <- R + alpha Vd and the chi^2 partials (visibility
+        // workgroups); Phi of the new image
+        hipLaunchKernelGGL(k_cg_update<R>, dim3(pix_grid(c) + c->n_visit), blk, 0, st, P<R>(I), CP<R>(c->d_dir),
+                           c->d_ls, pp(c, 1), c->d_scal, c->d_chan, c->d_flag, c->n, c->n_pb, c->pix_blk, c->M,
+                           c->Mb, c->lam, c->d_vis, c->d_w, c->d_R, c->d_Vd, c->d_vispart, c->d_chan_img,
+                           c->d_ivis_base, pix_grid(c), adj_scaled(c), ctr(c, CTR_UPD));
+        return hipGetLastError();
+    }
+    // 10-12. gradient at the new point, projected gradient, beta and the scalars
+    grad_launch<R>(c, I, c->d_g, pp(c, 1), 2, user, st);
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -891,7 +962,18 @@ hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_
     if (c->n_visit == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart,
-                       c->d_chan_img, mode, adj_scaled(c));
+                       c->d_chan_img, mode, adj_scaled(c), (unsigned *)nullptr, (const int *)nullptr,
+                       (const double *)nullptr, (double *)nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_vis_sum_raw(const VisItem *items, int n_items, const double2 *vpart, int n_parts, long long ztot,
+                              double2 *out, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vis, dim3(n_items), dim3(NTHR), 0, st, items, vpart, n_parts, ztot,
+                       (const double2 *)nullptr, (const float *)nullptr, (double2 *)nullptr, (double2 *)nullptr,
+                       out, (const double *)nullptr, (double *)nullptr, (const int *)nullptr, 0, 0,
+                       (unsigned *)nullptr, (const int *)nullptr, (const double *)nullptr, (double *)nullptr, 0.0);
     return hipGetLastError();
 }
 
@@ -899,17 +981,14 @@ hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t 
     if (c->n_visit == 0 || !adj_scaled(c)) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, (const float *)nullptr, const_cast<double2 *>(coef), c->d_Vd,
-                       (double2 *)nullptr, c->d_scal, c->d_vispart, c->d_chan_img, 4, 1);
+                       (double2 *)nullptr, c->d_scal, c->d_vispart, c->d_chan_img, 4, 1, (unsigned *)nullptr,
+                       (const int *)nullptr, (const double *)nullptr, (double *)nullptr, 0.0);
     return hipGetLastError();
 }
 
-hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, hipStream_t st) {
-    return c->prec == UVMEM_FP64 ? t_grad<double>(c, I, out, mode, st) : t_grad<float>(c, I, out, mode, st);
-}
-
-hipError_t launch_chan_phi(const uvmem_ctx *c, double *user_scal, hipStream_t st) {
-    hipLaunchKernelGGL(k_chan_phi, dim3(c->nimg), dim3(NTHR), 0, st, c->d_vispart, c->d_ivis_base, pp(c, 0),
-                       c->n_pb, c->lam, c->d_scal, user_scal);
+hipError_t launch_grad(const uvmem_ctx *c, const void *I, void *out, int mode, double *user_scal, hipStream_t st) {
+    if (c->prec == UVMEM_FP64) grad_launch<double>(c, I, out, pp(c, 1), mode, user_scal, st);
+    else grad_launch<float>(c, I, out, pp(c, 1), mode, user_scal, st);
     return hipGetLastError();
 }
 
@@ -929,28 +1008,10 @@ hipError_t launch_set_hist(const uvmem_ctx *c, double *hist, hipStream_t st) {
     return hipGetLastError();
 }
 
-namespace {
-template <typename R>
-hipError_t t_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
-    hipError_t e;
-    const dim3 gp(pix_grid(c)), gc(c->nimg), blk(NTHR);
-    // 1. direction update and projection; partial gt.d
-    hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       c->d_scal, c->d_chan, pp(c, 0), c->n, c->n_pb, c->pix_blk, c->Mb);
-    // 2-3. restart test, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
-    hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
-                       CP<R>(c->d_beam), P<R>(c->d_bop), c->d_ichan_base, pp(c, 0), c->d_scal, c->d_chan, pp(c, 1),
-                       c->n, c->np, c->n_pb, c->pix_blk, c->M, c->Mb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // 4. Vd = F(d)
-    return hipSuccess;
+hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
+    return c->prec == UVMEM_FP64 ? t_cg_phase<double>(c, I, user, phase, st)
+                                 : t_cg_phase<float>(c, I, user, phase, st);
 }
-}  // namespace
-
-// The CG step is split so that the host can bracket the DFT launches with
-// timing events: cg_phase(c, I, user, phase, st) with phase 0 = before the
-// forward model, 1 = between forward and adjoint, 2 = after the adjoint.
-hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st);
 
 hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t st) {
     hipError_t e;
@@ -959,53 +1020,6 @@ hipError_t launch_cg_step(const uvmem_ctx *c, void *I, double *user, hipStream_t
     if ((e = launch_cg_phase(c, I, user, 1, st)) != hipSuccess) return e;
     if ((e = launch_adjoint(c, c->d_R, c->d_w, st, 1)) != hipSuccess) return e;
     return launch_cg_phase(c, I, user, 2, st);
-}
-
-namespace {
-template <typename R>
-hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
-    const dim3 gp(pix_grid(c)), gc(c->nimg), blk(NTHR);
-    if (phase == 0) return t_cg_step<R>(c, I, user, st);
-    if (phase == 1) {
-        // 5. Vd and the quadratic coefficients a, b of chi^2 along d
-        if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart,
-                               c->has_region ? c->n_fparts_m : c->n_fparts,
-                               (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, c->d_chan_img, 2, 0);
-        // 6-7. line search: pass 0 initialises the state (from the visibility
-        // partials and the direction pass's partials in pp[1]); pass t > 0
-        // advances S^t-1 (ls[t%2]) with P^t-1 (pp[(t+1)%2]); every pass
-        // stores S^t in ls[(t+1)%2] and evaluates P^t into pp[t%2]
-        const int L = c->ls_steps;
-        for (int t = 0; t < L; ++t) {
-            hipLaunchKernelGGL(k_ls_step<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_dir), lsb(c, t % 2),
-                               lsb(c, (t + 1) % 2), pp(c, (t + 1) % 2), pp(c, t % 2), c->d_vispart,
-                               c->d_ivis_base, c->d_chan, c->n, c->n_pb, c->pix_blk, c->M, c->lam, t == 0 ? 1 : 0);
-        }
-        const int last = (L - 1) % 2;   // pp buffer holding the last partials
-        // 8-9. one launch: the final update of the step, I <- max(I + alpha d, M)
-        // and its entropy partial (pixel workgroups); R <- R + alpha Vd and the
-        // chi^2 partials (visibility workgroups)
-        hipLaunchKernelGGL(k_cg_update<R>, dim3(pix_grid(c) + c->n_visit), blk, 0, st, P<R>(I), CP<R>(c->d_dir),
-                           lsb(c, 1 - last), pp(c, last), pp(c, 1 - last), c->d_scal, c->d_chan, c->d_flag, c->n,
-                           c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, c->d_vis, c->d_w, c->d_R, c->d_Vd,
-                           c->d_vispart, c->d_chan_img, pix_grid(c), adj_scaled(c));
-        return hipGetLastError();
-    }
-    // 11. gradient at the new point, projected gradient, PR partials
-    const int last = (c->ls_steps - 1) % 2;
-    grad_launch<R>(c, I, c->d_g, pp(c, last), 2, st);
-    // 12. beta and scalars
-    hipLaunchKernelGGL(k_chan_beta, gc, blk, 0, st, c->d_vispart, c->d_ivis_base, pp(c, 1 - last), pp(c, last),
-                       c->n_pb, c->lam, c->d_scal, c->d_chan, user);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
-    return c->prec == UVMEM_FP64 ? t_cg_phase<double>(c, I, user, phase, st)
-                                 : t_cg_phase<float>(c, I, user, phase, st);
 }
 
 }  // namespace uvm

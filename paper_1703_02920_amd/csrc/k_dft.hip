@@ -19,6 +19,8 @@
 // kernels take sincospi of the reduced phase, the FP32 ones cos and sin from
 // the quadrant and remainder of 4 t (see cisphase), the split ones the
 // hardware sine and cosine.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace uvm {
@@ -1236,6 +1238,572 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restri
             }
 }
 
+// Adjoint, split precision, 256 x 256 pixel tile, eight waves of 128 (i) x 64
+// (j), software-pipelined over steps of 16 visibilities.  The real and
+// imaginary parts of a step are concatenated along the contraction
+// dimension, so one v_mfma_f32_16x16x32 covers the step's 16 visibilities:
+//   G[i][j] += sum_{k'} A[i][k'] B[k'][j],
+//   A[i][k] = Re P[k][i], A[i][16 + k] = -Im P[k][i]   (P = w c conj E_v)
+//   B[k][j] = cos 2 pi a_k m_j, B[16 + k][j] = sin 2 pi a_k m_j,
+// three products per pair (hi hi, hi lo, lo hi).  Per step and workgroup:
+//   tables  -- fine and coarse factors of both axes (one hardware sin/cos per
+//              entry, 1,024 entries: two per thread),
+//   operands -- one 32-element row per thread, P (threads 0-255) or E
+//              (256-511), formed from the tables and split into hi and lo,
+//   products -- 96 matrix instructions per wave.
+// The operand rows of step s + 1 and the tables of step s + 2 are formed
+// while the matrix cores contract step s: operands and tables are
+// double-buffered in LDS, so one workgroup barrier per step orders them.
+// Chunk sums are FP32 and the partial tile is stored in FP32.
+template <typename H>
+__global__ __launch_bounds__(512, 1) void k_adjoint_h16s(const AdjItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const double2 *__restrict__ coef,
+                                                         const float *__restrict__ w,
+                                                         const double *__restrict__ vispart,
+                                                         const int *__restrict__ vis_base,
+                                                         float *__restrict__ gpart, int n, int np) {
+    typedef typename Half16<H>::h8 h8;
+    constexpr int TT = 256;
+    constexpr int KV = 16;         // visibilities per step
+    constexpr int KP = 2 * KV;     // contraction length per step (re, im)
+    constexpr int NR = 8;          // 16-row blocks per wave (128 rows)
+    constexpr int NCB = 4;         // 16-column blocks per wave (64 columns)
+    constexpr int TR = KV + 2;     // table row stride in float2 (16-byte aligned rows)
+    // operands: [buffer][hi, lo][row: P 0-255, E 256-511][KP], 16-byte
+    // chunks XOR-swizzled by (row >> 1) & 3
+    __shared__ __attribute__((aligned(16))) H sOp[2][2][2 * TT][KP];
+    // tables: [buffer][axis: v (P side), u (E side)][fine, coarse][index][k]
+    __shared__ __attribute__((aligned(16))) float2 sTab[2][2][2][16][TR];
+    __shared__ double sRed[8];
+    auto swz = [](int r, int c) { return 8 * (c ^ ((r >> 1) & 3)); };
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q = lane & 15, g = lane >> 4;
+    const int wi = (wave >> 2) * 128, wj = (wave & 3) * 64;
+    const int half = n / 2;
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        double m = 0.0;
+        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 512)
+            m = fmax(m, vispart[(size_t)x * NPART + 2]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sRed[wave] = m;
+        __syncthreads();
+        m = sRed[0];
+#pragma unroll
+        for (int x = 1; x < 8; ++x) m = fmax(m, sRed[x]);
+        scale = pow2_scale((float)m);
+    }
+
+    // table task: axis tax (0: v / P side, 1: u / E side), index tix, visibility tk of the step
+    const int tax = tid >> 8, tix = (tid >> 4) & 15, tk = tid & 15;
+    const double *xsrc = tax == 0 ? b : a;
+    const int origin = (tax == 0 ? i0 : j0) + tix - half;
+    struct Pre {
+        double x;
+        double2 c;
+        float w;
+    };
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k = kb + tk;
+        p.x = 0.0;
+        p.c = make_double2(0.0, 0.0);
+        p.w = 0.f;
+        if (k < it.kend) {
+            p.x = xsrc[k];
+            if (tax == 0) {
+                p.c = coef[k];
+                p.w = w ? w[k] : 1.f;
+            }
+        }
+    };
+    // fine[idx][k] = conj(s w_k c_k E(b_k (i0 + idx - N/2))) or E(a_k (j0 + idx - N/2));
+    // coarse[idx][k] = conj E(16 b_k idx) or E(16 a_k idx)   (E(x) = exp(2 pi i x))
+    auto gen = [&](int tb, const Pre &p) {
+        float c, sn;
+        cis2pi_hw((float)phase(p.x, origin), c, sn);
+        float2 fine;
+        if (tax == 0) {
+            const float cr = scale * (float)((double)p.w * p.c.x);
+            const float ci = scale * (float)((double)p.w * p.c.y);
+            fine = make_float2(cr * c - ci * sn, -(cr * sn + ci * c));
+        } else {
+            fine = make_float2(c, sn);
+        }
+        sTab[tb][tax][0][tix][tk] = fine;
+        cis2pi_hw((float)phase(p.x, 16 * tix), c, sn);
+        sTab[tb][tax][1][tix][tk] = make_float2(c, tax == 0 ? -sn : sn);
+    };
+    // operand row of this thread: side fside (0: P, 1: E), row frow of that side
+    const int fside = tid >> 8, frow = tid & 255;
+    const int fq = frow & 15, ft = frow >> 4;
+    const int orow = fside * TT + frow;
+    // half a row: visibilities 8 hk .. 8 hk + 7, both parts (chunks hk and 2 + hk)
+    auto form_half = [&](int tb, int ob, int hk) {
+        const float2 *fr = &sTab[tb][fside][0][fq][8 * hk];
+        const float2 *cr = &sTab[tb][fside][1][ft][8 * hk];
+        float re[8], im[8];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const float4 f2 = *reinterpret_cast<const float4 *>(fr + e);
+            const float4 c2 = *reinterpret_cast<const float4 *>(cr + e);
+            re[e] = f2.x * c2.x - f2.y * c2.y;
+            im[e] = f2.x * c2.y + f2.y * c2.x;
+            re[e + 1] = f2.z * c2.z - f2.w * c2.w;
+            im[e + 1] = f2.z * c2.w + f2.w * c2.z;
+        }
+        h8 rh, rl, ih, il;
+        split8<H>(re, rh, rl);
+        split8<H>(im, ih, il);
+        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, hk)]) = rh;
+        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, hk)]) = rl;
+        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, 2 + hk)]) = ih;
+        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, 2 + hk)]) = il;
+    };
+
+    floatx4 acc[NR][NCB];
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+        for (int y = 0; y < NCB; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const long long kb0 = it.kbeg;
+    const int nsteps = (int)((it.kend - it.kbeg + KV - 1) / KV);
+    Pre pre;
+    fetch(kb0, pre);
+    gen(0, pre);
+    fetch(kb0 + KV, pre);
+    __syncthreads();
+    form_half(0, 0, 0);
+    form_half(0, 0, 1);
+    gen(1, pre);
+    __syncthreads();
+    // One basic block per step (no branches), so that the scheduler can
+    // spread the operand formation of step s + 1 and the table work of step
+    // s + 2 between the matrix instructions of step s.  In the last steps
+    // they form rows from stale tables or zero data into buffers that are
+    // never read again.
+    for (int s = 0; s < nsteps; ++s) {
+        const int ob = s & 1;
+        fetch(kb0 + (long long)(s + 2) * KV, pre);
+        // E fragments of this wave's four column blocks
+        h8 eh[NCB], el[NCB];
+#pragma unroll
+        for (int y = 0; y < NCB; ++y) {
+            const int r = TT + wj + 16 * y + q;
+            eh[y] = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, g)]);
+            el[y] = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, g)]);
+        }
+        // the eight row blocks, the P fragments of the next block loaded
+        // while this one contracts
+        h8 ph, pl;
+        {
+            const int r = wi + q;
+            ph = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, g)]);
+            pl = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, g)]);
+        }
+#pragma unroll
+        for (int x = 0; x < NR; ++x) {
+            const h8 ch = ph, cl = pl;
+            if (x + 1 < NR) {
+                const int r = wi + 16 * (x + 1) + q;
+                ph = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, g)]);
+                pl = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, g)]);
+            }
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(ch, eh[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(ch, el[y], acc[x][y]);
+#pragma unroll
+            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(cl, eh[y], acc[x][y]);
+            if (x == 1) form_half(ob ^ 1, ob ^ 1, 0);
+            if (x == 3) gen(ob, pre);
+            if (x == 5) form_half(ob ^ 1, ob ^ 1, 1);
+        }
+        __syncthreads();
+    }
+    float *out = gpart + (size_t)it.slot * np * np;
+    const float inv = 1.f / scale;   // a power of two: exact
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+        for (int y = 0; y < NCB; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * x + 4 * g + r;
+                const int j = j0 + wj + 16 * y + q;
+                out[(size_t)i * np + j] = acc[x][y][r] * inv;
+            }
+}
+
+// 32 x 32 x 16 forms of the split-precision products (v_mfma_f32_32x32x16_{bf16,
+// f16}): lane l supplies A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32],
+// e = 0..7, and holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in accumulator
+// register r (checked on gfx950).  They issue twice the products per cycle of
+// the 16 x 16 x 32 forms on this hardware.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+template <typename H> struct Half32;
+template <> struct Half32<__bf16> {
+    static __device__ __forceinline__ floatx16 mma(bf16x8 a, bf16x8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Half32<_Float16> {
+    static __device__ __forceinline__ floatx16 mma(f16x8 a, f16x8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Adjoint, split precision, 256 x 256 pixel tile, eight waves of 128 (i) x 64
+// (j): the pipeline of k_adjoint_h16s on 32 x 32 x 16 products.  A step's
+// contraction length 32 (16 visibilities, real then imaginary parts) is two
+// 16-long slices; per slice each wave contracts four 32-row P tiles with two
+// 32-column E tiles, three products each (48 matrix instructions per step).
+template <typename H>
+__global__ __launch_bounds__(512, 1) void k_adjoint_h16m(const AdjItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const double2 *__restrict__ coef,
+                                                         const float *__restrict__ w,
+                                                         const double *__restrict__ vispart,
+                                                         const int *__restrict__ vis_base,
+                                                         float *__restrict__ gpart, int n, int np) {
+    typedef typename Half16<H>::h8 h8;
+    constexpr int TT = 256;
+    constexpr int KV = 16;         // visibilities per step
+    constexpr int KP = 2 * KV;     // contraction length per step (re, im)
+    constexpr int NX = 4;          // 32-row P tiles per wave (128 rows)
+    constexpr int NY = 2;          // 32-column E tiles per wave (64 columns)
+    constexpr int TR = KV + 2;     // table row stride in float2 (16-byte aligned rows)
+    // operands: [buffer][hi, lo][row: P 0-255, E 256-511][KP], 16-byte
+    // chunks XOR-swizzled by (row >> 1) & 3
+    __shared__ __attribute__((aligned(16))) H sOp[2][2][2 * TT][KP];
+    // tables: [buffer][axis: v (P side), u (E side)][fine, coarse][index][k]
+    __shared__ __attribute__((aligned(16))) float2 sTab[2][2][2][16][TR];
+    __shared__ double sRed[8];
+    auto swz = [](int r, int c) { return 8 * (c ^ ((r >> 1) & 3)); };
+
+    const AdjItem it = items[blockIdx.x];
+    const int i0 = it.ti * TT, j0 = it.tj * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, hk = lane >> 5;
+    const int wi = (wave >> 2) * 128, wj = (wave & 3) * 64;
+    const int half = n / 2;
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        double m = 0.0;
+        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 512)
+            m = fmax(m, vispart[(size_t)x * NPART + 2]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sRed[wave] = m;
+        __syncthreads();
+        m = sRed[0];
+#pragma unroll
+        for (int x = 1; x < 8; ++x) m = fmax(m, sRed[x]);
+        scale = pow2_scale((float)m);
+    }
+
+    // table task: axis tax (0: v / P side, 1: u / E side), index tix, visibility tk of the step
+    const int tax = tid >> 8, tix = (tid >> 4) & 15, tk = tid & 15;
+    const double *xsrc = tax == 0 ? b : a;
+    const int origin = (tax == 0 ? i0 : j0) + tix - half;
+    struct Pre {
+        double x;
+        double2 c;
+        float w;
+    };
+    auto fetch = [&](long long kb, Pre &p) {
+        const long long k = kb + tk;
+        p.x = 0.0;
+        p.c = make_double2(0.0, 0.0);
+        p.w = 0.f;
+        if (k < it.kend) {
+            p.x = xsrc[k];
+            if (tax == 0) {
+                p.c = coef[k];
+                p.w = w ? w[k] : 1.f;
+            }
+        }
+    };
+    // fine[idx][k] = conj(s w_k c_k E(b_k (i0 + idx - N/2))) or E(a_k (j0 + idx - N/2));
+    // coarse[idx][k] = conj E(16 b_k idx) or E(16 a_k idx)   (E(x) = exp(2 pi i x))
+    auto gen = [&](int tb, const Pre &p) {
+        float c, sn;
+        cis2pi_hw((float)phase(p.x, origin), c, sn);
+        float2 fine;
+        if (tax == 0) {
+            const float cr = scale * (float)((double)p.w * p.c.x);
+            const float ci = scale * (float)((double)p.w * p.c.y);
+            fine = make_float2(cr * c - ci * sn, -(cr * sn + ci * c));
+        } else {
+            fine = make_float2(c, sn);
+        }
+        sTab[tb][tax][0][tix][tk] = fine;
+        cis2pi_hw((float)phase(p.x, 16 * tix), c, sn);
+        sTab[tb][tax][1][tix][tk] = make_float2(c, tax == 0 ? -sn : sn);
+    };
+    // operand row of this thread: side fside (0: P, 1: E), row frow of that side
+    const int fside = tid >> 8, frow = tid & 255;
+    const int fq = frow & 15, ft = frow >> 4;
+    const int orow = fside * TT + frow;
+    // half a row: visibilities 8 hv .. 8 hv + 7, both parts (chunks hv and 2 + hv)
+    auto form_half = [&](int tb, int ob, int hv) {
+        const float2 *fr = &sTab[tb][fside][0][fq][8 * hv];
+        const float2 *cr = &sTab[tb][fside][1][ft][8 * hv];
+        float re[8], im[8];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const float4 f2 = *reinterpret_cast<const float4 *>(fr + e);
+            const float4 c2 = *reinterpret_cast<const float4 *>(cr + e);
+            re[e] = f2.x * c2.x - f2.y * c2.y;
+            im[e] = f2.x * c2.y + f2.y * c2.x;
+            re[e + 1] = f2.z * c2.z - f2.w * c2.w;
+            im[e + 1] = f2.z * c2.w + f2.w * c2.z;
+        }
+        h8 rh, rl, ih, il;
+        split8<H>(re, rh, rl);
+        split8<H>(im, ih, il);
+        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, hv)]) = rh;
+        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, hv)]) = rl;
+        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, 2 + hv)]) = ih;
+        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, 2 + hv)]) = il;
+    };
+
+    floatx16 acc[NX][NY];
+#pragma unroll
+    for (int x = 0; x < NX; ++x)
+#pragma unroll
+        for (int y = 0; y < NY; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+
+    const long long kb0 = it.kbeg;
+    const int nsteps = (int)((it.kend - it.kbeg + KV - 1) / KV);
+    Pre pre;
+    fetch(kb0, pre);
+    gen(0, pre);
+    fetch(kb0 + KV, pre);
+    __syncthreads();
+    form_half(0, 0, 0);
+    form_half(0, 0, 1);
+    gen(1, pre);
+    __syncthreads();
+    // One basic block per step (no branches): the operand rows of step s + 1
+    // and the tables of step s + 2 are formed between the matrix
+    // instructions of step s.  In the last steps they form rows from stale
+    // tables or zero data into buffers that are never read again.
+    for (int s = 0; s < nsteps; ++s) {
+        const int ob = s & 1;
+        fetch(kb0 + (long long)(s + 2) * KV, pre);
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const int ck = 2 * sl + hk;     // this lane's 8-element chunk of the slice
+            h8 eh[NY], el[NY];
+#pragma unroll
+            for (int y = 0; y < NY; ++y) {
+                const int r = TT + wj + 32 * y + l32;
+                eh[y] = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, ck)]);
+                el[y] = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, ck)]);
+            }
+#pragma unroll
+            for (int x = 0; x < NX; ++x) {
+                const int r = wi + 32 * x + l32;
+                const h8 ph = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, ck)]);
+                const h8 pl = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, ck)]);
+#pragma unroll
+                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(ph, eh[y], acc[x][y]);
+#pragma unroll
+                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(ph, el[y], acc[x][y]);
+#pragma unroll
+                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(pl, eh[y], acc[x][y]);
+                if (sl == 0 && x == 1) form_half(ob ^ 1, ob ^ 1, 0);
+                if (sl == 1 && x == 0) gen(ob, pre);
+                if (sl == 1 && x == 2) form_half(ob ^ 1, ob ^ 1, 1);
+            }
+        }
+        __syncthreads();
+    }
+    float *out = gpart + (size_t)it.slot * np * np;
+    const float inv = 1.f / scale;   // a power of two: exact
+#pragma unroll
+    for (int x = 0; x < NX; ++x)
+#pragma unroll
+        for (int y = 0; y < NY; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = i0 + wi + 32 * x + 8 * (r >> 2) + 4 * hk + (r & 3);
+                const int j = j0 + wj + 32 * y + l32;
+                out[(size_t)i * np + j] = acc[x][y][r] * inv;
+            }
+}
+
+// Forward, split precision, persistent, 32 x 32 x 16 products.  As
+// k_forward_h16p, a workgroup of eight waves holds an IB x JB image block
+// (hi and lo halves, fp16 scaled by a power of two to the block maximum) in
+// LDS and streams visibility tiles through its waves, here 32 visibilities
+// per wave tile.  The image rows are the A operand and the twiddles the B
+// operand, so the products come out transposed, T[k][i] in D[i][k]: lane l
+// holds visibility l % 32 of the tile for 16 rows of each 32-row tile.  Per
+// 16-column step the lane forms its eight twiddles E(a_k (j - N/2)) from a
+// coarse factor and eight fine ones (hardware sin/cos of FP64-reduced
+// phases) and splits them; then the row dot
+//   V_k = sum_i conj E(b_k (i - N/2)) T[k][i]
+// is summed in the lane over its 64 rows with the row factor split as
+// E(b_k (i0 - N/2 + 4 h)) E(b_k r) E(8 b_k a) E(32 b_k t) (h = l / 32, row
+// 32 t + 8 a + 4 h + r), and the two lanes of a visibility are added.
+template <typename H, int IB, int JB>
+__global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restrict__ items,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ b,
+                                                         const float *__restrict__ bop,
+                                                         double2 *__restrict__ vpart, int n, int np,
+                                                         long long ztot) {
+    typedef typename Half16<H>::h8 h8;
+    constexpr int NT = IB / 32;        // 32-row tiles of the block
+    constexpr int KSTEPS = JB / 16;
+    constexpr int NCG = JB / 8;
+    constexpr int SWM = NCG >= 16 ? 15 : NCG - 1;
+    __shared__ __attribute__((aligned(16))) H sH[IB][JB];
+    __shared__ __attribute__((aligned(16))) H sL[IB][JB];
+    __shared__ float sMax[8];
+
+    const FwdPItem it = items[blockIdx.x];
+    const int i0 = it.ib * IB, j0 = it.jb * JB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, hk = lane >> 5;
+    const int half = n / 2;
+    const float *Bc = bop + (size_t)it.chan * np * np;
+    constexpr int VROW = JB / 4;
+    float scale = 1.f;
+    if constexpr (Half16<H>::scaled) {
+        float m = 0.f;
+        for (int x = tid; x < IB * VROW; x += 512) {
+            const int row = x / VROW, c4 = x % VROW;
+            const float4 v = *reinterpret_cast<const float4 *>(Bc + (size_t)(i0 + row) * np + j0 + 4 * c4);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (lane == 0) sMax[wave] = m;
+        __syncthreads();
+        m = sMax[0];
+#pragma unroll
+        for (int x = 1; x < 8; ++x) m = fmaxf(m, sMax[x]);
+        scale = pow2_scale(m);
+    }
+    for (int x = tid; x < IB * NCG; x += 512) {
+        const int row = x / NCG, cg = x % NCG;
+        const float *src = Bc + (size_t)(i0 + row) * np + j0 + 8 * cg;
+        const float4 v0 = *reinterpret_cast<const float4 *>(src);
+        const float4 v1 = *reinterpret_cast<const float4 *>(src + 4);
+        const float vv[8] = {v0.x * scale, v0.y * scale, v0.z * scale, v0.w * scale,
+                             v1.x * scale, v1.y * scale, v1.z * scale, v1.w * scale};
+        h8 hv, lv;
+        split8<H>(vv, hv, lv);
+        const int o = 8 * (cg ^ (row & SWM));
+        *reinterpret_cast<h8 *>(&sH[row][o]) = hv;
+        *reinterpret_cast<h8 *>(&sL[row][o]) = lv;
+    }
+    __syncthreads();
+    const double unscale = 1.0 / (double)scale;
+    constexpr int TV = 32;
+    const long long nk = it.kend - it.kbeg;
+    const long long ntiles = (nk + TV - 1) / TV;
+    // tile wave * nwg + wg of each round: a round's leftover tiles go to one
+    // wave of distinct workgroups, so no CU carries them on all its SIMDs
+    const long long stride = 8LL * it.nwg;
+    for (long long tile = (long long)wave * it.nwg + it.wg; tile < ntiles; tile += stride) {
+        const long long k0 = it.kbeg + TV * tile;
+        const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
+        const bool ok = l32 < nvalid;
+        const double ak = ok ? a[k0 + l32] : 0.0;
+        const double bk = ok ? b[k0 + l32] : 0.0;
+        float fc[8], fs[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
+        floatx16 accR[NT], accI[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                accR[t][r] = 0.f;
+                accI[t][r] = 0.f;
+            }
+#pragma unroll 2
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            // twiddles of columns j0 + 16 ks + 8 h + e: E(a_k (j0 + 16 ks + 8 h - N/2)) E(a_k e)
+            float cc, sc;
+            cis2pi_hw((float)phase(ak, j0 + 16 * ks + 8 * hk - half), cc, sc);
+            float cv[8], nsv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                cv[e] = cc * fc[e] - sc * fs[e];
+                nsv[e] = -(sc * fc[e] + cc * fs[e]);
+            }
+            h8 th, tl, uh, ul;
+            split8<H>(cv, th, tl);
+            split8<H>(nsv, uh, ul);
+            const int o = 8 * ((2 * ks + hk) ^ (l32 & SWM));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const h8 bh = *reinterpret_cast<const h8 *>(&sH[32 * t + l32][o]);
+                const h8 bl = *reinterpret_cast<const h8 *>(&sL[32 * t + l32][o]);
+                accR[t] = Half32<H>::mma(bh, th, accR[t]);
+                accI[t] = Half32<H>::mma(bh, uh, accI[t]);
+                accR[t] = Half32<H>::mma(bh, tl, accR[t]);
+                accI[t] = Half32<H>::mma(bh, ul, accI[t]);
+                accR[t] = Half32<H>::mma(bl, th, accR[t]);
+                accI[t] = Half32<H>::mma(bl, uh, accI[t]);
+            }
+        }
+        // row dot of the lane's visibility over its 64 rows
+        float f1c[4], f1s[4], f2c[4], f2s[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cis2pi_hw((float)phase(bk, r), f1c[r], f1s[r]);
+            cis2pi_hw((float)phase(bk, 8 * r), f2c[r], f2s[r]);
+        }
+        float c32, s32, cb, sb;
+        cis2pi_hw((float)phase(bk, 32), c32, s32);
+        cis2pi_hw((float)phase(bk, i0 + 4 * hk - half), cb, sb);
+        // W = sum_t conj(E(32 b_k))^t W_t by Horner's rule, W_t = sum_a conj
+        // E(8 b_k a) sum_r conj E(b_k r) T_t[4 a + r]
+        float wr = 0.f, wi = 0.f;
+#pragma unroll
+        for (int t = NT - 1; t >= 0; --t) {
+            float tr = 0.f, ti = 0.f;
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+                float ur = 0.f, ui = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float xr = accR[t][4 * aa + r], xi = accI[t][4 * aa + r];
+                    ur += f1c[r] * xr + f1s[r] * xi;
+                    ui += f1c[r] * xi - f1s[r] * xr;
+                }
+                tr += f2c[aa] * ur + f2s[aa] * ui;
+                ti += f2c[aa] * ui - f2s[aa] * ur;
+            }
+            const float nr = tr + c32 * wr + s32 * wi;
+            wi = ti + c32 * wi - s32 * wr;
+            wr = nr;
+        }
+        double vr = (double)(cb * wr + sb * wi), vi = (double)(cb * wi - sb * wr);
+        vr += __shfl_xor(vr, 32, 64);
+        vi += __shfl_xor(vi, 32, 64);
+        if (hk == 0 && ok) vpart[(size_t)it.part * ztot + k0 + l32] = make_double2(vr * unscale, vi * unscale);
+    }
+}
+
 template <typename T>
 hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st, const FwdPItem *items, int nitems) {
     if (nitems == 0) return hipSuccess;
@@ -1284,6 +1852,17 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
 template <typename H, int NV>
 hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st, const FwdPItem *items, int nitems) {
     const dim3 grid(nitems), blk(512);
+    static const bool old16 = std::getenv("UVMEM_SPLIT_FWD_16") != nullptr;
+    if (!old16 && c->ib_rows == 128 && c->jb_cols == 256) {
+        hipLaunchKernelGGL((k_forward_h16m<H, 128, 256>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+        return hipGetLastError();
+    }
+    if (!old16 && c->ib_rows == 128 && c->jb_cols == 128) {
+        hipLaunchKernelGGL((k_forward_h16m<H, 128, 128>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
+                           c->d_vpart, c->n, c->np, (long long)c->ztot);
+        return hipGetLastError();
+    }
     if (c->ib_rows == 128 && c->jb_cols == 256)
         hipLaunchKernelGGL((k_forward_h16p<H, 128, 256, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
@@ -1308,8 +1887,16 @@ template <typename H>
 hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, const AdjItem *items,
                    int nitems) {
     if (nitems == 0) return hipSuccess;
-    if (c->adj_tt == 256)
+    static const bool old_split = std::getenv("UVMEM_SPLIT_ADJ_W") != nullptr;
+    static const bool m32_split = std::getenv("UVMEM_SPLIT_ADJ_M") != nullptr;
+    if (c->adj_tt == 256 && m32_split)
+        hipLaunchKernelGGL((k_adjoint_h16m<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
+                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
+    else if (c->adj_tt == 256 && old_split)
         hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
+                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
+    else if (c->adj_tt == 256)
+        hipLaunchKernelGGL((k_adjoint_h16s<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else if (c->adj_tt == 128)
         hipLaunchKernelGGL((k_adjoint_h16<H, 64>), dim3(nitems), dim3(256), 0, st, items, c->d_a, c->d_b,
@@ -1321,6 +1908,22 @@ hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipS
 }
 
 }  // namespace
+
+hipError_t launch_forward_f32_raw(int ib_rows, int jb_cols, const FwdPItem *items, int nitems, const double *a,
+                                  const double *b, const float *bop, double2 *vpart, int n, int np,
+                                  long long ztot, hipStream_t st) {
+    if (nitems == 0) return hipSuccess;
+    const dim3 grid(nitems), blk(512);
+    if (ib_rows == 128 && jb_cols == 256)
+        hipLaunchKernelGGL((k_forward_p<float, 128, 256>), grid, blk, 0, st, items, a, b, bop, vpart, n, np, ztot);
+    else if (ib_rows == 128 && jb_cols == 128)
+        hipLaunchKernelGGL((k_forward_p<float, 128, 128>), grid, blk, 0, st, items, a, b, bop, vpart, n, np, ztot);
+    else if (ib_rows == 64 && jb_cols == 64)
+        hipLaunchKernelGGL((k_forward_p<float, 64, 64>), grid, blk, 0, st, items, a, b, bop, vpart, n, np, ztot);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st, int dir) {
     if (c->fwd_model == UVMEM_FWD_GRIDDED) return launch_grid_forward(c, bop, st);
