@@ -61,7 +61,9 @@ typedef enum uvmem_status {
     UVMEM_ENOMEM = -2,   /* device or host allocation failed                  */
     UVMEM_EDEVICE = -3,  /* a HIP runtime call failed                         */
     UVMEM_EDOMAIN = -4,  /* an image pixel was <= 0 or NaN (from uvmem_check) */
-    UVMEM_ESTATE = -5    /* call out of order (e.g. set_* after finalize)     */
+    UVMEM_ESTATE = -5,   /* call out of order (e.g. set_* after finalize)     */
+    UVMEM_ETOOBIG = -6   /* sizes need more than an allocation-free entry
+                            point's fixed scratch (UVMEM_NOALLOC_SCRATCH_BYTES) */
 } uvmem_status;
 
 /* Precision of the DFT contractions (the chi^2, entropy and line-search sums
@@ -268,6 +270,32 @@ int uvmem_timing_read(uvmem_ctx *ctx, int which, double *total_ms, int64_t *coun
  * visibility arrays and its count. */
 int uvmem_info(const uvmem_ctx *ctx, int64_t *out, int nout);
 int uvmem_chan_range(const uvmem_ctx *ctx, int chan, int64_t *offset, int64_t *nvis);
+
+/* Allocation-free forward model, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result as uvmem_forward of an FP32 context with
+ * one channel whose beam image is `beam`, on the same FP32 matrix-core
+ * kernels, but without a context:
+ *   vis_k = sum_ij A_ij I_ij exp(-2 pi i (u_k x_j + v_k y_i)),
+ * x_j = (j - n/2) cell_rad, y_i = (i - n/2) cell_rad.
+ * Arguments: n even in [2, 8192]; nvis >= 0; u, v: device double[nvis]
+ * (wavelengths; not validated -- non-finite values or |u| cell_rad, |v|
+ * cell_rad beyond 4096 cycles per pixel give meaningless visibilities);
+ * beam: device float[n][n] or NULL (A = 1); I: device float[n][n]; vis:
+ * device double[nvis][2] (re, im), written; hip_stream: a hipStream_t of the
+ * current device (NULL = null stream).  Enqueues on hip_stream and returns
+ * without synchronising; calls no allocating routine.  Scratch: one fixed
+ * device array of UVMEM_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends, shared by every call on that GPU -- calls that overlap on
+ * one GPU (different streams, or host threads) race; calls on one stream
+ * are ordered.  Returns UVMEM_EINVAL for bad sizes or null pointers,
+ * UVMEM_ETOOBIG when the sizes need more than the scratch
+ * (8 nvis + 8 nvis + 4 Np^2 + 16 nvis B Np^2 / (IB JB) + tables, each part
+ * rounded up to 256 bytes; Np = n rounded up to a multiple of 64, IB x JB =
+ * 128 x 256, 128 x 128 or 64 x 64 by Np), UVMEM_EDEVICE on a launch error. */
+#define UVMEM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int uvmem_forward_noalloc(int n, double cell_rad, int64_t nvis, const double *u_dev, const double *v_dev,
+                          const float *beam_dev, const float *I_dev, double *vis_dev, void *hip_stream);
 
 const char *uvmem_last_error(const uvmem_ctx *ctx);
 const char *uvmem_strerror(int code);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libuvmem.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "k_dft.hip", "k_aux.hip", "k_grid.hip"]
+SOURCES = ["api.hip", "k_dft.hip", "k_aux.hip", "k_grid.hip", "noalloc.hip"]
 ARCH = os.environ.get("UVMEM_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

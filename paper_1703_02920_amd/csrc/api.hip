@@ -246,6 +246,7 @@ const char *uvmem_strerror(int code) {
     case UVMEM_EDEVICE: return "HIP runtime error";
     case UVMEM_EDOMAIN: return "image pixel <= 0 or NaN";
     case UVMEM_ESTATE: return "call out of order";
+    case UVMEM_ETOOBIG: return "sizes exceed the allocation-free scratch";
     default: return "unknown status";
     }
 }

@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuvmem.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EDOMAIN, ESTATE, ETOOBIG = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 MODES = {"cube": 0, "shared": 1}
 FORWARD_MODELS = {"dft": 0, "gridded": 1}
@@ -31,7 +31,7 @@ SYMBOLS = [
     "uvmem_cg_init", "uvmem_cg_step", "uvmem_cg_run", "uvmem_cg_get_state", "uvmem_cg_set_state",
     "uvmem_set_mask", "uvmem_dirty_image", "uvmem_noise", "uvmem_fit_beam",
     "uvmem_check", "uvmem_timing_enable", "uvmem_timing_read", "uvmem_info", "uvmem_chan_range",
-    "uvmem_last_error", "uvmem_strerror",
+    "uvmem_last_error", "uvmem_strerror", "uvmem_forward_noalloc",
 ]
 
 _lib = None
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
         "uvmem_timing_read": [vp, ci, ctypes.POINTER(dbl), ctypes.POINTER(i64), ci],
         "uvmem_info": [vp, ctypes.POINTER(i64), ci],
         "uvmem_chan_range": [vp, ci, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "uvmem_forward_noalloc": [ci, dbl, i64, vp, vp, vp, vp, vp, vp],
         "uvmem_last_error": [vp],
         "uvmem_strerror": [ci],
     }
@@ -383,6 +384,37 @@ class Context:
         ms, cnt = ctypes.c_double(), ctypes.c_int64()
         self._call("uvmem_timing_read", int(which), ctypes.byref(ms), ctypes.byref(cnt), 1 if reset else 0)
         return float(ms.value), int(cnt.value)
+
+
+def forward_noalloc(n: int, cell: float, u: torch.Tensor, v: torch.Tensor, I: torch.Tensor,
+                    beam: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """uvmem_forward_noalloc: model visibilities of the FP32 image I (n x n)
+    through the beam image `beam` (None: A = 1), without a context and
+    without allocating on the library side; u, v are float64 device tensors
+    in wavelengths.  Returns `out` (complex128, len(u); allocated here by
+    torch when not given)."""
+    L = load()
+    nvis = int(u.numel())
+    for name, t, dt in (("u", u, torch.float64), ("v", v, torch.float64), ("I", I, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+    if v.numel() != nvis or I.numel() != n * n:
+        raise ValueError("v must match u; I must have n * n elements")
+    if beam is not None and (beam.dtype != torch.float32 or not beam.is_cuda or not beam.is_contiguous()
+                             or beam.numel() != n * n):
+        raise ValueError("beam must be a contiguous float32 n x n device tensor")
+    if out is None:
+        out = torch.empty(max(nvis, 1), dtype=torch.complex128, device=I.device)[:nvis]
+    elif out.dtype != torch.complex128 or out.numel() != nvis or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex128 tensor of len(u) elements")
+    st = stream if stream is not None else torch.cuda.current_stream(I.device)
+    code = L.uvmem_forward_noalloc(int(n), float(cell), nvis, _ptr(u), _ptr(v),
+                                   _ptr(beam) if beam is not None else None, _ptr(I),
+                                   _ptr(out) if nvis else None, ctypes.c_void_p(st.cuda_stream))
+    if code != OK:
+        raise UvmemError(code, L.uvmem_strerror(code).decode())
+    return out
 
 
 class PhiFunction(torch.autograd.Function):
