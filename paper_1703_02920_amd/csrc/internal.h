@@ -26,19 +26,20 @@ constexpr int ADJ_KMIN = 256;
 constexpr int ADJ_KMAX_SPLIT = 32768;
 // visibilities per FP32 sum of the 256-tile FP32 adjoint before it is folded
 // into FP64 (and the chunk length up to which its partials stay FP32)
-constexpr int ADJ_F32_SUM = 2048;
+constexpr int ADJ_F32_SUM = 8192;
 // Partial-sum slots per pixel / visibility item.
-constexpr int NPART = 8;
-// Trial steps evaluated per line-search pass.
-constexpr int LS_K = 4;
+constexpr int NPART = 16;
+// Trial steps evaluated per line-search pass (two partials each).
+constexpr int LS_K = 8;
 // Relative tolerance that decides "pixel at the bound I <= M (1 + tol)".
 constexpr double BOUND_TOL = 1e-12;
 // Gridded model: cells holding more visibilities than this are reduced by a
 // wave each before the node gather (bounds the gather's serial loops).
 constexpr int GRID_DENSE = 16;
-// Default number of line-search passes per CG step; a channel whose search
-// has converged skips the remaining passes.
-constexpr int LS_STEPS = 4;
+// Default number of line-search passes per CG step after the start in the
+// direction's visibility pass (which already settles a step that reaches
+// alpha_max); a channel whose search has converged skips the remaining passes.
+constexpr int LS_STEPS = 3;
 
 // One workgroup of the persistent split-precision forward model: image block
 // (ib, jb) of a channel resident in LDS; the workgroup is number `wg` of the
@@ -77,18 +78,20 @@ struct VisItem {
 enum {
     LSS_PHASE = 0,   // 0 = searching, 3 = done
     LSS_LO,          // largest step known to have phi' < 0
-    LSS_HI,          // bracket end (< 0 means +infinity)
+    LSS_HI,          // bracket end with phi'(HI) >= 0 (< 0 means +infinity)
     LSS_FLO, LSS_HLO,   // phi', phi'' at LO
     LSS_FHI, LSS_HHI,   // phi', phi'' at HI (when HI_EVAL)
     LSS_HI_EVAL,     // 1 once phi'(HI) > 0 is known
     LSS_T0,          // LS_K trial steps (ascending) evaluated by the next pass
-    LSS_ALPHA = LSS_T0 + 4,   // accepted step once done
+    LSS_ALPHA = LSS_T0 + LS_K,   // accepted step once done
     LSS_A,           // sum w |Vd|^2
     LSS_B,           // sum w Re(conj(R) Vd)
     LSS_AMAX,        // alpha_max (< 0 means +infinity)
     LSS_STOP,        // 1 if the channel has stopped
     LSS_N = 24
 };
+static_assert(LSS_STOP < LSS_N, "line-search state overflows its record");
+static_assert(2 * LS_K <= NPART, "line-search partials overflow a partial record");
 
 // Per-image flags / CG bookkeeping kept on the device (double).
 enum {
@@ -108,7 +111,7 @@ enum {
 enum {
     CTR_DIR = 0,     // k_cg_dir: gt . d
     CTR_DIR2,        // k_cg_dir2: alpha_max and the entropy parts of phi', phi''
-    CTR_VIS,         // k_vis (direction): a, b; line-search start
+    CTR_VIS,         // k_cg_vis: a, b, phi'(alpha_max); line-search start
     CTR_LS,          // k_ls_step: phi', phi'' at the trial steps
     CTR_UPD,         // k_cg_update: S and chi^2 of the new image
     CTR_GRAD,        // k_grad: the Polak-Ribiere sums / Phi of an evaluation

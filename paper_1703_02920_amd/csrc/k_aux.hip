@@ -48,6 +48,17 @@ __device__ __forceinline__ double block_min(double v) {
     return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
+// Partial records are written and read at device coherence (relaxed
+// agent-scope atomic stores and loads: they bypass the caches that are not
+// coherent between the chiplets), so that the workgroup that finishes a
+// reduction in the same launch reads every other workgroup's record.
+__device__ __forceinline__ void coh_store(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coh_load(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Sum slot `s` (K slots starting at s0) of n_items partial records of NPART
 // doubles starting at `base`, in index order (strided per thread, then the
 // fixed workgroup reduction).
@@ -57,38 +68,40 @@ __device__ __forceinline__ void sum_partials(const double *base, int n_items, in
     for (int x = 0; x < K; ++x) out[x] = 0.0;
     for (int it = threadIdx.x; it < n_items; it += NTHR) {
 #pragma unroll
-        for (int x = 0; x < K; ++x) out[x] += base[(size_t)it * NPART + s0 + x];
+        for (int x = 0; x < K; ++x) out[x] += coh_load(base + (size_t)it * NPART + s0 + x);
     }
     block_sum<K>(out);
 }
 
 __device__ __forceinline__ double min_partials(const double *base, int n_items, int s) {
     double m = INFINITY;
-    for (int it = threadIdx.x; it < n_items; it += NTHR) m = fmin(m, base[(size_t)it * NPART + s]);
+    for (int it = threadIdx.x; it < n_items; it += NTHR) m = fmin(m, coh_load(base + (size_t)it * NPART + s));
     return block_min(m);
 }
 
 // Arrival at the end of a partial-sum pass, once thread 0 has stored this
-// workgroup's partial record: returns true (in every thread) in exactly one
-// workgroup per image and launch, the last to arrive at `ctr`, which may then
-// read every record of the image and finish the image's reduction in a fixed
-// order.  The counter only elects that workgroup (the sums never depend on
-// arrival order) and is left at zero for the next launch; no workgroup waits
-// for another.
+// workgroup's partial record (coh_store): returns true (in every thread) in
+// exactly one workgroup per image and launch, the last to arrive at `ctr`,
+// which may then read every record of the image (coh_load) and finish the
+// image's reduction in a fixed order.  Thread 0 waits for its record's store
+// to complete before it counts itself in, so the last arrival finds every
+// record in place.  The counter only elects that workgroup (the sums never
+// depend on arrival order) and is left at zero for the next launch; no
+// workgroup waits for another.
 __device__ __forceinline__ bool arrive_last(unsigned *ctr, unsigned expected) {
     __shared__ unsigned s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();   // this workgroup's record before its arrival
-        const unsigned t = atomicAdd(ctr, 1u);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);   // this workgroup's record stored
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const unsigned t = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool last = t + 1 == expected;
-        if (last) atomicExch(ctr, 0u);
+        if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = last ? 1u : 0u;
     }
     __syncthreads();
-    if (s_last == 0) return false;
-    __threadfence();       // every other record after the last arrival
-    return true;
+    return s_last != 0;
 }
 
 // ---------------------------------------------------------------- fill
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(NTHR) void k_prologue(const R *__restrict__ I, cons
     if (with_entropy) {
         if (bad) atomicOr(flag, 1);
         block_sum<1>(s);
-        if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = s[0];
+        if (threadIdx.x == 0) coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 0, s[0]);
     }
 }
 
@@ -202,44 +215,31 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
     if (mode != 0 && mode != 4) {
         block_sum<2>(acc);
         if (threadIdx.x == 0) {
-            vispart[(size_t)item * NPART + 0] = acc[0];
-            vispart[(size_t)item * NPART + 1] = acc[1];
+            coh_store(vispart + (size_t)item * NPART + 0, acc[0]);
+            coh_store(vispart + (size_t)item * NPART + 1, acc[1]);
         }
     }
     if (with_max && mode != 0 && mode != 2) {
         cmax = -block_min(-cmax);
-        if (threadIdx.x == 0) vispart[(size_t)item * NPART + 2] = cmax;
+        if (threadIdx.x == 0) coh_store(vispart + (size_t)item * NPART + 2, cmax);
     }
 }
 
-__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop);
+__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop,
+                        bool am_eval, double f_am, double h_am);
 
-// mode 2 (the CG direction's visibilities): the last visibility workgroup of
-// an image sums a, b and starts the image's line search from them and from
-// the direction pass's totals in `chan`.
+// Visibility pass over the context's items (modes 0, 1, 3 and 4 above).
 __global__ __launch_bounds__(NTHR) void k_vis(const VisItem *__restrict__ items,
                                               const double2 *__restrict__ vpart, int n_parts, long long ztot,
                                               const double2 *__restrict__ vo, const float *__restrict__ w,
                                               double2 *__restrict__ R, double2 *__restrict__ Vd,
                                               double2 *__restrict__ out, const double *__restrict__ scal,
                                               double *__restrict__ vispart, const int *__restrict__ chan_img,
-                                              int mode, int with_max, unsigned *__restrict__ ctr,
-                                              const int *__restrict__ ivis_base, const double *__restrict__ chan,
-                                              double *__restrict__ ls, double lam) {
+                                              int mode, int with_max) {
     const VisItem it = items[blockIdx.x];
     const int img = chan_img ? chan_img[it.chan] : 0;
     const double alpha = mode == 3 ? scal[(size_t)img * UVMEM_NSCAL + UVMEM_S_ALPHA] : 0.0;
     vis_item(it, blockIdx.x, vpart, n_parts, ztot, vo, w, R, Vd, out, vispart, mode, with_max, alpha);
-    if (mode != 2) return;
-    const int v0 = ivis_base[img], v1 = ivis_base[img + 1];
-    if (!arrive_last(ctr + img, (unsigned)(v1 - v0))) return;
-    double ab[2];
-    sum_partials<2>(vispart + (size_t)v0 * NPART, v1 - v0, 0, ab);
-    if (threadIdx.x == 0) {
-        const double *ch = chan + (size_t)img * CH_N;
-        ls_init(ls + (size_t)img * LSS_N, ab[0], ab[1], lam * ch[CH_E1], lam * ch[CH_E2], ch[CH_AMAX],
-                ch[CH_STOP] != 0.0);
-    }
 }
 
 // ---------------------------------------------------------------- gradient
@@ -361,8 +361,8 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
     if (mode == 2) {
         block_sum<2>(acc);
         if (threadIdx.x == 0) {
-            ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
-            ppart[((size_t)c * n_pb + pb) * NPART + 1] = acc[1];
+            coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 0, acc[0]);
+            coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 1, acc[1]);
         }
     }
     if ((mode != 1 && mode != 2) || !arrive_last(tail.ctr + c, (unsigned)n_pb)) return;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const
         acc[0] += gn * gn;
     }
     block_sum<1>(acc);
-    if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
+    if (threadIdx.x == 0) coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 0, acc[0]);
     if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double gg[1];
     sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gg);
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         acc[0] += gtv * (double)dr;
     }
     block_sum<1>(acc);
-    if (threadIdx.x == 0) ppart[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
+    if (threadIdx.x == 0) coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 0, acc[0]);
     if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double gtd[1];
     sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
@@ -532,9 +532,9 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
     block_sum<2>(acc);
     if (threadIdx.x == 0) {
         double *pp = ppart + ((size_t)c * n_pb + pb) * NPART;
-        pp[0] = acc[0];
-        pp[1] = acc[1];
-        pp[2] = amax;
+        coh_store(pp + 0, acc[0]);
+        coh_store(pp + 1, acc[1]);
+        coh_store(pp + 2, amax);
     }
     if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double e[2];
@@ -547,20 +547,29 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const
         ch[CH_AMAX] = am;
         // no visibility workgroup will start this image's line search
         if (ivis_base[c + 1] == ivis_base[c])
-            ls_init(ls + (size_t)c * LSS_N, 0.0, 0.0, lam * e[0], lam * e[1], am, ch[CH_STOP] != 0.0);
+            ls_init(ls + (size_t)c * LSS_N, 0.0, 0.0, lam * e[0], lam * e[1], am, ch[CH_STOP] != 0.0, false, 0.0,
+                    0.0);
     }
 }
 
 // ---- line search: exact minimisation of the convex phi on [0, alpha_max]
 //   phi'(al)  = b + a al + lambda sum d (ln((I + al d)/M) + 1)
 //   phi''(al) = a + lambda sum d^2 / (I + al d)
-// phi' is increasing; its entropy part is concave (log-like), so a single
-// Newton sequence from the left creeps.  Each pass evaluates phi', phi'' at
-// LS_K trial steps inside the current bracket [LO, HI] -- Newton steps from
-// both ends, the secant step and fill-in points, or a geometric ladder while
-// HI is unbounded -- and keeps the smallest bracket.  The state is advanced
-// identically by every workgroup of the channel.
+// The entropy part of phi' increases with al, so phi'(al) >= phi'(0) + a al
+// and the minimiser lies below -phi'(0)/a: that bounds a search without
+// alpha_max.  The start knows phi', phi'' at 0 and, from the direction's
+// visibility pass, at alpha_max, which settles a step that reaches alpha_max
+// without any pass.  Each pass evaluates phi', phi'' at LS_K trial steps
+// inside the bracket [LO, HI] and keeps the smallest bracket.  With HI
+// evaluated the trials are the root of the cubic Hermite interpolant of phi'
+// on the bracket, the Newton steps from both ends, the secant step and points
+// 1e-3 and 1e-6 of the bracket either side of the cubic's root; with HI an
+// unevaluated bound, a geometric ladder from the Newton step to HI; with no
+// bound, factors of 4 from the Newton step.  A bracket narrowed to 1e-13 (or
+// the last pass) accepts the cubic's root.  The state is advanced identically
+// by every workgroup of the channel.
 enum { PH_SEARCH = 0, PH_DONE = 3 };
+static_assert(LS_K == 8, "the bracket proposal fills eight trial steps");
 
 __device__ __forceinline__ void ls_finish(double *st, double al) {
     st[LSS_PHASE] = PH_DONE;
@@ -569,38 +578,62 @@ __device__ __forceinline__ void ls_finish(double *st, double al) {
     for (int m = 0; m < LS_K; ++m) st[LSS_T0 + m] = al;
 }
 
+// Root in [lo, hi] of the cubic Hermite interpolant p of phi' from its values
+// f0 < 0 < f1 and slopes h0, h1 at the ends, by Newton's method on the unit
+// parameter s of the bracket, safeguarded by bisection of the sub-bracket on
+// which p changes sign.
+__device__ double hermite_root(double lo, double hi, double f0, double f1, double h0, double h1) {
+    const double w = hi - lo, d0 = h0 * w, d1 = h1 * w;
+    double sl = 0.0, sh = 1.0;
+    double s = f0 / (f0 - f1);
+    if (!(s > 0.0 && s < 1.0)) s = 0.5;
+    for (int it = 0; it < 64; ++it) {
+        const double s2 = s * s, s3 = s2 * s;
+        const double p = (2.0 * s3 - 3.0 * s2 + 1.0) * f0 + (s3 - 2.0 * s2 + s) * d0 + (3.0 * s2 - 2.0 * s3) * f1 +
+                         (s3 - s2) * d1;
+        if (p == 0.0) break;
+        if (p < 0.0) sl = s;
+        else sh = s;
+        const double dp = 6.0 * (s2 - s) * (f0 - f1) + (3.0 * s2 - 4.0 * s + 1.0) * d0 + (3.0 * s2 - 2.0 * s) * d1;
+        double sn = dp != 0.0 ? s - p / dp : 0.5 * (sl + sh);
+        if (!(sn > sl && sn < sh)) sn = 0.5 * (sl + sh);
+        if (sn == s) break;
+        s = sn;
+    }
+    return fmin(fmax(lo + s * w, lo), hi);
+}
+
+__device__ __forceinline__ double ls_cubic(const double *st) {
+    return hermite_root(st[LSS_LO], st[LSS_HI], st[LSS_FLO], st[LSS_FHI], st[LSS_HLO], st[LSS_HHI]);
+}
+
 __device__ void ls_propose(double *st) {
     const double lo = st[LSS_LO], hi = st[LSS_HI];
     const double tn = lo - st[LSS_FLO] / st[LSS_HLO];   // > lo (FLO < 0, HLO > 0)
     double t[LS_K];
     if (hi < 0.0) {
-        const double base = (tn > lo && isfinite(tn)) ? tn : (lo > 0.0 ? 2.0 * lo : 1.0);
-        t[0] = base;
-        t[1] = 4.0 * base;
-        t[2] = 16.0 * base;
-        t[3] = 64.0 * base;
+        double x = (tn > lo && isfinite(tn)) ? tn : (lo > 0.0 ? 2.0 * lo : 1.0);
+        for (int m = 0; m < LS_K; ++m, x *= 4.0) t[m] = x;
     } else if (st[LSS_HI_EVAL] == 0.0) {
-        // alpha_max not evaluated yet: it is the last trial
         const double t0 = (tn > lo && tn < hi) ? tn : lo + 0.5 * (hi - lo);
-        t[0] = t0;
-        t[1] = t0 + (hi - t0) / 3.0;
-        t[2] = t0 + 2.0 * (hi - t0) / 3.0;
-        t[3] = hi;
+        const double r = log(hi / t0) / (LS_K - 1);
+        for (int m = 0; m < LS_K - 1; ++m) t[m] = t0 * exp(r * m);
+        t[LS_K - 1] = hi;
     } else {
         const double w = hi - lo;
-        const double th = hi - st[LSS_FHI] / st[LSS_HHI];
-        const double ts = lo - st[LSS_FLO] * w / (st[LSS_FHI] - st[LSS_FLO]);
-        double c[3] = {tn, ts, th};
-        for (int m = 0; m < 3; ++m)
-            if (!(c[m] > lo && c[m] < hi)) c[m] = lo + 0.25 * (m + 1) * w;
-        double mn = fmin(c[0], fmin(c[1], c[2])), mx = fmax(c[0], fmax(c[1], c[2]));
-        t[0] = c[0];
-        t[1] = c[1];
-        t[2] = c[2];
-        t[3] = mx > mn ? 0.5 * (mn + mx) : lo + 0.5 * w;
+        const double rc = ls_cubic(st);
+        t[0] = rc;
+        t[1] = tn;
+        t[2] = hi - st[LSS_FHI] / st[LSS_HHI];
+        t[3] = lo - st[LSS_FLO] * w / (st[LSS_FHI] - st[LSS_FLO]);
+        t[4] = rc - 1e-3 * w;
+        t[5] = rc + 1e-3 * w;
+        t[6] = rc - 1e-6 * w;
+        t[7] = rc + 1e-6 * w;
+        for (int m = 0; m < LS_K; ++m)
+            if (!(t[m] > lo && t[m] < hi)) t[m] = lo + (m + 1) * w / (LS_K + 1);
     }
-    // ascending order (insertion sort of four)
-    for (int i = 1; i < LS_K; ++i)
+    for (int i = 1; i < LS_K; ++i)   // ascending (insertion sort)
         for (int j = i; j > 0 && t[j] < t[j - 1]; --j) {
             const double x = t[j]; t[j] = t[j - 1]; t[j - 1] = x;
         }
@@ -608,9 +641,11 @@ __device__ void ls_propose(double *st) {
     for (int m = 0; m < LS_K; ++m) st[LSS_T0 + m] = t[m];
 }
 
-// Initial state from a, b, e1 = lambda sum d (ln(I/M) + 1), e2 = lambda sum
-// d^2/I (so phi'(0) = b + e1, phi''(0) = a + e2) and alpha_max.
-__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop) {
+// Start from a, b, e1 = lambda sum d (ln(I/M) + 1), e2 = lambda sum d^2/I
+// (so phi'(0) = b + e1, phi''(0) = a + e2), alpha_max and, when am_eval, the
+// entropy parts f_am, h_am of phi', phi'' at alpha_max.
+__device__ void ls_init(double *st, double a, double b, double e1, double e2, double amax, bool stop,
+                        bool am_eval, double f_am, double h_am) {
     st[LSS_A] = a;
     st[LSS_B] = b;
     st[LSS_AMAX] = isfinite(amax) ? amax : -1.0;
@@ -626,6 +661,18 @@ __device__ void ls_init(double *st, double a, double b, double e1, double e2, do
     if (stop || !(st[LSS_FLO] < 0.0) || !(st[LSS_HLO] > 0.0) || (isfinite(amax) && amax <= 0.0)) {
         ls_finish(st, 0.0);
         return;
+    }
+    if (isfinite(amax) && am_eval) {
+        const double fa = b + a * amax + f_am;
+        if (fa <= 0.0) {   // phi' <= 0 on all of [0, alpha_max]
+            ls_finish(st, amax);
+            return;
+        }
+        st[LSS_FHI] = fa;
+        st[LSS_HHI] = a + h_am;
+        st[LSS_HI_EVAL] = 1.0;
+    } else if (!isfinite(amax) && a > 0.0) {
+        st[LSS_HI] = -st[LSS_FLO] / a;
     }
     ls_propose(st);
 }
@@ -647,28 +694,24 @@ __device__ void ls_update(double *st, const double *f, const double *h) {
         st[LSS_HHI] = h[m];
         st[LSS_HI_EVAL] = 1.0;
     } else if (st[LSS_HI] >= 0.0 && st[LSS_HI_EVAL] == 0.0 && st[LSS_T0 + LS_K - 1] == st[LSS_HI]) {
-        // phi'(alpha_max) <= 0: the minimiser on [0, alpha_max] is alpha_max
+        // phi'(HI) <= 0 at an unevaluated end: HI is alpha_max, the minimiser
+        // on [0, alpha_max], or the bound -phi'(0)/a, where phi' >= 0, so the
+        // root up to rounding
         ls_finish(st, st[LSS_HI]);
         return;
     }
     const double lo = st[LSS_LO], hi = st[LSS_HI];
     if (st[LSS_HI_EVAL] != 0.0 && hi - lo <= 1e-13 * hi) {
-        const double ts = lo - st[LSS_FLO] * (hi - lo) / (st[LSS_FHI] - st[LSS_FLO]);
-        ls_finish(st, (ts >= lo && ts <= hi) ? ts : lo);
+        ls_finish(st, ls_cubic(st));
         return;
     }
     ls_propose(st);
 }
 
-// Accepted step when the pass budget ran out: the secant step of the
+// Accepted step when the pass budget ran out: the cubic's root in the
 // bracket, or the largest step known to descend.
 __device__ double ls_fallback(const double *st) {
-    const double lo = st[LSS_LO], hi = st[LSS_HI];
-    if (st[LSS_HI_EVAL] != 0.0) {
-        const double ts = lo - st[LSS_FLO] * (hi - lo) / (st[LSS_FHI] - st[LSS_FLO]);
-        if (ts >= lo && ts <= hi) return ts;
-    }
-    return lo;
+    return st[LSS_HI_EVAL] != 0.0 ? ls_cubic(st) : st[LSS_LO];
 }
 
 // Sum the LS_K (phi' entropy part, phi'' entropy part) partials of a channel
@@ -682,6 +725,65 @@ __device__ __forceinline__ void ls_eval(const double *st, const double *pp, int 
         const double t = st[LSS_T0 + m];
         f[m] = st[LSS_B] + st[LSS_A] * t + lam * e[2 * m];
         h[m] = st[LSS_A] + lam * e[2 * m + 1];
+    }
+}
+
+// Step 5: Vd and the partials of a = sum w |Vd|^2 and b = sum w Re(conj(R) Vd)
+// (the first n_visit workgroups, one visibility item each), and the entropy
+// parts of phi', phi'' at alpha_max (pixel workgroups of the images that have
+// visibilities; zero without a finite alpha_max).  The last workgroup of an
+// image starts its line search from these totals and the direction pass's.
+template <typename R>
+__global__ __launch_bounds__(NTHR) void k_cg_vis(const VisItem *__restrict__ items, int n_visit,
+                                                 const double2 *__restrict__ vpart, int n_parts, long long ztot,
+                                                 const float *__restrict__ w, double2 *__restrict__ Rv,
+                                                 double2 *__restrict__ Vd, double *__restrict__ vispart,
+                                                 const int *__restrict__ chan_img, const int *__restrict__ ivis_base,
+                                                 const R *__restrict__ I, const R *__restrict__ dir,
+                                                 double *__restrict__ ppart, int n, int n_pb, int pb_len, double M,
+                                                 double lam, const double *__restrict__ chan,
+                                                 double *__restrict__ ls, unsigned *__restrict__ ctr) {
+    int img;
+    if ((int)blockIdx.x < n_visit) {
+        const VisItem it = items[blockIdx.x];
+        img = chan_img[it.chan];
+        vis_item(it, blockIdx.x, vpart, n_parts, ztot, nullptr, w, Rv, Vd, nullptr, vispart, 2, 0, 0.0);
+    } else {
+        const int blk = (int)blockIdx.x - n_visit;
+        img = blk / n_pb;
+        const int pb = blk % n_pb;
+        if (ivis_base[img + 1] == ivis_base[img]) return;   // started by the direction pass
+        const double *chc = chan + (size_t)img * CH_N;
+        const double am = chc[CH_AMAX];
+        double acc[2] = {0.0, 0.0};
+        if (isfinite(am) && chc[CH_STOP] == 0.0) {
+            const long long npix = (long long)n * n;
+            for (int r = 0; r < pb_len / NTHR; ++r) {
+                const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
+                if (p >= npix) break;
+                const size_t q = (size_t)img * npix + p;
+                const double d = (double)dir[q];
+                if (d == 0.0) continue;
+                const double x = (double)I[q] + am * d;
+                acc[0] += d * (log(x / M) + 1.0);
+                acc[1] += d * d / x;
+            }
+        }
+        block_sum<2>(acc);
+        if (threadIdx.x == 0) {
+            coh_store(ppart + ((size_t)img * n_pb + pb) * NPART + 0, acc[0]);
+            coh_store(ppart + ((size_t)img * n_pb + pb) * NPART + 1, acc[1]);
+        }
+    }
+    const int v0 = ivis_base[img], v1 = ivis_base[img + 1];
+    if (!arrive_last(ctr + img, (unsigned)(v1 - v0 + n_pb))) return;
+    double ab[2], fh[2];
+    sum_partials<2>(vispart + (size_t)v0 * NPART, v1 - v0, 0, ab);
+    sum_partials<2>(ppart + (size_t)img * n_pb * NPART, n_pb, 0, fh);
+    if (threadIdx.x == 0) {
+        const double *ch = chan + (size_t)img * CH_N;
+        ls_init(ls + (size_t)img * LSS_N, ab[0], ab[1], lam * ch[CH_E1], lam * ch[CH_E2], ch[CH_AMAX],
+                ch[CH_STOP] != 0.0, true, lam * fh[0], lam * fh[1]);
     }
 }
 
@@ -730,7 +832,7 @@ __global__ __launch_bounds__(NTHR) void k_ls_step(const R *__restrict__ I, const
     block_sum<2 * LS_K>(acc);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int m = 0; m < 2 * LS_K; ++m) ppart[((size_t)c * n_pb + pb) * NPART + m] = acc[m];
+        for (int m = 0; m < 2 * LS_K; ++m) coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + m, acc[m]);
     }
     if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double f[LS_K], h[LS_K];
@@ -786,7 +888,7 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
         }
         if (bad) atomicOr(flag, 1);
         block_sum<1>(acc);
-        if (threadIdx.x == 0) pp_out[((size_t)c * n_pb + pb) * NPART + 0] = acc[0];
+        if (threadIdx.x == 0) coh_store(pp_out + ((size_t)c * n_pb + pb) * NPART + 0, acc[0]);
     }
     const int v0 = ivis_base[c], v1 = ivis_base[c + 1];
     if (!arrive_last(ctr + c, (unsigned)(n_pb + v1 - v0))) return;
@@ -900,14 +1002,14 @@ hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipS
         return hipGetLastError();
     }
     if (phase == 1) {
-        // 5. Vd and the quadratic coefficients a, b of chi^2 along d; the
-        // line search starts from them
+        // 5. Vd, the quadratic coefficients a, b of chi^2 along d and phi'
+        // at alpha_max; the line search starts from them
         if (c->n_visit)
-            hipLaunchKernelGGL(k_vis, dim3(c->n_visit), blk, 0, st, c->d_vis, c->d_vpart,
-                               c->has_region ? c->n_fparts_m : c->n_fparts,
-                               (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, (double2 *)nullptr,
-                               c->d_scal, c->d_vispart, c->d_chan_img, 2, 0, ctr(c, CTR_VIS), c->d_ivis_base,
-                               c->d_chan, c->d_ls, c->lam);
+            hipLaunchKernelGGL(k_cg_vis<R>, dim3(c->n_visit + pix_grid(c)), blk, 0, st, c->d_vis, c->n_visit,
+                               c->d_vpart, c->has_region ? c->n_fparts_m : c->n_fparts, (long long)c->ztot,
+                               c->d_w, c->d_R, c->d_Vd, c->d_vispart, c->d_chan_img, c->d_ivis_base, CP<R>(I),
+                               CP<R>(c->d_dir), pp(c, 1), c->n, c->n_pb, c->pix_blk, c->M, c->lam, c->d_chan,
+                               c->d_ls, ctr(c, CTR_VIS));
         // 6-7. line-search passes (the last one accepts a step)
         const int L = c->ls_steps;
         for (int t = 0; t < L; ++t)
@@ -962,8 +1064,7 @@ hipError_t launch_vis_sum(const uvmem_ctx *c, int mode, double2 *out, hipStream_
     if (c->n_visit == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, c->d_w, c->d_R, c->d_Vd, out, c->d_scal, c->d_vispart,
-                       c->d_chan_img, mode, adj_scaled(c), (unsigned *)nullptr, (const int *)nullptr,
-                       (const double *)nullptr, (double *)nullptr, 0.0);
+                       c->d_chan_img, mode, adj_scaled(c));
     return hipGetLastError();
 }
 
@@ -972,8 +1073,7 @@ hipError_t launch_vis_sum_raw(const VisItem *items, int n_items, const double2 *
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(n_items), dim3(NTHR), 0, st, items, vpart, n_parts, ztot,
                        (const double2 *)nullptr, (const float *)nullptr, (double2 *)nullptr, (double2 *)nullptr,
-                       out, (const double *)nullptr, (double *)nullptr, (const int *)nullptr, 0, 0,
-                       (unsigned *)nullptr, (const int *)nullptr, (const double *)nullptr, (double *)nullptr, 0.0);
+                       out, (const double *)nullptr, (double *)nullptr, (const int *)nullptr, 0, 0);
     return hipGetLastError();
 }
 
@@ -981,8 +1081,7 @@ hipError_t launch_coef_max(const uvmem_ctx *c, const double2 *coef, hipStream_t 
     if (c->n_visit == 0 || !adj_scaled(c)) return hipSuccess;
     hipLaunchKernelGGL(k_vis, dim3(c->n_visit), dim3(NTHR), 0, st, c->d_vis, c->d_vpart, c->n_fparts,
                        (long long)c->ztot, c->d_vo, (const float *)nullptr, const_cast<double2 *>(coef), c->d_Vd,
-                       (double2 *)nullptr, c->d_scal, c->d_vispart, c->d_chan_img, 4, 1, (unsigned *)nullptr,
-                       (const int *)nullptr, (const double *)nullptr, (double *)nullptr, 0.0);
+                       (double2 *)nullptr, c->d_scal, c->d_vispart, c->d_chan_img, 4, 1);
     return hipGetLastError();
 }
 
