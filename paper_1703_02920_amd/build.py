@@ -44,7 +44,10 @@ PEAK_OUT = os.path.join(os.path.dirname(HERE), "libmfma_peak.so")
 
 def build_peak() -> str:
     tmp = PEAK_OUT + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *FLAGS, "-shared", "-o", tmp, PEAK_SRC]
+    # matrix instructions in the VGPR form: with accumulators in AGPRs the
+    # compiler copies them between registers inside the loop, and the copies
+    # (not the matrix cores) set the rate of the 16-wide forms
+    cmd = ["hipcc", *FLAGS, "-mllvm", "--amdgpu-mfma-vgpr-form=1", "-shared", "-o", tmp, PEAK_SRC]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for mfma_peak.hip:\n" + r.stdout + r.stderr)

@@ -124,7 +124,6 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
-
 // Column contraction of one 16-visibility tile of the forward against KT
 // 16-row slices of the LDS image block, starting at slice t0:
 //   acc[t][k][q'] = sum_j E_u[k][j] B[16 (t0 + t) + q'][j]  (real, imaginary)
@@ -485,7 +484,6 @@ __global__ __launch_bounds__(256) void k_adjoint(const AdjItem *__restrict__ ite
                 out[(size_t)i * np + j] = sizeof(T) == 4 ? sAcc[slot(x, y, r)] : (double)acc[x][y][r];
             }
 }
-
 
 // ----------------------------------------------------------------------------
 // Adjoint, FP32, 256 x 256 workgroup tile, eight waves of 64 (i) x 128 (j).
@@ -1056,188 +1054,6 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
             }
 }
 
-// Adjoint, split precision, 256 x 256 pixel tile, eight waves (2 x 4 waves
-// of 128 x 64 pixels).  The operand tables grow with the tile side while the
-// matrix-core work grows with its area, so the larger tile halves the table
-// and splitting work per product.  Per 32-visibility step:
-//   1. every thread forms one fine and one coarse entry of each axis
-//      (k = tid / 16, index tid % 16), hardware sin/cos of FP64-reduced phases:
-//        Hv[q][k] = conj(s w_k c_k E(b_k (i0 + q - N/2))),  Gv[t][k] = conj E(16 b_k t)
-//        Fu[q][k] = E(a_k (j0 + q - N/2)),                  Gu[t][k] = E(16 a_k t)
-//      (s: the fp16 power-of-two scale; E(x) = exp(2 pi i x));
-//   2. every thread forms one operand row, P[i][k] = Hv Gv (waves 0-3) or
-//      E[j][k] = Fu Gu (waves 4-7), split into hi and lo halves;
-//   3. each wave keeps its four E column blocks in registers and streams its
-//      eight P row blocks: 6 MFMAs per 16 x 16 block pair.
-// Chunk sums are FP32 and the partial tile is stored in FP32.
-template <typename H>
-__global__ __launch_bounds__(512, 1) void k_adjoint_h16w(const AdjItem *__restrict__ items,
-                                                         const double *__restrict__ a,
-                                                         const double *__restrict__ b,
-                                                         const double2 *__restrict__ coef,
-                                                         const float *__restrict__ w,
-                                                         const double *__restrict__ vispart,
-                                                         const int *__restrict__ vis_base,
-                                                         float *__restrict__ gpart, int n, int np) {
-    typedef typename Half16<H>::h8 h8;
-    constexpr int TT = 256;
-    constexpr int KS = 32;
-    constexpr int KT = KS + 2;     // padded table rows (float2)
-    constexpr int NR = 8;          // 16-row blocks per wave (128 rows)
-    constexpr int NCB = 4;         // 16-column blocks per wave (64 columns)
-    __shared__ __attribute__((aligned(16))) float2 sHv[16][KT], sFu[16][KT], sGv[16][KT], sGu[16][KT];
-    __shared__ __attribute__((aligned(16))) H sP[4][TT][KS];   // re_h, re_l, -im_h, -im_l
-    __shared__ __attribute__((aligned(16))) H sE[4][TT][KS];   // cos_h, cos_l, sin_h, sin_l
-    __shared__ double sRed[8];
-    // group kg of row r is stored at group kg ^ ((r >> 1) & 3): eight
-    // consecutive rows then hit distinct LDS banks for 16-byte accesses
-    auto swz = [](int r, int kg) { return 8 * (kg ^ ((r >> 1) & 3)); };
-
-    const AdjItem it = items[blockIdx.x];
-    const int i0 = it.ti * TT, j0 = it.tj * TT;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int q = lane & 15, g = lane >> 4;
-    const int wi = (wave >> 2) * 128, wj = (wave & 3) * 64;
-    const int half = n / 2;
-    float scale = 1.f;
-    if constexpr (Half16<H>::scaled) {
-        double m = 0.0;
-        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 512)
-            m = fmax(m, vispart[(size_t)x * NPART + 2]);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        if (lane == 0) sRed[wave] = m;
-        __syncthreads();
-        m = sRed[0];
-#pragma unroll
-        for (int x = 1; x < 8; ++x) m = fmax(m, sRed[x]);
-        scale = pow2_scale((float)m);
-    }
-
-    // table task of this thread: visibility k = tid / 16 of the step, index tid % 16
-    const int tk = tid >> 4, tq = tid & 15;
-    struct Pre {
-        double a, b;
-        double2 c;
-        float w;
-    };
-    auto fetch = [&](long long kb, Pre &p) {
-        const long long k = kb + tk;
-        p.a = p.b = 0.0;
-        p.c = make_double2(0.0, 0.0);
-        p.w = 0.f;
-        if (k < it.kend) { p.a = a[k]; p.b = b[k]; p.c = coef[k]; p.w = w ? w[k] : 1.f; }
-    };
-
-    floatx4 acc[NR][NCB];
-#pragma unroll
-    for (int x = 0; x < NR; ++x)
-#pragma unroll
-        for (int y = 0; y < NCB; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    // operand row of this thread in the split stage
-    const int dim = tid >> 8, row = tid & 255;
-    const float2 *f_row = dim == 0 ? sHv[row & 15] : sFu[row & 15];
-    const float2 *g_row = dim == 0 ? sGv[row >> 4] : sGu[row >> 4];
-    H (*dst)[TT][KS] = dim == 0 ? sP : sE;
-
-    Pre cur, nxt;
-    fetch(it.kbeg, cur);
-    for (long long kb = it.kbeg; kb < it.kend; kb += KS) {
-        if (kb + KS < it.kend) fetch(kb + KS, nxt);
-        // ---- 1. twiddle tables (zero coefficients / unit factors past the end)
-        {
-            float c, s;
-            cis2pi_hw((float)phase(cur.b, i0 + tq - half), c, s);
-            const float cr = scale * (float)((double)cur.w * cur.c.x);
-            const float ci = scale * (float)((double)cur.w * cur.c.y);
-            sHv[tq][tk] = make_float2(cr * c - ci * s, -(cr * s + ci * c));
-            cis2pi_hw((float)phase(cur.a, j0 + tq - half), c, s);
-            sFu[tq][tk] = make_float2(c, s);
-            cis2pi_hw((float)phase(cur.b, 16 * tq), c, s);
-            sGv[tq][tk] = make_float2(c, -s);
-            cis2pi_hw((float)phase(cur.a, 16 * tq), c, s);
-            sGu[tq][tk] = make_float2(c, s);
-        }
-        __syncthreads();
-        // ---- 2. pre-split operand rows
-#pragma unroll
-        for (int kg = 0; kg < KS / 8; ++kg) {
-            float re[8], im[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float2 fv = f_row[8 * kg + e], gv = g_row[8 * kg + e];
-                re[e] = fv.x * gv.x - fv.y * gv.y;
-                im[e] = fv.x * gv.y + fv.y * gv.x;
-            }
-            h8 v0, v1, v2, v3;
-            split8<H>(re, v0, v1);
-            split8<H>(im, v2, v3);
-            const int o = swz(row, kg);
-            *reinterpret_cast<h8 *>(&dst[0][row][o]) = v0;
-            *reinterpret_cast<h8 *>(&dst[1][row][o]) = v1;
-            *reinterpret_cast<h8 *>(&dst[2][row][o]) = v2;
-            *reinterpret_cast<h8 *>(&dst[3][row][o]) = v3;
-        }
-        __syncthreads();
-        // ---- 3. contract on matrix cores
-        h8 ech[NCB], ecl[NCB], esh[NCB], esl[NCB];
-#pragma unroll
-        for (int y = 0; y < NCB; ++y) {
-            const int r = wj + 16 * y + q;
-            const int o = swz(r, g);
-            ech[y] = *reinterpret_cast<const h8 *>(&sE[0][r][o]);
-            ecl[y] = *reinterpret_cast<const h8 *>(&sE[1][r][o]);
-            esh[y] = *reinterpret_cast<const h8 *>(&sE[2][r][o]);
-            esl[y] = *reinterpret_cast<const h8 *>(&sE[3][r][o]);
-        }
-        // P fragments of row block x + 1 are loaded while block x contracts
-        h8 nph, npl, nqh, nql;
-        auto load_p = [&](int x, h8 &ph, h8 &pl, h8 &qh, h8 &ql) {
-            const int r = wi + 16 * x + q;
-            const int o = swz(r, g);
-            ph = *reinterpret_cast<const h8 *>(&sP[0][r][o]);
-            pl = *reinterpret_cast<const h8 *>(&sP[1][r][o]);
-            qh = *reinterpret_cast<const h8 *>(&sP[2][r][o]);
-            ql = *reinterpret_cast<const h8 *>(&sP[3][r][o]);
-        };
-        load_p(0, nph, npl, nqh, nql);
-#pragma unroll
-        for (int x = 0; x < NR; ++x) {
-            const h8 prh = nph, prl = npl, pih = nqh, pil = nql;
-            if (x + 1 < NR) load_p(x + 1, nph, npl, nqh, nql);
-            // product-major order: four independent accumulators between
-            // dependent matrix-core instructions
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prh, ech[y], acc[x][y]);
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pih, esh[y], acc[x][y]);
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prh, ecl[y], acc[x][y]);
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pih, esl[y], acc[x][y]);
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(prl, ech[y], acc[x][y]);
-#pragma unroll
-            for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(pil, esh[y], acc[x][y]);
-        }
-        cur = nxt;
-    }
-    float *out = gpart + (size_t)it.slot * np * np;
-    const float inv = 1.f / scale;   // a power of two: exact
-#pragma unroll
-    for (int x = 0; x < NR; ++x)
-#pragma unroll
-        for (int y = 0; y < NCB; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wi + 16 * x + 4 * g + r;
-                const int j = j0 + wj + 16 * y + q;
-                out[(size_t)i * np + j] = acc[x][y][r] * inv;
-            }
-}
-
 // Adjoint, split precision, 256 x 256 pixel tile, eight waves of 128 (i) x 64
 // (j), software-pipelined over steps of 16 visibilities.  The real and
 // imaginary parts of a step are concatenated along the contraction
@@ -1460,191 +1276,6 @@ template <> struct Half32<_Float16> {
     }
 };
 
-// Adjoint, split precision, 256 x 256 pixel tile, eight waves of 128 (i) x 64
-// (j): the pipeline of k_adjoint_h16s on 32 x 32 x 16 products.  A step's
-// contraction length 32 (16 visibilities, real then imaginary parts) is two
-// 16-long slices; per slice each wave contracts four 32-row P tiles with two
-// 32-column E tiles, three products each (48 matrix instructions per step).
-template <typename H>
-__global__ __launch_bounds__(512, 1) void k_adjoint_h16m(const AdjItem *__restrict__ items,
-                                                         const double *__restrict__ a,
-                                                         const double *__restrict__ b,
-                                                         const double2 *__restrict__ coef,
-                                                         const float *__restrict__ w,
-                                                         const double *__restrict__ vispart,
-                                                         const int *__restrict__ vis_base,
-                                                         float *__restrict__ gpart, int n, int np) {
-    typedef typename Half16<H>::h8 h8;
-    constexpr int TT = 256;
-    constexpr int KV = 16;         // visibilities per step
-    constexpr int KP = 2 * KV;     // contraction length per step (re, im)
-    constexpr int NX = 4;          // 32-row P tiles per wave (128 rows)
-    constexpr int NY = 2;          // 32-column E tiles per wave (64 columns)
-    constexpr int TR = KV + 2;     // table row stride in float2 (16-byte aligned rows)
-    // operands: [buffer][hi, lo][row: P 0-255, E 256-511][KP], 16-byte
-    // chunks XOR-swizzled by (row >> 1) & 3
-    __shared__ __attribute__((aligned(16))) H sOp[2][2][2 * TT][KP];
-    // tables: [buffer][axis: v (P side), u (E side)][fine, coarse][index][k]
-    __shared__ __attribute__((aligned(16))) float2 sTab[2][2][2][16][TR];
-    __shared__ double sRed[8];
-    auto swz = [](int r, int c) { return 8 * (c ^ ((r >> 1) & 3)); };
-
-    const AdjItem it = items[blockIdx.x];
-    const int i0 = it.ti * TT, j0 = it.tj * TT;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int l32 = lane & 31, hk = lane >> 5;
-    const int wi = (wave >> 2) * 128, wj = (wave & 3) * 64;
-    const int half = n / 2;
-    float scale = 1.f;
-    if constexpr (Half16<H>::scaled) {
-        double m = 0.0;
-        for (int x = vis_base[it.chan] + tid; x < vis_base[it.chan + 1]; x += 512)
-            m = fmax(m, vispart[(size_t)x * NPART + 2]);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        if (lane == 0) sRed[wave] = m;
-        __syncthreads();
-        m = sRed[0];
-#pragma unroll
-        for (int x = 1; x < 8; ++x) m = fmax(m, sRed[x]);
-        scale = pow2_scale((float)m);
-    }
-
-    // table task: axis tax (0: v / P side, 1: u / E side), index tix, visibility tk of the step
-    const int tax = tid >> 8, tix = (tid >> 4) & 15, tk = tid & 15;
-    const double *xsrc = tax == 0 ? b : a;
-    const int origin = (tax == 0 ? i0 : j0) + tix - half;
-    struct Pre {
-        double x;
-        double2 c;
-        float w;
-    };
-    auto fetch = [&](long long kb, Pre &p) {
-        const long long k = kb + tk;
-        p.x = 0.0;
-        p.c = make_double2(0.0, 0.0);
-        p.w = 0.f;
-        if (k < it.kend) {
-            p.x = xsrc[k];
-            if (tax == 0) {
-                p.c = coef[k];
-                p.w = w ? w[k] : 1.f;
-            }
-        }
-    };
-    // fine[idx][k] = conj(s w_k c_k E(b_k (i0 + idx - N/2))) or E(a_k (j0 + idx - N/2));
-    // coarse[idx][k] = conj E(16 b_k idx) or E(16 a_k idx)   (E(x) = exp(2 pi i x))
-    auto gen = [&](int tb, const Pre &p) {
-        float c, sn;
-        cis2pi_hw((float)phase(p.x, origin), c, sn);
-        float2 fine;
-        if (tax == 0) {
-            const float cr = scale * (float)((double)p.w * p.c.x);
-            const float ci = scale * (float)((double)p.w * p.c.y);
-            fine = make_float2(cr * c - ci * sn, -(cr * sn + ci * c));
-        } else {
-            fine = make_float2(c, sn);
-        }
-        sTab[tb][tax][0][tix][tk] = fine;
-        cis2pi_hw((float)phase(p.x, 16 * tix), c, sn);
-        sTab[tb][tax][1][tix][tk] = make_float2(c, tax == 0 ? -sn : sn);
-    };
-    // operand row of this thread: side fside (0: P, 1: E), row frow of that side
-    const int fside = tid >> 8, frow = tid & 255;
-    const int fq = frow & 15, ft = frow >> 4;
-    const int orow = fside * TT + frow;
-    // half a row: visibilities 8 hv .. 8 hv + 7, both parts (chunks hv and 2 + hv)
-    auto form_half = [&](int tb, int ob, int hv) {
-        const float2 *fr = &sTab[tb][fside][0][fq][8 * hv];
-        const float2 *cr = &sTab[tb][fside][1][ft][8 * hv];
-        float re[8], im[8];
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-            const float4 f2 = *reinterpret_cast<const float4 *>(fr + e);
-            const float4 c2 = *reinterpret_cast<const float4 *>(cr + e);
-            re[e] = f2.x * c2.x - f2.y * c2.y;
-            im[e] = f2.x * c2.y + f2.y * c2.x;
-            re[e + 1] = f2.z * c2.z - f2.w * c2.w;
-            im[e + 1] = f2.z * c2.w + f2.w * c2.z;
-        }
-        h8 rh, rl, ih, il;
-        split8<H>(re, rh, rl);
-        split8<H>(im, ih, il);
-        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, hv)]) = rh;
-        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, hv)]) = rl;
-        *reinterpret_cast<h8 *>(&sOp[ob][0][orow][swz(orow, 2 + hv)]) = ih;
-        *reinterpret_cast<h8 *>(&sOp[ob][1][orow][swz(orow, 2 + hv)]) = il;
-    };
-
-    floatx16 acc[NX][NY];
-#pragma unroll
-    for (int x = 0; x < NX; ++x)
-#pragma unroll
-        for (int y = 0; y < NY; ++y)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
-
-    const long long kb0 = it.kbeg;
-    const int nsteps = (int)((it.kend - it.kbeg + KV - 1) / KV);
-    Pre pre;
-    fetch(kb0, pre);
-    gen(0, pre);
-    fetch(kb0 + KV, pre);
-    __syncthreads();
-    form_half(0, 0, 0);
-    form_half(0, 0, 1);
-    gen(1, pre);
-    __syncthreads();
-    // One basic block per step (no branches): the operand rows of step s + 1
-    // and the tables of step s + 2 are formed between the matrix
-    // instructions of step s.  In the last steps they form rows from stale
-    // tables or zero data into buffers that are never read again.
-    for (int s = 0; s < nsteps; ++s) {
-        const int ob = s & 1;
-        fetch(kb0 + (long long)(s + 2) * KV, pre);
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            const int ck = 2 * sl + hk;     // this lane's 8-element chunk of the slice
-            h8 eh[NY], el[NY];
-#pragma unroll
-            for (int y = 0; y < NY; ++y) {
-                const int r = TT + wj + 32 * y + l32;
-                eh[y] = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, ck)]);
-                el[y] = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, ck)]);
-            }
-#pragma unroll
-            for (int x = 0; x < NX; ++x) {
-                const int r = wi + 32 * x + l32;
-                const h8 ph = *reinterpret_cast<const h8 *>(&sOp[ob][0][r][swz(r, ck)]);
-                const h8 pl = *reinterpret_cast<const h8 *>(&sOp[ob][1][r][swz(r, ck)]);
-#pragma unroll
-                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(ph, eh[y], acc[x][y]);
-#pragma unroll
-                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(ph, el[y], acc[x][y]);
-#pragma unroll
-                for (int y = 0; y < NY; ++y) acc[x][y] = Half32<H>::mma(pl, eh[y], acc[x][y]);
-                if (sl == 0 && x == 1) form_half(ob ^ 1, ob ^ 1, 0);
-                if (sl == 1 && x == 0) gen(ob, pre);
-                if (sl == 1 && x == 2) form_half(ob ^ 1, ob ^ 1, 1);
-            }
-        }
-        __syncthreads();
-    }
-    float *out = gpart + (size_t)it.slot * np * np;
-    const float inv = 1.f / scale;   // a power of two: exact
-#pragma unroll
-    for (int x = 0; x < NX; ++x)
-#pragma unroll
-        for (int y = 0; y < NY; ++y)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = i0 + wi + 32 * x + 8 * (r >> 2) + 4 * hk + (r & 3);
-                const int j = j0 + wj + 32 * y + l32;
-                out[(size_t)i * np + j] = acc[x][y][r] * inv;
-            }
-}
-
 // Forward, split precision, persistent, 32 x 32 x 16 products.  As
 // k_forward_h16p, a workgroup of eight waves holds an IB x JB image block
 // (hi and lo halves, fp16 scaled by a power of two to the block maximum) in
@@ -1747,7 +1378,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restr
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 cv[e] = cc * fc[e] - sc * fs[e];
-                nsv[e] = -(sc * fc[e] + cc * fs[e]);
+                nsv[e] = (-sc) * fc[e] - cc * fs[e];   // negations fold into the operand modifiers
             }
             h8 th, tl, uh, ul;
             split8<H>(cv, th, tl);
@@ -1852,22 +1483,11 @@ hipError_t adj_dispatch(const uvmem_ctx *c, const double2 *coef, const float *w,
 template <typename H, int NV>
 hipError_t fwd_h16_t(const uvmem_ctx *c, const float *B, hipStream_t st, const FwdPItem *items, int nitems) {
     const dim3 grid(nitems), blk(512);
-    static const bool old16 = std::getenv("UVMEM_SPLIT_FWD_16") != nullptr;
-    if (!old16 && c->ib_rows == 128 && c->jb_cols == 256) {
+    if (c->ib_rows == 128 && c->jb_cols == 256)
         hipLaunchKernelGGL((k_forward_h16m<H, 128, 256>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
-        return hipGetLastError();
-    }
-    if (!old16 && c->ib_rows == 128 && c->jb_cols == 128) {
-        hipLaunchKernelGGL((k_forward_h16m<H, 128, 128>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
-                           c->d_vpart, c->n, c->np, (long long)c->ztot);
-        return hipGetLastError();
-    }
-    if (c->ib_rows == 128 && c->jb_cols == 256)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 256, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
-                           c->d_vpart, c->n, c->np, (long long)c->ztot);
     else if (c->ib_rows == 128 && c->jb_cols == 128)
-        hipLaunchKernelGGL((k_forward_h16p<H, 128, 128, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
+        hipLaunchKernelGGL((k_forward_h16m<H, 128, 128>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
                            c->d_vpart, c->n, c->np, (long long)c->ztot);
     else
         hipLaunchKernelGGL((k_forward_h16p<H, 64, 64, NV>), grid, blk, 0, st, items, c->d_a, c->d_b, B,
@@ -1887,15 +1507,7 @@ template <typename H>
 hipError_t adj_h16(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, const AdjItem *items,
                    int nitems) {
     if (nitems == 0) return hipSuccess;
-    static const bool old_split = std::getenv("UVMEM_SPLIT_ADJ_W") != nullptr;
-    static const bool m32_split = std::getenv("UVMEM_SPLIT_ADJ_M") != nullptr;
-    if (c->adj_tt == 256 && m32_split)
-        hipLaunchKernelGGL((k_adjoint_h16m<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
-                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
-    else if (c->adj_tt == 256 && old_split)
-        hipLaunchKernelGGL((k_adjoint_h16w<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
-                           coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
-    else if (c->adj_tt == 256)
+    if (c->adj_tt == 256)
         hipLaunchKernelGGL((k_adjoint_h16s<H>), dim3(nitems), dim3(512), 0, st, items, c->d_a, c->d_b,
                            coef, w, c->d_vispart, c->d_vis_base, (float *)c->d_gpart, c->n, c->np);
     else if (c->adj_tt == 128)

@@ -3,6 +3,9 @@
     python rocprof_summary.py stats DIR OUT.md --cmd "..." [--note "..."]
         kernel statistics (``--kernel-trace --stats --output-format csv``) as a
         markdown table, with the command that produced them.
+    python rocprof_summary.py counters DIR OUT.md --kernels k_a k_b --cmd "..." [--note "..."]
+        median per dispatch of each SQ / GRBM counter of one ``--pmc`` run for
+        the named kernels, with the derived matrix-core ratios.
     python rocprof_summary.py traffic --workload W --fetch DIR --write DIR \\
             --copy-fetch DIR --copy-write DIR --copy-bytes B --kernels k_forward k_adjoint --out OUT.md
         HBM traffic per launch from two counter runs (FETCH_SIZE, then
@@ -157,6 +160,55 @@ def traffic(args):
     print(f"wrote {args.out} and {rec_path}")
 
 
+def counters(args):
+    path = _one(args.dir, "*counter_collection.csv")
+    vals, dur = {}, {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            k = _fname(r["Kernel_Name"])
+            if k in args.kernels:
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                dur.setdefault(k, {})[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    for k, d in dur.items():
+        vals[k]["duration_s"] = list(d.values())
+    names = sorted({c for d in vals.values() for c in d})
+    lines = [f"# {args.title}", "", "Command (repository root, one MI355X):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp && cd -", args.cmd, "```", ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += [f"Source: `{os.path.basename(path)}`; median over the dispatches of each kernel.", "",
+              "| counter | " + " | ".join(f"`{k}`" for k in args.kernels) + " |",
+              "|---|" + "---:|" * len(args.kernels)]
+    med = {k: {c: statistics.median(v) for c, v in vals.get(k, {}).items()} for k in args.kernels}
+    lines.append("| dispatches | " + " | ".join(str(len(next(iter(vals[k].values())))) if k in vals else "0"
+                                              for k in args.kernels) + " |")
+    for c in names:
+        lines.append(f"| {c} | " + " | ".join(f"{med[k][c]:.4g}" if c in med[k] else "" for k in args.kernels) + " |")
+
+    def ratio(k, a, b, scale=1.0):
+        m = med[k]
+        return f"{scale * m[a] / m[b]:.3f}" if a in m and b in m and m[b] else ""
+    derived = [
+        ("engine clock, GHz: GRBM_GUI_ACTIVE / 8 XCDs / dispatch duration",
+         lambda k: ratio(k, "GRBM_GUI_ACTIVE", "duration_s", 1.0 / 8 / 1e9)),
+        ("MFMA busy per SIMD cycle: SQ_VALU_MFMA_BUSY_CYCLES x 8 / (GRBM_GUI_ACTIVE x 1024)",
+         lambda k: ratio(k, "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", 8.0 / 1024.0)),
+        ("co-executing share of MFMA busy: SQ_VALU_MFMA_COEXEC_CYCLES / SQ_VALU_MFMA_BUSY_CYCLES",
+         lambda k: ratio(k, "SQ_VALU_MFMA_COEXEC_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES")),
+        ("vector instructions per matrix instruction: SQ_INSTS_VALU / SQ_INSTS_MFMA",
+         lambda k: ratio(k, "SQ_INSTS_VALU", "SQ_INSTS_MFMA")),
+        ("LDS instructions per matrix instruction: SQ_INSTS_LDS / SQ_INSTS_MFMA",
+         lambda k: ratio(k, "SQ_INSTS_LDS", "SQ_INSTS_MFMA")),
+    ]
+    lines += ["", "| derived | " + " | ".join(f"`{k}`" for k in args.kernels) + " |",
+              "|---|" + "---:|" * len(args.kernels)]
+    for label, fn in derived:
+        lines.append(f"| {label} | " + " | ".join(fn(k) for k in args.kernels) + " |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -166,6 +218,13 @@ def main():
     s.add_argument("--cmd", required=True)
     s.add_argument("--title", default="Kernel statistics")
     s.add_argument("--note", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("out")
+    c.add_argument("--kernels", nargs="+", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default="Counters")
+    c.add_argument("--note", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--workload", required=True)
     t.add_argument("--fetch", required=True)
@@ -178,7 +237,7 @@ def main():
     t.add_argument("--cmd", nargs="+", required=True)
     t.add_argument("--out", required=True)
     args = ap.parse_args()
-    stats(args) if args.what == "stats" else traffic(args)
+    {"stats": stats, "counters": counters, "traffic": traffic}[args.what](args)
 
 
 if __name__ == "__main__":
