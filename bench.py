@@ -161,8 +161,9 @@ def cpu_baseline(ds, target_s: float = 12.0, single_s: float = 4.0):
 
 MFMA_KINDS = {"fp32": (0, "v_mfma_f32_16x16x4_f32"), "fp64": (1, "v_mfma_f64_16x16x4_f64"),
               "bf16": (2, "v_mfma_f32_16x16x32_bf16"), "fp16": (3, "v_mfma_f32_16x16x32_f16"),
-              "bf16_32x32": (4, "v_mfma_f32_32x32x16_bf16")}
-SPEC_PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16_32x32": 2500.0}
+              "bf16_32x32": (4, "v_mfma_f32_32x32x16_bf16"), "fp16_32x32": (5, "v_mfma_f32_32x32x16_f16")}
+SPEC_PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16_32x32": 2500.0,
+             "fp16_32x32": 2500.0}
 
 
 def mfma_peak(kinds=None, target_ms=20.0):
@@ -175,7 +176,7 @@ def mfma_peak(kinds=None, target_ms=20.0):
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     out = {}
     blocks = 1024
-    flops = {0: 2048.0 * 8, 1: 2048.0 * 8, 2: 16384.0 * 8, 3: 16384.0 * 8, 4: 32768.0 * 4}
+    flops = {0: 2048.0 * 8, 1: 2048.0 * 8, 2: 16384.0 * 8, 3: 16384.0 * 8, 4: 32768.0 * 4, 5: 32768.0 * 4}
     for name in (kinds or MFMA_KINDS):
         kind, inst = MFMA_KINDS[name]
         iters = int(target_ms * 1e-3 * SPEC_PEAK[name] * 1e12 / (4 * blocks * flops[kind]))
@@ -186,6 +187,25 @@ def mfma_peak(kinds=None, target_ms=20.0):
         out[name] = {"instruction": inst, "tflops": tf.value, "spec_tflops": SPEC_PEAK[name],
                      "frac_of_spec": tf.value / SPEC_PEAK[name], "ms": ms.value, "iters": iters}
     return out
+
+
+# matrix-instruction form of each split-precision DFT kernel on 128-row
+# forward blocks and 256-pixel adjoint tiles (the c2-c5 workloads)
+SPLIT_FORMS = {"bf16x3": {"forward": "bf16_32x32", "adjoint": "bf16"},
+               "fp16x3": {"forward": "fp16_32x32", "adjoint": "fp16"}}
+
+
+def mixed_measured(prec, kern, flops_per_launch):
+    """Issued 3-product rate of each split DFT kernel over the measured rate
+    of the matrix-instruction form it uses."""
+    try:
+        forms = SPLIT_FORMS[prec]
+        pk = mfma_peak(sorted(set(forms.values())))
+    except (OSError, RuntimeError, KeyError):
+        return None
+    return {k: {"frac": 3 * flops_per_launch / (v / 1e3) / 1e12 / pk[forms[k]]["tflops"],
+                "measured_peak": pk[forms[k]]["tflops"], "instruction": pk[forms[k]]["instruction"]}
+            for k, v in kern.items() if k in forms}
 
 
 def run_steps(ctx, steps, warmup, graph):
@@ -651,6 +671,7 @@ def main():
                                                              for k, v in mkern.items()},
                              "mfma_frac_3_product_issued": {k: 3 * flops_per_launch / (v / 1e3) / 1e12 / PEAK[mp]
                                                             for k, v in mkern.items()},
+                             "mfma_frac_3_product_of_measured_peak": mixed_measured(mp, mkern, flops_per_launch),
                              "rel_err_vs_fp64": eval_error(ds, mctx, ref)}
                 mctx.close()
         ref.close()

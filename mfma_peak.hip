@@ -56,36 +56,41 @@ __global__ __launch_bounds__(256) void k_peak(int iters, float seed, float *out)
                 else acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc[c], 0, 0, 0);
             }
         for (int c = 0; c < CHAINS; ++c) sum += acc[c][0] + acc[c][3];
-    } else {   // v_mfma_f32_32x32x16_bf16
-        bf16x8 a, b;
+    } else {   // v_mfma_f32_32x32x16_{bf16,f16}
+        typedef typename std::conditional<KIND == 4, bf16x8, f16x8>::type h8;
+        typedef typename std::conditional<KIND == 4, __bf16, _Float16>::type H;
+        h8 a, b;
         for (int e = 0; e < 8; ++e) {
-            a[e] = (__bf16)(x + 0.01f * e);
-            b[e] = (__bf16)(1.f - 0.01f * e);
+            a[e] = (H)(x + 0.01f * e);
+            b[e] = (H)(1.f - 0.01f * e);
         }
         floatx16 acc[CHAINS / 2];
         for (int c = 0; c < CHAINS / 2; ++c)
             for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
         for (int t = 0; t < iters; ++t)
 #pragma unroll
-            for (int c = 0; c < CHAINS / 2; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+            for (int c = 0; c < CHAINS / 2; ++c) {
+                if constexpr (KIND == 4) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+                else acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[c], 0, 0, 0);
+            }
         for (int c = 0; c < CHAINS / 2; ++c) sum += acc[c][0] + acc[c][15];
     }
     out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
 }
 
 // flops of one instruction and instructions per wave per iteration
-constexpr double FLOPS[5] = {2.0 * 16 * 16 * 4, 2.0 * 16 * 16 * 4, 2.0 * 16 * 16 * 32, 2.0 * 16 * 16 * 32,
-                             2.0 * 32 * 32 * 16};
-constexpr int PER_ITER[5] = {CHAINS, CHAINS, CHAINS, CHAINS, CHAINS / 2};
+constexpr double FLOPS[6] = {2.0 * 16 * 16 * 4, 2.0 * 16 * 16 * 4, 2.0 * 16 * 16 * 32, 2.0 * 16 * 16 * 32,
+                             2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 16};
+constexpr int PER_ITER[6] = {CHAINS, CHAINS, CHAINS, CHAINS, CHAINS / 2, CHAINS / 2};
 
 }  // namespace
 
 // kind: 0 FP32 16x16x4, 1 FP64 16x16x4, 2 bf16 16x16x32, 3 fp16 16x16x32,
-// 4 bf16 32x32x16.  Runs `blocks` workgroups of four waves, `iters` loop
+// 4 bf16 32x32x16, 5 fp16 32x32x16.  Runs `blocks` workgroups of four waves, `iters` loop
 // iterations each, `reps` timed launches after one warm-up; writes the best
 // launch's TFLOP/s and milliseconds.  Returns 0, or the HIP error code.
 extern "C" int mfma_peak(int kind, int blocks, int iters, int reps, double *tflops, double *ms) {
-    if (kind < 0 || kind > 4 || blocks < 1 || iters < 1 || reps < 1 || !tflops || !ms) return -1;
+    if (kind < 0 || kind > 5 || blocks < 1 || iters < 1 || reps < 1 || !tflops || !ms) return -1;
     float *out = nullptr;
     hipError_t e = hipMalloc((void **)&out, (size_t)blocks * 256 * sizeof(float));
     if (e != hipSuccess) return (int)e;
@@ -100,7 +105,8 @@ extern "C" int mfma_peak(int kind, int blocks, int iters, int reps, double *tflo
         case 1: hipLaunchKernelGGL(k_peak<1>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
         case 2: hipLaunchKernelGGL(k_peak<2>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
         case 3: hipLaunchKernelGGL(k_peak<3>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
-        default: hipLaunchKernelGGL(k_peak<4>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
+        case 4: hipLaunchKernelGGL(k_peak<4>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
+        default: hipLaunchKernelGGL(k_peak<5>, dim3(blocks), dim3(256), 0, nullptr, iters, 0.5f, out); break;
         }
         e = hipGetLastError();
         (void)hipEventRecord(e1, nullptr);

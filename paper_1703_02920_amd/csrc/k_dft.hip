@@ -811,7 +811,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16p(const FwdPItem *__restr
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 cv[e] = cc * fc[v][e] - sc * fs[v][e];
-                nsv[e] = -(sc * fc[v][e] + cc * fs[v][e]);
+                nsv[e] = (-sc) * fc[v][e] - cc * fs[v][e];
             }
             split8<H>(cv, th, tl);
             split8<H>(nsv, uh, ul);
