@@ -243,7 +243,15 @@ int uvmem_cg_step(uvmem_ctx *ctx, void *I_dev, double *scal_dev);
 int uvmem_cg_run(uvmem_ctx *ctx, void *I_dev, int iters, double *scal_hist_dev, int use_graph);
 /* Checkpoint of the CG state (direction, projected gradients, residuals,
  * scalars, iteration count) to/from host memory.  With host_blob == NULL,
- * get_state only reports the size in *bytes.  Both synchronise the stream. */
+ * get_state only reports the size in *bytes.  Both synchronise the stream.
+ * Blob layout (native byte order, parts back to back): a 48-byte header
+ * (uint64 magic; int32 image side, channel count, precision, mode, forward
+ * model, grid side, gradient model, pad; int64 total visibilities), then the
+ * direction d, the projected gradient and the gradient, each n_img x N x N
+ * values of the context's real type (double for UVMEM_FP64, else float),
+ * the residuals R (complex128 per visibility), the UVMEM_NSCAL scalars of
+ * each image (double) and eight double CG flags per image.  set_state
+ * refuses a blob whose header does not match the context. */
 int uvmem_cg_get_state(uvmem_ctx *ctx, void *host_blob, size_t *bytes);
 int uvmem_cg_set_state(uvmem_ctx *ctx, const void *host_blob, size_t bytes);
 

@@ -200,8 +200,14 @@ int build_layout(uvmem_ctx *c) {
     c->np = ((c->n + 63) / 64) * 64;
     // persistent forward: image blocks resident in LDS, 128 x 256 where the
     // size allows (FP32 and bf16 also sum at most 256 columns in one FP32
-    // accumulator; the blocks are combined in FP64), 64 x 64 in FP64
-    if (c->prec == UVMEM_FP64) { c->ib_rows = 64; c->jb_cols = 64; }
+    // accumulator; the blocks are combined in FP64).  FP64 keeps 64 rows (its
+    // accumulators take twice the registers) and takes up to 256 columns:
+    // each tile's twiddle set-up and row dot then feed four times the products
+    // of a 64 x 64 block (512^2 x 1.0M: forward 22.1 -> 17.2 ms)
+    if (c->prec == UVMEM_FP64) {
+        c->ib_rows = 64;
+        c->jb_cols = c->np % 256 == 0 ? 256 : c->np % 128 == 0 ? 128 : 64;
+    }
     else if (c->np % 256 == 0) { c->ib_rows = 128; c->jb_cols = 256; }
     else if (c->np % 128 == 0) { c->ib_rows = 128; c->jb_cols = 128; }
     else { c->ib_rows = 64; c->jb_cols = 64; }
@@ -209,13 +215,14 @@ int build_layout(uvmem_ctx *c) {
     c->n_jb = c->np / c->jb_cols;
     c->n_fparts = c->fwd_model == UVMEM_FWD_GRIDDED ? 1 : c->n_ib * c->n_jb;
     // adjoint pixel tile: 256 x 256 for the FP32 and split kernels where the
-    // padded side allows (halves their table work per product), else
-    // 128 x 128 (FP32, split), 64 x 64 (FP64)
-    c->adj_tt = (c->prec != UVMEM_FP64 && c->np % 128 == 0) ? 128 : 64;
+    // padded side allows (halves their table work per product), else 128 x 128
+    // (FP64 too: its twiddle tables then feed four times the products of a
+    // 64 x 64 tile, 512^2 x 1.0M: 22.9 -> 17.5 ms), else 64 x 64
+    c->adj_tt = c->np % 128 == 0 ? 128 : 64;
     if (c->prec != UVMEM_FP64 && c->np % 256 == 0) c->adj_tt = 256;
     if (const char *env = std::getenv("UVMEM_ADJ_TILE")) {
         const int t = std::atoi(env);
-        if ((t == 64 || (t == 128 && c->prec != UVMEM_FP64) || (t == 256 && c->prec != UVMEM_FP64)) && c->np % t == 0)
+        if ((t == 64 || t == 128 || (t == 256 && c->prec != UVMEM_FP64)) && c->np % t == 0)
             c->adj_tt = t;
     }
     c->adj_nt = c->np / c->adj_tt;
@@ -562,13 +569,15 @@ int finalize_impl(uvmem_ctx *c) {
                 if (umask[(size_t)i * n + j]) return true;
         return false;
     };
-    // ---- adjoint: split-K chunks.  Resident slots: 256 CUs x (1 workgroup,
-    // or 2 for the split kernel on 128 x 128 tiles).  A channel of Z_c
+    // ---- adjoint: split-K chunks.  Resident slots: 256 CUs x the workgroups
+    // of the context's adjoint kernel that fit on a CU at once (1 for the
+    // 512-thread 256 x 256 tiles, 2-3 for the 256-thread 128 x 128 and 64 x
+    // 64 tiles, from the compiled kernel's occupancy).  A channel of Z_c
     // visibilities is cut into ceil(Z_c / klen) equal chunks (multiples of 16)
     // and every chunk covers the used pixel tiles; the split kernel's chunks
     // are also bounded because it sums a chunk in FP32 only.
     const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
-    const int adj_slots = (split && c->adj_tt == 128) ? 512 : 256;
+    const int adj_slots = 256 * adjoint_wgs_per_cu(c);
     auto chunks_of = [&](int64_t nv, int64_t klen, int64_t &len) {
         const int64_t nch = (nv + klen - 1) / klen;
         len = nch ? ((nv + nch - 1) / nch + 15) / 16 * 16 : 0;

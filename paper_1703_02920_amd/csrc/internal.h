@@ -20,7 +20,7 @@ constexpr int NTHR = 256;
 constexpr int VIS_WGS = 1024;
 constexpr int PIX_WGS = 1024;
 // Minimum visibilities per adjoint split-K chunk (multiple of 16).
-constexpr int ADJ_KMIN = 256;
+constexpr int ADJ_KMIN = 64;
 // Maximum visibilities per split-K chunk of the split-precision adjoint,
 // whose chunk sums are FP32 only (bounds their rounding growth).
 constexpr int ADJ_KMAX_SPLIT = 32768;
@@ -109,8 +109,7 @@ enum {
 // Arrival counters of the per-image reductions finished by the last
 // workgroup to arrive ([CTR_N][nimg] unsigned, zero between launches).
 enum {
-    CTR_DIR = 0,     // k_cg_dir: gt . d
-    CTR_DIR2,        // k_cg_dir2: alpha_max and the entropy parts of phi', phi''
+    CTR_DIR = 0,     // k_cg_dir: gt . d, alpha_max and the entropy parts of phi', phi''
     CTR_VIS,         // k_cg_vis: a, b, phi'(alpha_max); line-search start
     CTR_LS,          // k_ls_step: phi', phi'' at the trial steps
     CTR_UPD,         // k_cg_update: S and chi^2 of the new image
@@ -253,6 +252,9 @@ hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st, i
 // grad != 0: a gradient, needed inside a focus region only (its own tiles
 // and split-K slot table).
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, int grad = 0);
+// Workgroups of that adjoint kernel resident on one CU at once (occupancy of
+// the compiled kernel; at least 1).
+int adjoint_wgs_per_cu(const uvmem_ctx *c);
 // Gridded forward model and its exact adjoint (k_grid.hip): the forward
 // writes the single forward partial vpart[0][k]; the adjoint writes the
 // channel's plane gpart[slot_base[c]] (one slot per channel).

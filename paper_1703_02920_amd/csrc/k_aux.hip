@@ -445,21 +445,32 @@ __global__ __launch_bounds__(NTHR) void k_cg_init(const R *__restrict__ I, const
     }
 }
 
-// Step 1: d <- -gt + beta d, projected onto the feasible directions at the
-// bound (d = 0 on the active set, d >= 0 on the other bound pixels); partial
-// gt . d.  The last workgroup of an image takes step 2: restart with d = -gt
-// when gt . d >= 0, stop when the projected gradient is zero.
+// Steps 1-3: d <- -gt + beta d, projected onto the feasible directions at the
+// bound (d = 0 on the active set, d >= 0 on the other bound pixels), stored
+// with B = A o d for the forward model; partials of gt . d and, for this
+// direction and for the restart direction -gt, of the entropy parts of
+// phi'(0) - b and phi''(0) - a and of alpha_max.  The last workgroup of an
+// image takes step 2: restart with d = -gt when gt . d >= 0 (it then rewrites
+// the image's d and B itself, which a restart alone needs), stop when the
+// projected gradient is zero; it keeps the chosen direction's totals and
+// starts the line search of an image that has no visibilities.
 template <typename R>
 __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const R *__restrict__ g,
                                                  const R *__restrict__ gt, R *__restrict__ dir,
+                                                 const R *__restrict__ beam, R *__restrict__ bop,
+                                                 const int *__restrict__ ichan_base,
                                                  const double *__restrict__ scal, double *__restrict__ chan,
-                                                 double *__restrict__ ppart, int n, int n_pb, int pb_len, double Mb,
-                                                 unsigned *__restrict__ ctr) {
+                                                 double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
+                                                 double M, double Mb, double lam, unsigned *__restrict__ ctr,
+                                                 const int *__restrict__ ivis_base, double *__restrict__ ls) {
     const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
     const long long npix = (long long)n * n;
     const double beta = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_BETA];
     const bool stop = chan[(size_t)c * CH_N + CH_STOP] != 0.0;
-    double acc[1] = {0.0};
+    const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
+    // [0] gt . d; entropy parts [1], [2] of d and [3], [4] of -gt
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double am_d = INFINITY, am_s = INFINITY;
     for (int r = 0; r < pb_len / NTHR; ++r) {
         const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
         if (p >= npix) break;
@@ -472,83 +483,60 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         if (stop) d = 0.0;
         const R dr = (R)d;
         dir[q] = dr;
-        acc[0] += gtv * (double)dr;
-    }
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) coh_store(ppart + ((size_t)c * n_pb + pb) * NPART + 0, acc[0]);
-    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
-    double gtd[1];
-    sum_partials<1>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, gtd);
-    if (threadIdx.x == 0) {
-        const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
-        double *ch = chan + (size_t)c * CH_N;
-        const bool restart = gtd[0] >= 0.0;
-        if (stop || gg == 0.0) ch[CH_STOP] = 1.0;
-        ch[CH_RESTART] = restart ? 1.0 : 0.0;
-        ch[CH_GTD] = restart ? -gg : gtd[0];
-        ch[CH_GG_OLD] = gg;
-    }
-}
-
-// Step 3: apply the restart, stage B = A o d for the forward model, and the
-// partials of alpha_max, phi'(0) - b and phi''(0) - a (entropy parts); the
-// last workgroup of an image stores their totals (and starts the line search
-// of an image that has no visibilities).
-template <typename R>
-__global__ __launch_bounds__(NTHR) void k_cg_dir2(const R *__restrict__ I, const R *__restrict__ gt,
-                                                  R *__restrict__ dir, const R *__restrict__ beam,
-                                                  R *__restrict__ bop, const int *__restrict__ ichan_base,
-                                                  double *__restrict__ chan,
-                                                  double *__restrict__ ppart, int n, int np, int n_pb, int pb_len,
-                                                  double M, double Mb, unsigned *__restrict__ ctr,
-                                                  const int *__restrict__ ivis_base, double *__restrict__ ls,
-                                                  double lam) {
-    const int c = blockIdx.x / n_pb, pb = blockIdx.x % n_pb;
-    const long long npix = (long long)n * n;
-    const double *chc = chan + (size_t)c * CH_N;
-    const bool stop = chc[CH_STOP] != 0.0;
-    const bool restart = chc[CH_RESTART] != 0.0;
-    const int ch0 = ichan_base[c], ch1 = ichan_base[c + 1];   // the channels that see this image
-    double amax = INFINITY;
-    double acc[2] = {0.0, 0.0};
-    for (int r = 0; r < pb_len / NTHR; ++r) {
-        const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
-        if (p >= npix) break;
-        const size_t q = (size_t)c * npix + p;
-        double d = restart ? -(double)gt[q] : (double)dir[q];
-        if (stop) d = 0.0;
-        const R dr = (R)d;
+        const int i = (int)(p / n), j = (int)(p % n);
+        for (int ch = ch0; ch < ch1; ++ch)
+            bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
         d = (double)dr;
+        const double s = stop ? 0.0 : -gtv;
+        const double lg = log(x / M) + 1.0;
+        acc[0] += gtv * d;
+        acc[1] += d * lg;
+        acc[2] += d * d / x;
+        acc[3] += s * lg;
+        acc[4] += s * s / x;
+        if (d < 0.0) am_d = fmin(am_d, (x - Mb) / (-d));
+        if (s < 0.0) am_s = fmin(am_s, (x - Mb) / (-s));
+    }
+    block_sum<5>(acc);
+    am_d = block_min(am_d);
+    am_s = block_min(am_s);
+    if (threadIdx.x == 0) {
+        double *pp = ppart + ((size_t)c * n_pb + pb) * NPART;
+        for (int m = 0; m < 5; ++m) coh_store(pp + m, acc[m]);
+        coh_store(pp + 5, am_d);
+        coh_store(pp + 6, am_s);
+    }
+    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
+    double t[5];
+    sum_partials<5>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, t);
+    const double am0 = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 5);
+    const double am1 = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 6);
+    const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
+    const bool restart = t[0] >= 0.0;
+    const bool stop_now = stop || gg == 0.0;
+    if (threadIdx.x == 0) {
+        double *ch = chan + (size_t)c * CH_N;
+        if (stop_now) ch[CH_STOP] = 1.0;
+        ch[CH_RESTART] = restart ? 1.0 : 0.0;
+        ch[CH_GTD] = restart ? -gg : t[0];
+        ch[CH_GG_OLD] = gg;
+        ch[CH_E1] = restart ? t[3] : t[1];
+        ch[CH_E2] = restart ? t[4] : t[2];
+        ch[CH_AMAX] = restart ? am1 : am0;
+        // no visibility workgroup will start this image's line search
+        if (ivis_base[c + 1] == ivis_base[c])
+            ls_init(ls + (size_t)c * LSS_N, 0.0, 0.0, lam * ch[CH_E1], lam * ch[CH_E2], ch[CH_AMAX], stop_now,
+                    false, 0.0, 0.0);
+    }
+    // a stopped image's direction is zero already (gt = 0 or stop)
+    if (!restart || stop_now) return;
+    for (long long p = threadIdx.x; p < npix; p += NTHR) {
+        const size_t q = (size_t)c * npix + p;
+        const R dr = (R)(-(double)gt[q]);
         dir[q] = dr;
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
             bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
-        const double x = (double)I[q];
-        if (d < 0.0) amax = fmin(amax, (x - Mb) / (-d));
-        acc[0] += d * (log(x / M) + 1.0);
-        acc[1] += d * d / x;
-    }
-    amax = block_min(amax);
-    block_sum<2>(acc);
-    if (threadIdx.x == 0) {
-        double *pp = ppart + ((size_t)c * n_pb + pb) * NPART;
-        coh_store(pp + 0, acc[0]);
-        coh_store(pp + 1, acc[1]);
-        coh_store(pp + 2, amax);
-    }
-    if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
-    double e[2];
-    sum_partials<2>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, e);
-    const double am = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 2);
-    if (threadIdx.x == 0) {
-        double *ch = chan + (size_t)c * CH_N;
-        ch[CH_E1] = e[0];
-        ch[CH_E2] = e[1];
-        ch[CH_AMAX] = am;
-        // no visibility workgroup will start this image's line search
-        if (ivis_base[c + 1] == ivis_base[c])
-            ls_init(ls + (size_t)c * LSS_N, 0.0, 0.0, lam * e[0], lam * e[1], am, ch[CH_STOP] != 0.0, false, 0.0,
-                    0.0);
     }
 }
 
@@ -992,13 +980,12 @@ template <typename R>
 hipError_t t_cg_phase(const uvmem_ctx *c, void *I, double *user, int phase, hipStream_t st) {
     const dim3 gp(pix_grid(c)), blk(NTHR);
     if (phase == 0) {
-        // 1-2. direction update and projection; restart test and stop
+        // 1-3. direction update and projection, restart test and stop, B = A o d,
+        // alpha_max and the entropy parts of phi'(0), phi''(0)
         hipLaunchKernelGGL(k_cg_dir<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_g), CP<R>(c->d_gt), P<R>(c->d_dir),
-                           c->d_scal, c->d_chan, pp(c, 1), c->n, c->n_pb, c->pix_blk, c->Mb, ctr(c, CTR_DIR));
-        // 3. restart applied, B = A o d, alpha_max and entropy parts of phi'(0), phi''(0)
-        hipLaunchKernelGGL(k_cg_dir2<R>, gp, blk, 0, st, CP<R>(I), CP<R>(c->d_gt), P<R>(c->d_dir),
-                           CP<R>(c->d_beam), P<R>(c->d_bop), c->d_ichan_base, c->d_chan, pp(c, 1), c->n, c->np,
-                           c->n_pb, c->pix_blk, c->M, c->Mb, ctr(c, CTR_DIR2), c->d_ivis_base, c->d_ls, c->lam);
+                           CP<R>(c->d_beam), P<R>(c->d_bop), c->d_ichan_base, c->d_scal, c->d_chan, pp(c, 1), c->n,
+                           c->np, c->n_pb, c->pix_blk, c->M, c->Mb, c->lam, ctr(c, CTR_DIR), c->d_ivis_base,
+                           c->d_ls);
         return hipGetLastError();
     }
     if (phase == 1) {

@@ -1450,6 +1450,17 @@ hipError_t fwd_dispatch(const uvmem_ctx *c, const void *bop, hipStream_t st, con
                                (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
             return hipGetLastError();
         }
+    } else {
+        if (c->ib_rows == 64 && c->jb_cols == 256) {
+            hipLaunchKernelGGL((k_forward_p<T, 64, 256>), grid, blk, 0, st, items, c->d_a, c->d_b,
+                               (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+            return hipGetLastError();
+        }
+        if (c->ib_rows == 64 && c->jb_cols == 128) {
+            hipLaunchKernelGGL((k_forward_p<T, 64, 128>), grid, blk, 0, st, items, c->d_a, c->d_b,
+                               (const T *)bop, c->d_vpart, c->n, c->np, (long long)c->ztot);
+            return hipGetLastError();
+        }
     }
     hipLaunchKernelGGL((k_forward_p<T, 64, 64>), grid, blk, 0, st, items, c->d_a, c->d_b, (const T *)bop,
                        c->d_vpart, c->n, c->np, (long long)c->ztot);
@@ -1547,6 +1558,35 @@ hipError_t launch_forward(const uvmem_ctx *c, const void *bop, hipStream_t st, i
     if (c->prec == UVMEM_BF16X3) return fwd_h16<__bf16>(c, bop, st, it, ni);
     if (c->prec == UVMEM_FP16X3) return fwd_h16<_Float16>(c, bop, st, it, ni);
     return fwd_dispatch<float>(c, bop, st, it, ni);
+}
+
+// Workgroups of the adjoint kernel that this context launches which fit on
+// one CU at once (registers, LDS and waves of the compiled kernel), at
+// least 1.
+int adjoint_wgs_per_cu(const uvmem_ctx *c) {
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    const bool split = c->prec == UVMEM_BF16X3 || c->prec == UVMEM_FP16X3;
+    if (split) {
+        if (c->adj_tt == 256)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint_h16s<__bf16>, 512, 0);
+        else if (c->adj_tt == 128)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint_h16<__bf16, 64>, 256, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint_h16<__bf16, 32>, 256, 0);
+    } else if (c->prec == UVMEM_FP64) {
+        if (c->adj_tt == 128)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<double, 64>, 256, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<double, 32>, 256, 0);
+    } else if (c->adj_tt == 256) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint_w<true>, 512, 0);
+    } else if (c->adj_tt == 128) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<float, 64>, 256, 0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adjoint<float, 32>, 256, 0);
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_adjoint(const uvmem_ctx *c, const double2 *coef, const float *w, hipStream_t st, int grad) {

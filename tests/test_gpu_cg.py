@@ -211,3 +211,40 @@ def test_domain_flag_and_errors():
     assert ei.value.code == EINVAL and "cycles per pixel" in str(ei.value)
     u[7] = 4095.0 / prob.cell
     c2.set_uv(0, u, ch["v"], prob.cell)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_restart_when_direction_is_not_descent(prec):
+    """The CG's restart (steepest descent when the projected direction does
+    not descend, R13): a checkpoint whose direction is +gt with beta = 1 makes
+    the next direction -gt + gt = 0, so gt . d = 0 >= 0 and the step must
+    restart with d = -gt.  That is the direction of the first step after
+    cg_init (d = -gt, beta = 0), so both steps give the same bits."""
+    import struct
+    from paper_1703_02920_amd.uvmem import S_BETA
+    _cuda()
+    ds = synth.make_config(1)
+    flush(f"restart path c1 {prec}")
+    prob = Problem.from_dataset(ds)
+    ctx = prob.context(prec)
+    I = ctx.image()
+    ctx.cg_init(I, init_to_floor=True)
+    blob = bytearray(ctx.get_state())
+    I0 = I.clone()
+    s_a = ctx.cg_step(I).clone()
+    I_a = I.clone()
+    # blob: 48-byte header, d, gt, g (n_img x N x N of the real type),
+    # R (complex128 per visibility), scalars, CG flags (uvmem.h)
+    hdr, elem = 48, (8 if prec == "fp64" else 4)
+    img = prob.n_chan * ds.n * ds.n * elem
+    ztot = sum(len(ch["u"]) for ch in prob.chans)
+    blob[hdr:hdr + img] = blob[hdr + img:hdr + 2 * img]          # d := +gt
+    struct.pack_into("=d", blob, hdr + 3 * img + 16 * ztot + 8 * S_BETA, 1.0)
+    I.copy_(I0)
+    ctx.set_state(bytes(blob))
+    s_b = ctx.cg_step(I).clone()
+    ctx.check()
+    flush(f"  plain first step phi {float(s_a[0, 0]):.12e}, restarted {float(s_b[0, 0]):.12e}")
+    assert float(s_a[0, 3]) > 0.0
+    assert torch.equal(I, I_a)
+    assert torch.equal(s_a, s_b)
