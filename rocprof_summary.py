@@ -195,8 +195,11 @@ def counters(args):
          lambda k: ratio(k, "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", 8.0 / 1024.0)),
         ("co-executing share of MFMA busy: SQ_VALU_MFMA_COEXEC_CYCLES / SQ_VALU_MFMA_BUSY_CYCLES",
          lambda k: ratio(k, "SQ_VALU_MFMA_COEXEC_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES")),
-        ("vector instructions per matrix instruction: SQ_INSTS_VALU / SQ_INSTS_MFMA",
+        ("vector instructions per matrix instruction, the matrix one included: SQ_INSTS_VALU / SQ_INSTS_MFMA",
          lambda k: ratio(k, "SQ_INSTS_VALU", "SQ_INSTS_MFMA")),
+        ("other vector instructions per matrix instruction: (SQ_INSTS_VALU - SQ_INSTS_MFMA) / SQ_INSTS_MFMA",
+         lambda k: (f"{med[k]['SQ_INSTS_VALU'] / med[k]['SQ_INSTS_MFMA'] - 1.0:.3f}"
+                    if med[k].get("SQ_INSTS_MFMA") else "")),
         ("LDS instructions per matrix instruction: SQ_INSTS_LDS / SQ_INSTS_MFMA",
          lambda k: ratio(k, "SQ_INSTS_LDS", "SQ_INSTS_MFMA")),
     ]
