@@ -233,7 +233,7 @@ int build_layout(uvmem_ctx *c) {
     c->ztot = c->off[C];
     // pixel and visibility kernels: about PIX_WGS / VIS_WGS workgroups in
     // all (enough to spread the streaming over the CUs; few enough that the
-    // per-channel partial sums each workgroup recomputes stay short)
+    // last workgroup of an image sums a short list of partial records)
     auto roundup = [](int64_t x, int64_t m) { return ((x + m - 1) / m) * m; };
     int64_t pix_wgs = PIX_WGS, vis_wgs = VIS_WGS;
     if (const char *env = std::getenv("UVMEM_PIX_WGS")) pix_wgs = std::max(1L, std::atol(env));

@@ -213,20 +213,28 @@ def test_domain_flag_and_errors():
     c2.set_uv(0, u, ch["v"], prob.cell)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_restart_when_direction_is_not_descent(prec):
+@pytest.mark.parametrize("case", ["c1-fp64", "c1-fp32", "cube3-fp32", "shared3-fp32", "shared3-bf16x3"])
+def test_restart_when_direction_is_not_descent(case):
     """The CG's restart (steepest descent when the projected direction does
     not descend, R13): a checkpoint whose direction is +gt with beta = 1 makes
     the next direction -gt + gt = 0, so gt . d = 0 >= 0 and the step must
     restart with d = -gt.  That is the direction of the first step after
-    cg_init (d = -gt, beta = 0), so both steps give the same bits."""
+    cg_init (d = -gt, beta = 0), so both steps give the same bits.  Cases:
+    the 64^2 workload, and three uneven channels (96^2) as three images or
+    one shared image (the restart rewrites every channel's B = A o d)."""
     import struct
-    from paper_1703_02920_amd.uvmem import S_BETA
+    from paper_1703_02920_amd.uvmem import NSCAL, S_BETA
     _cuda()
-    ds = synth.make_config(1)
-    flush(f"restart path c1 {prec}")
-    prob = Problem.from_dataset(ds)
-    ctx = prob.context(prec)
+    name, prec = case.split("-")
+    flush(f"restart path {case}")
+    if name == "c1":
+        ds = synth.make_config(1)
+        prob, mode = Problem.from_dataset(ds), "cube"
+    else:
+        prob = Problem.random(96, [1500, 700, 2300], seed=37)
+        mode = "shared" if name.startswith("shared") else "cube"
+    n_img = 1 if mode == "shared" else prob.n_chan
+    ctx = prob.context(prec, mode=mode)
     I = ctx.image()
     ctx.cg_init(I, init_to_floor=True)
     blob = bytearray(ctx.get_state())
@@ -236,15 +244,16 @@ def test_restart_when_direction_is_not_descent(prec):
     # blob: 48-byte header, d, gt, g (n_img x N x N of the real type),
     # R (complex128 per visibility), scalars, CG flags (uvmem.h)
     hdr, elem = 48, (8 if prec == "fp64" else 4)
-    img = prob.n_chan * ds.n * ds.n * elem
+    img = n_img * prob.n * prob.n * elem
     ztot = sum(len(ch["u"]) for ch in prob.chans)
     blob[hdr:hdr + img] = blob[hdr + img:hdr + 2 * img]          # d := +gt
-    struct.pack_into("=d", blob, hdr + 3 * img + 16 * ztot + 8 * S_BETA, 1.0)
+    for m in range(n_img):                                        # beta := 1
+        struct.pack_into("=d", blob, hdr + 3 * img + 16 * ztot + 8 * (m * NSCAL + S_BETA), 1.0)
     I.copy_(I0)
     ctx.set_state(bytes(blob))
     s_b = ctx.cg_step(I).clone()
     ctx.check()
     flush(f"  plain first step phi {float(s_a[0, 0]):.12e}, restarted {float(s_b[0, 0]):.12e}")
-    assert float(s_a[0, 3]) > 0.0
+    assert bool((s_a[:, 3] > 0.0).all())
     assert torch.equal(I, I_a)
     assert torch.equal(s_a, s_b)
