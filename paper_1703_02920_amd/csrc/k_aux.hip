@@ -55,6 +55,9 @@ __device__ __forceinline__ double block_min(double v) {
 __device__ __forceinline__ void coh_store(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void coh_store(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ double coh_load(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -482,10 +485,13 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         else if (atb) d = fmax(d, 0.0);
         if (stop) d = 0.0;
         const R dr = (R)d;
-        dir[q] = dr;
+        // device-coherent stores: a restart rewrites these pixels from the
+        // last workgroup, which may run on another chiplet, and no cache may
+        // keep an older copy to write back after it
+        coh_store(dir + q, dr);
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
-            bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
+            coh_store(bop + (size_t)ch * np * np + (size_t)i * np + j, beam[(size_t)ch * npix + p] * dr);
         d = (double)dr;
         const double s = stop ? 0.0 : -gtv;
         const double lg = log(x / M) + 1.0;
@@ -533,10 +539,10 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
     for (long long p = threadIdx.x; p < npix; p += NTHR) {
         const size_t q = (size_t)c * npix + p;
         const R dr = (R)(-(double)gt[q]);
-        dir[q] = dr;
+        coh_store(dir + q, dr);
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
-            bop[(size_t)ch * np * np + (size_t)i * np + j] = beam[(size_t)ch * npix + p] * dr;
+            coh_store(bop + (size_t)ch * np * np + (size_t)i * np + j, beam[(size_t)ch * npix + p] * dr);
     }
 }
 
