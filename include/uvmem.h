@@ -40,8 +40,9 @@
  *    the concatenation of the channels in channel order.
  *  - Hot entry points (phi_and_grad, forward, adjoint, cg_step, cg_run) only
  *    enqueue work on the context's stream and never synchronise; the
- *    results are valid once that stream has reached them.  They allocate
- *    nothing: uvmem_finalize allocates every buffer.
+ *    results are valid once that stream has reached them.  They allocate no
+ *    buffers: uvmem_finalize allocates every one (cg_run's first graph
+ *    capture on an image leaves the instantiation to the HIP runtime).
  */
 #ifndef UVMEM_H
 #define UVMEM_H
@@ -237,7 +238,11 @@ int uvmem_fit_beam(uvmem_ctx *ctx, const void *psf_dev, double *bmaj, double *bm
  * search stalls (no descent, or zero projected gradient) stops: later steps
  * leave it unchanged.  cg_run performs `iters` steps, writing scalars to
  * scal_hist_dev (double[iters][n_img][UVMEM_NSCAL], may be NULL); with
- * use_graph != 0 it replays one step captured as a HIP graph. */
+ * use_graph != 0 it replays one step captured as a HIP graph.  The first
+ * use_graph call on an image captures that step on a stream the context
+ * owns and instantiates the graph (the HIP runtime allocates the executable
+ * graph there); later calls only launch it on the context's stream.  No
+ * call synchronises. */
 int uvmem_cg_init(uvmem_ctx *ctx, void *I_dev, int init_to_floor);
 int uvmem_cg_step(uvmem_ctx *ctx, void *I_dev, double *scal_dev);
 int uvmem_cg_run(uvmem_ctx *ctx, void *I_dev, int iters, double *scal_hist_dev, int use_graph);
