@@ -228,18 +228,45 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
     const long long nfull = ntiles / stride * stride;
     const bool share = NT == 8 && ntiles > nfull && (ntiles - nfull + it.nwg - 1) / it.nwg <= 2;
     const long long tend = share ? nfull : ntiles;
+    // the coordinates a tile needs, loaded one tile ahead: the eight waves
+    // reach their tile boundaries together, so a load issued at the boundary
+    // would stall them all at once
+    constexpr int NCO = 16 * NT / 64;   // coarse-table entries per lane
+    static_assert(16 * NT % 64 == 0, "image blocks of 64 or 128 rows");
+    struct TileK {
+        double ak, bco[NCO], br[4];
+    };
+    auto load_k = [&](long long tile, TileK &tk) {
+        const long long k0 = it.kbeg + 16 * tile;
+        const long long nv = it.kend - k0;   // <= 0 past the last tile
+        tk.ak = q < nv ? a[k0 + q] : 0.0;
+#pragma unroll
+        for (int m = 0; m < NCO; ++m) {
+            const int kk = (lane + 64 * m) / NT;
+            tk.bco[m] = kk < nv ? b[k0 + kk] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kk = Mfma<T>::drow(g, r);
+            tk.br[r] = kk < nv ? b[k0 + kk] : 0.0;
+        }
+    };
+    TileK cur;
+    load_k((long long)wave * it.nwg + it.wg, cur);
     for (long long tile = (long long)wave * it.nwg + it.wg; tile < tend; tile += stride) {
         const long long k0 = it.kbeg + 16 * tile;
         const int nvalid = (int)(it.kend - k0 < 16 ? it.kend - k0 : 16);
-        const double ak = q < nvalid ? a[k0 + q] : 0.0;
+        const TileK tk = cur;
+        load_k(tile + stride, cur);
         acc_t accR[NT], accI[NT];
-        fwd_contract<T, NT, JB>(sB, 0, ak, j0, half, q, g, accR, accI);
+        fwd_contract<T, NT, JB>(sB, 0, tk.ak, j0, half, q, g, accR, accI);
         // per-wave coarse factors E(16 b_k t) of the tile's 16 rows
-        for (int e = lane; e < 16 * NT; e += 64) {
+#pragma unroll
+        for (int m = 0; m < NCO; ++m) {
+            const int e = lane + 64 * m;
             const int kk = e / NT, t = e % NT;
-            const double bk = kk < nvalid ? b[k0 + kk] : 0.0;
             T c, sn;
-            cisphase(bk, 16 * t, c, sn);
+            cisphase(tk.bco[m], 16 * t, c, sn);
             sCo[wave][kk][t] = make_double2((double)c, (double)sn);
         }
         __builtin_amdgcn_wave_barrier();
@@ -248,7 +275,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_p(const FwdPItem *__restrict
         for (int r = 0; r < 4; ++r) {
             const int kk = Mfma<T>::drow(g, r);
             const bool ok = kk < nvalid;
-            const double bk = ok ? b[k0 + kk] : 0.0;
+            const double bk = tk.br[r];
             T fcq, fsq;
             cisphase(bk, i0 + q - half, fcq, fsq);
             // conj(E_v) T = conj(fine) sum_t conj(coarse_t) T_t, in FP64
@@ -1070,6 +1097,9 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_h16(const AdjItem *__restric
 // The operand rows of step s + 1 and the tables of step s + 2 are formed
 // while the matrix cores contract step s: operands and tables are
 // double-buffered in LDS, so one workgroup barrier per step orders them.
+// The visibility data of a table step are loaded three steps ahead (held in
+// registers for a whole step) and the tables are formed last in the step,
+// which covers the latency of loads that miss the caches.
 // Chunk sums are FP32 and the partial tile is stored in FP32.
 template <typename H>
 __global__ __launch_bounds__(512, 1) void k_adjoint_h16s(const AdjItem *__restrict__ items,
@@ -1191,14 +1221,16 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16s(const AdjItem *__restri
 
     const long long kb0 = it.kbeg;
     const int nsteps = (int)((it.kend - it.kbeg + KV - 1) / KV);
-    Pre pre;
+    Pre pre, pre2;
     fetch(kb0, pre);
     gen(0, pre);
     fetch(kb0 + KV, pre);
+    fetch(kb0 + 2 * KV, pre2);
     __syncthreads();
     form_half(0, 0, 0);
     form_half(0, 0, 1);
     gen(1, pre);
+    pre = pre2;
     __syncthreads();
     // One basic block per step (no branches), so that the scheduler can
     // spread the operand formation of step s + 1 and the table work of step
@@ -1207,7 +1239,7 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16s(const AdjItem *__restri
     // never read again.
     for (int s = 0; s < nsteps; ++s) {
         const int ob = s & 1;
-        fetch(kb0 + (long long)(s + 2) * KV, pre);
+        fetch(kb0 + (long long)(s + 3) * KV, pre2);
         // E fragments of this wave's four column blocks
         h8 eh[NCB], el[NCB];
 #pragma unroll
@@ -1239,9 +1271,10 @@ __global__ __launch_bounds__(512, 1) void k_adjoint_h16s(const AdjItem *__restri
 #pragma unroll
             for (int y = 0; y < NCB; ++y) acc[x][y] = Half16<H>::mma(cl, eh[y], acc[x][y]);
             if (x == 1) form_half(ob ^ 1, ob ^ 1, 0);
-            if (x == 3) gen(ob, pre);
-            if (x == 5) form_half(ob ^ 1, ob ^ 1, 1);
+            if (x == 4) form_half(ob ^ 1, ob ^ 1, 1);
+            if (x == 7) gen(ob, pre);
         }
+        pre = pre2;
         __syncthreads();
     }
     float *out = gpart + (size_t)it.slot * np * np;
