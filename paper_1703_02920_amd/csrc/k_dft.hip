@@ -1385,16 +1385,19 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restr
     // tile wave * nwg + wg of each round: a round's leftover tiles go to one
     // wave of distinct workgroups, so no CU carries them on all its SIMDs
     const long long stride = 8LL * it.nwg;
-    for (long long tile = (long long)wave * it.nwg + it.wg; tile < ntiles; tile += stride) {
-        const long long k0 = it.kbeg + TV * tile;
-        const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
-        const bool ok = l32 < nvalid;
-        const double ak = ok ? a[k0 + l32] : 0.0;
-        const double bk = ok ? b[k0 + l32] : 0.0;
+    // With at most two leftover tiles per workgroup after the full rounds,
+    // the eight waves share each leftover tile, a 1/8 of its columns each
+    // (one wave alone would keep one SIMD busy for a whole tile after the
+    // others have finished); the eight partial visibilities are added in
+    // wave order.
+    const long long nfull = ntiles / stride * stride;
+    const bool share = KSTEPS % 8 == 0 && ntiles > nfull && (ntiles - nfull + it.nwg - 1) / it.nwg <= 2;
+    const long long tend = share ? nfull : ntiles;
+    // T[k][i] over the column steps [ks0, ks1) of the lane's visibility
+    auto contract = [&](double ak, int ks0, int ks1, floatx16 (&accR)[NT], floatx16 (&accI)[NT]) {
         float fc[8], fs[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) cis2pi_hw((float)phase(ak, e), fc[e], fs[e]);
-        floatx16 accR[NT], accI[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -1403,7 +1406,7 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restr
                 accI[t][r] = 0.f;
             }
 #pragma unroll 2
-        for (int ks = 0; ks < KSTEPS; ++ks) {
+        for (int ks = ks0; ks < ks1; ++ks) {
             // twiddles of columns j0 + 16 ks + 8 h + e: E(a_k (j0 + 16 ks + 8 h - N/2)) E(a_k e)
             float cc, sc;
             cis2pi_hw((float)phase(ak, j0 + 16 * ks + 8 * hk - half), cc, sc);
@@ -1429,7 +1432,11 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restr
                 accI[t] = Half32<H>::mma(bl, uh, accI[t]);
             }
         }
-        // row dot of the lane's visibility over its 64 rows
+    };
+    // row dot of the lane's visibility over its 64 rows, the two lanes of a
+    // visibility added (unscaled)
+    auto row_dot = [&](double bk, const floatx16 (&accR)[NT], const floatx16 (&accI)[NT], double &vr,
+                       double &vi) {
         float f1c[4], f1s[4], f2c[4], f2s[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1461,10 +1468,48 @@ __global__ __launch_bounds__(512, 1) void k_forward_h16m(const FwdPItem *__restr
             wi = ti + c32 * wi - s32 * wr;
             wr = nr;
         }
-        double vr = (double)(cb * wr + sb * wi), vi = (double)(cb * wi - sb * wr);
+        vr = (double)(cb * wr + sb * wi);
+        vi = (double)(cb * wi - sb * wr);
         vr += __shfl_xor(vr, 32, 64);
         vi += __shfl_xor(vi, 32, 64);
+    };
+    for (long long tile = (long long)wave * it.nwg + it.wg; tile < tend; tile += stride) {
+        const long long k0 = it.kbeg + TV * tile;
+        const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
+        const bool ok = l32 < nvalid;
+        const double ak = ok ? a[k0 + l32] : 0.0;
+        const double bk = ok ? b[k0 + l32] : 0.0;
+        floatx16 accR[NT], accI[NT];
+        contract(ak, 0, KSTEPS, accR, accI);
+        double vr, vi;
+        row_dot(bk, accR, accI, vr, vi);
         if (hk == 0 && ok) vpart[(size_t)it.part * ztot + k0 + l32] = make_double2(vr * unscale, vi * unscale);
+    }
+    if (!share) return;
+    __shared__ double2 sSl[8][TV];
+    constexpr int KPW = KSTEPS / 8;   // column steps per wave
+    for (long long tile = nfull + it.wg; tile < ntiles; tile += it.nwg) {
+        const long long k0 = it.kbeg + TV * tile;
+        const int nvalid = (int)(it.kend - k0 < TV ? it.kend - k0 : TV);
+        const bool ok = l32 < nvalid;
+        const double ak = ok ? a[k0 + l32] : 0.0;
+        const double bk = ok ? b[k0 + l32] : 0.0;
+        floatx16 accR[NT], accI[NT];
+        contract(ak, KPW * wave, KPW * (wave + 1), accR, accI);
+        double vr, vi;
+        row_dot(bk, accR, accI, vr, vi);
+        if (hk == 0) sSl[wave][l32] = make_double2(vr, vi);
+        __syncthreads();
+        if (tid < nvalid) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                sr += sSl[w][tid].x;
+                si += sSl[w][tid].y;
+            }
+            vpart[(size_t)it.part * ztot + k0 + tid] = make_double2(sr * unscale, si * unscale);
+        }
+        __syncthreads();
     }
 }
 
