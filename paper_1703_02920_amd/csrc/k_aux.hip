@@ -167,18 +167,51 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
     double cmax = 0.0;   // max |Re|, |Im| of the adjoint's coefficients w R (mode 4: R alone)
     constexpr int U = 2;   // visibilities per thread and round, loads issued together
     for (long long k0 = it.kbeg; k0 < it.kend; k0 += U * NTHR) {
+        // the loads that do not depend on the forward partials are issued
+        // first, then every block's partials (four blocks in flight), which
+        // are summed in block order; indices past the item's end are clamped
+        // and null arrays replaced by the partials, so that no load sits
+        // behind a branch (values loaded that way are never used)
+        const double2 *anyv = vpart ? vpart : R;
+        const float *wsrc = w ? w : reinterpret_cast<const float *>(anyv);
+        const double2 *lsrc = mode == 1 ? vo : mode >= 2 ? R : anyv;
+        const double2 *l2src = mode == 3 ? Vd : anyv;
+        double ww[U];
+        double2 ld[U], ld2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long k = k0 + threadIdx.x + (long long)u * NTHR;
+            const long long kc = k < it.kend ? k : it.kend - 1;
+            const float wr = wsrc[kc];
+            ww[u] = w ? (double)wr : 1.0;
+            ld[u] = lsrc[kc];
+            ld2[u] = l2src[kc];
+        }
         double2 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = make_double2(0.0, 0.0);
         if (mode < 3) {
-            for (int ib = 0; ib < n_parts; ++ib) {
+            constexpr int PB = 4;
+            for (int ib0 = 0; ib0 < n_parts; ib0 += PB) {
+                double2 pv[PB][U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const long long k = k0 + threadIdx.x + (long long)u * NTHR;
-                    if (k < it.kend) {
-                        const double2 p = vpart[(size_t)ib * ztot + k];
-                        v[u].x += p.x;
-                        v[u].y += p.y;
+                for (int b = 0; b < PB; ++b)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const long long k = k0 + threadIdx.x + (long long)u * NTHR;
+                        const long long kc = k < it.kend ? k : it.kend - 1;
+                        const int ibc = ib0 + b < n_parts ? ib0 + b : n_parts - 1;
+                        pv[b][u] = vpart[(size_t)ibc * ztot + kc];
+                    }
+                // blocks past the last add -0.0, an exact identity (no branch
+                // between the loads and the sums)
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    const bool okb = ib0 + b < n_parts;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        v[u].x += okb ? pv[b][u].x : -0.0;
+                        v[u].y += okb ? pv[b][u].y : -0.0;
                     }
                 }
             }
@@ -187,31 +220,31 @@ __device__ __forceinline__ void vis_item(const VisItem it, int item, const doubl
         for (int u = 0; u < U; ++u) {
             const long long k = k0 + threadIdx.x + (long long)u * NTHR;
             if (k >= it.kend) continue;
-            const double ww = w ? (double)w[k] : 1.0;
+            const double wv = ww[u];
             if (mode == 0) {
                 out[k] = v[u];
             } else if (mode == 1) {
-                const double2 o = vo[k];
+                const double2 o = ld[u];
                 const double2 r = make_double2(v[u].x - (double)o.x, v[u].y - (double)o.y);
                 R[k] = r;
-                acc[0] += ww * (r.x * r.x + r.y * r.y);
-                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+                acc[0] += wv * (r.x * r.x + r.y * r.y);
+                cmax = fmax(cmax, wv * fmax(fabs(r.x), fabs(r.y)));
             } else if (mode == 2) {
                 Vd[k] = v[u];
-                const double2 r = R[k];
-                acc[0] += ww * (v[u].x * v[u].x + v[u].y * v[u].y);
-                acc[1] += ww * (r.x * v[u].x + r.y * v[u].y);
+                const double2 r = ld[u];
+                acc[0] += wv * (v[u].x * v[u].x + v[u].y * v[u].y);
+                acc[1] += wv * (r.x * v[u].x + r.y * v[u].y);
             } else if (mode == 3) {
-                const double2 d = Vd[k];
-                double2 r = R[k];
+                const double2 d = ld2[u];
+                double2 r = ld[u];
                 r.x += alpha * d.x;
                 r.y += alpha * d.y;
                 R[k] = r;
-                acc[0] += ww * (r.x * r.x + r.y * r.y);
-                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+                acc[0] += wv * (r.x * r.x + r.y * r.y);
+                cmax = fmax(cmax, wv * fmax(fabs(r.x), fabs(r.y)));
             } else {
-                const double2 r = R[k];
-                cmax = fmax(cmax, ww * fmax(fabs(r.x), fabs(r.y)));
+                const double2 r = ld[u];
+                cmax = fmax(cmax, wv * fmax(fabs(r.x), fabs(r.y)));
             }
         }
     }
@@ -295,6 +328,25 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
             const long long pc = okp[r] ? p : 0;
             off[r] = (size_t)(pc / n) * np + (size_t)(pc % n);
         }
+        // per-pixel inputs of the epilogue and the first channel's beam,
+        // loaded ahead of the slot sums, unconditionally (from a stand-in
+        // array where one is absent or unused, so that no load sits behind a
+        // branch; such values are never used)
+        const R *Isrc = mode == 1 || mode == 2 ? I : gt;
+        const unsigned char *msrc = mask ? mask : reinterpret_cast<const unsigned char *>(gt);
+        const size_t bbase = (size_t)(ch0 < ch1 ? ch0 : 0) * npix;
+        R xI[RP], xgt[RP], bm0[RP];
+        unsigned char mk[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
+            const long long pc = okp[r] ? p : 0;
+            const size_t q = (size_t)c * npix + pc;
+            xI[r] = Isrc[q];
+            xgt[r] = gt[q];
+            mk[r] = msrc[q];
+            bm0[r] = beam[bbase + pc];
+        }
         // grad chi^2 = sum over the image's channels of A_ch o (sum of the
         // channel's slots)
         double AG[RP];
@@ -333,7 +385,8 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
 #pragma unroll
             for (int r = 0; r < RP; ++r) {
                 const long long p = (long long)pb * pb_len + g0 + r * NTHR + threadIdx.x;
-                if (okp[r]) AG[r] += (mode == 3 ? 1.0 : (double)beam[(size_t)ch * npix + p]) * Gs[r];
+                const double A = mode == 3 ? 1.0 : ch == ch0 ? (double)bm0[r] : (double)beam[(size_t)ch * npix + p];
+                if (okp[r]) AG[r] += A * Gs[r];
             }
         }
 #pragma unroll
@@ -344,17 +397,17 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
             double gv = AG[r];
             if (mode == 3) gv *= img_scale[c];
             if (mode == 1 || mode == 2) {
-                const double x = (double)I[q];
+                const double x = (double)xI[r];
                 gv += lam * (log(x / M) + 1.0);
-                if (mask && !mask[q]) gv = 0.0;
+                if (mask && !mk[r]) gv = 0.0;
             }
             const R gr = (R)gv;
             out[q] = gr;
             if (mode == 2) {
-                const double x = (double)I[q];
+                const double x = (double)xI[r];
                 const bool act = (x <= Mb * (1.0 + BOUND_TOL)) && ((double)gr > 0.0);
                 const double gnew = act ? 0.0 : (double)gr;
-                const double gold = (double)gt[q];
+                const double gold = (double)xgt[r];
                 gt[q] = (R)gnew;
                 acc[0] += gnew * gnew;
                 acc[1] += gnew * gold;
@@ -479,6 +532,9 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         if (p >= npix) break;
         const size_t q = (size_t)c * npix + p;
         const double x = (double)I[q], gv = (double)g[q], gtv = (double)gt[q];
+        // the first channel's beam with the other loads (the stores below
+        // would otherwise hold it back)
+        const R bm0 = ch0 < ch1 ? beam[(size_t)ch0 * npix + p] : R(0);
         double d = -gtv + beta * (double)dir[q];
         const bool atb = x <= Mb * (1.0 + BOUND_TOL);
         if (atb && gv > 0.0) d = 0.0;
@@ -491,7 +547,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
         coh_store(dir + q, dr);
         const int i = (int)(p / n), j = (int)(p % n);
         for (int ch = ch0; ch < ch1; ++ch)
-            coh_store(bop + (size_t)ch * np * np + (size_t)i * np + j, beam[(size_t)ch * npix + p] * dr);
+            coh_store(bop + (size_t)ch * np * np + (size_t)i * np + j,
+                      (ch == ch0 ? bm0 : beam[(size_t)ch * npix + p]) * dr);
         d = (double)dr;
         const double s = stop ? 0.0 : -gtv;
         const double lg = log(x / M) + 1.0;
@@ -746,19 +803,24 @@ __global__ __launch_bounds__(NTHR) void k_cg_vis(const VisItem *__restrict__ ite
         const int blk = (int)blockIdx.x - n_visit;
         img = blk / n_pb;
         const int pb = blk % n_pb;
+        const long long npix = (long long)n * n;
+        // the thread's first pixel, loaded ahead of the image's scalars
+        // (pixel 0 stands in past the end)
+        const long long p_1 = (long long)pb * pb_len + threadIdx.x;
+        const size_t q_1 = (size_t)img * npix + (p_1 < npix ? p_1 : 0);
+        const R d_1 = dir[q_1], x_1 = I[q_1];
         if (ivis_base[img + 1] == ivis_base[img]) return;   // started by the direction pass
         const double *chc = chan + (size_t)img * CH_N;
         const double am = chc[CH_AMAX];
         double acc[2] = {0.0, 0.0};
         if (isfinite(am) && chc[CH_STOP] == 0.0) {
-            const long long npix = (long long)n * n;
             for (int r = 0; r < pb_len / NTHR; ++r) {
                 const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
                 if (p >= npix) break;
                 const size_t q = (size_t)img * npix + p;
-                const double d = (double)dir[q];
+                const double d = r == 0 ? (double)d_1 : (double)dir[q];
                 if (d == 0.0) continue;
-                const double x = (double)I[q] + am * d;
+                const double x = (r == 0 ? (double)x_1 : (double)I[q]) + am * d;
                 acc[0] += d * (log(x / M) + 1.0);
                 acc[1] += d * d / x;
             }
@@ -870,13 +932,13 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
             const long long p = (long long)pb * pb_len + r * NTHR + threadIdx.x;
             if (p >= npix) break;
             const size_t q = (size_t)c * npix + p;
-            double x = (double)I[q];
-            if (al != 0.0) {
-                x = fmax(x + al * (double)dir[q], Mb);
-                const R xr = (R)x;
-                I[q] = xr;
-                x = (double)xr;
-            }
+            // I and d are loaded together, before the step is known (selects,
+            // not a branch, so that the load of d is not deferred behind it)
+            const double x0 = (double)I[q], dv = (double)dir[q];
+            const R xr = (R)fmax(x0 + al * dv, Mb);
+            const bool moved = al != 0.0;
+            double x = moved ? (double)xr : x0;
+            if (moved) I[q] = xr;
             if (!(x > 0.0)) bad = 1;
             else acc[0] += x * log(x / M);
         }
