@@ -76,10 +76,60 @@ __device__ __forceinline__ void sum_partials(const double *base, int n_items, in
     block_sum<K>(out);
 }
 
-__device__ __forceinline__ double min_partials(const double *base, int n_items, int s) {
-    double m = INFINITY;
-    for (int it = threadIdx.x; it < n_items; it += NTHR) m = fmin(m, coh_load(base + (size_t)it * NPART + s));
-    return block_min(m);
+// Two record sets in one pass, their loads issued together (one memory round
+// trip instead of two): slots [s0, s0 + K) of na records at `a` and slots
+// [s1, s1 + L) of nb records at `b`, each summed in index order exactly as
+// sum_partials does.  Past a set's end a thread reads a stand-in record of
+// the other set (never of an empty one) and adds -0.0, an exact identity.
+template <int K, int L>
+__device__ __forceinline__ void sum_partials2(const double *a, int na, int s0, double (&oa)[K], const double *b,
+                                              int nb, int s1, double (&ob)[L]) {
+    double v[K + L];
+#pragma unroll
+    for (int x = 0; x < K + L; ++x) v[x] = 0.0;
+    const int nmax = na > nb ? na : nb;
+    for (int it = threadIdx.x; it < nmax; it += NTHR) {
+        const bool oka = it < na, okb = it < nb;
+        const double *ra = oka ? a + (size_t)it * NPART + s0 : b + (size_t)it * NPART + s1;
+        const double *rb = okb ? b + (size_t)it * NPART + s1 : ra;
+        double la[K], lb[L];
+#pragma unroll
+        for (int x = 0; x < K; ++x) la[x] = coh_load(ra + (oka ? x : 0));
+#pragma unroll
+        for (int x = 0; x < L; ++x) lb[x] = coh_load(rb + (okb ? x : 0));
+#pragma unroll
+        for (int x = 0; x < K; ++x) v[x] += oka ? la[x] : -0.0;
+#pragma unroll
+        for (int x = 0; x < L; ++x) v[K + x] += okb ? lb[x] : -0.0;
+    }
+    block_sum<K + L>(v);
+#pragma unroll
+    for (int x = 0; x < K; ++x) oa[x] = v[x];
+#pragma unroll
+    for (int x = 0; x < L; ++x) ob[x] = v[K + x];
+}
+
+// Sums of slots [0, K) and minima of slots [K, K + MN) of n_items records,
+// one pass over the records (the sums in the order of sum_partials).
+template <int K, int MN>
+__device__ __forceinline__ void sum_min_partials(const double *base, int n_items, double (&sums)[K],
+                                                 double (&mins)[MN]) {
+#pragma unroll
+    for (int x = 0; x < K; ++x) sums[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < MN; ++x) mins[x] = INFINITY;
+    for (int it = threadIdx.x; it < n_items; it += NTHR) {
+        double l[K + MN];
+#pragma unroll
+        for (int x = 0; x < K + MN; ++x) l[x] = coh_load(base + (size_t)it * NPART + x);
+#pragma unroll
+        for (int x = 0; x < K; ++x) sums[x] += l[x];
+#pragma unroll
+        for (int x = 0; x < MN; ++x) mins[x] = fmin(mins[x], l[K + x]);
+    }
+    block_sum<K>(sums);
+#pragma unroll
+    for (int x = 0; x < MN; ++x) mins[x] = block_min(mins[x]);
 }
 
 // Arrival at the end of a partial-sum pass, once thread 0 has stored this
@@ -426,8 +476,8 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
     if (mode == 1) {
         double x2[1], S[1];
         const int v0 = tail.ivis_base[c], v1 = tail.ivis_base[c + 1];
-        sum_partials<1>(tail.vispart + (size_t)v0 * NPART, v1 - v0, 0, x2);
-        sum_partials<1>(tail.pp_S + (size_t)c * n_pb * NPART, n_pb, 0, S);
+        sum_partials2<1, 1>(tail.vispart + (size_t)v0 * NPART, v1 - v0, 0, x2,
+                            tail.pp_S + (size_t)c * n_pb * NPART, n_pb, 0, S);
         if (threadIdx.x == 0) {
             const double chi2 = 0.5 * x2[0];
             sc[UVMEM_S_PHI] = chi2 + lam * S[0];
@@ -571,9 +621,9 @@ __global__ __launch_bounds__(NTHR) void k_cg_dir(const R *__restrict__ I, const 
     }
     if (!arrive_last(ctr + c, (unsigned)n_pb)) return;
     double t[5];
-    sum_partials<5>(ppart + (size_t)c * n_pb * NPART, n_pb, 0, t);
-    const double am0 = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 5);
-    const double am1 = min_partials(ppart + (size_t)c * n_pb * NPART, n_pb, 6);
+    double amm[2];
+    sum_min_partials<5, 2>(ppart + (size_t)c * n_pb * NPART, n_pb, t, amm);
+    const double am0 = amm[0], am1 = amm[1];
     const double gg = scal[(size_t)c * UVMEM_NSCAL + UVMEM_S_GNORM2];
     const bool restart = t[0] >= 0.0;
     const bool stop_now = stop || gg == 0.0;
@@ -834,8 +884,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_vis(const VisItem *__restrict__ ite
     const int v0 = ivis_base[img], v1 = ivis_base[img + 1];
     if (!arrive_last(ctr + img, (unsigned)(v1 - v0 + n_pb))) return;
     double ab[2], fh[2];
-    sum_partials<2>(vispart + (size_t)v0 * NPART, v1 - v0, 0, ab);
-    sum_partials<2>(ppart + (size_t)img * n_pb * NPART, n_pb, 0, fh);
+    sum_partials2<2, 2>(vispart + (size_t)v0 * NPART, v1 - v0, 0, ab, ppart + (size_t)img * n_pb * NPART, n_pb, 0,
+                        fh);
     if (threadIdx.x == 0) {
         const double *ch = chan + (size_t)img * CH_N;
         ls_init(ls + (size_t)img * LSS_N, ab[0], ab[1], lam * ch[CH_E1], lam * ch[CH_E2], ch[CH_AMAX],
@@ -949,8 +999,8 @@ __global__ __launch_bounds__(NTHR) void k_cg_update(R *__restrict__ I, const R *
     const int v0 = ivis_base[c], v1 = ivis_base[c + 1];
     if (!arrive_last(ctr + c, (unsigned)(n_pb + v1 - v0))) return;
     double x2[1], S[1];
-    sum_partials<1>(vispart + (size_t)v0 * NPART, v1 - v0, 0, x2);
-    sum_partials<1>(pp_out + (size_t)c * n_pb * NPART, n_pb, 0, S);
+    sum_partials2<1, 1>(vispart + (size_t)v0 * NPART, v1 - v0, 0, x2, pp_out + (size_t)c * n_pb * NPART, n_pb, 0,
+                        S);
     if (threadIdx.x == 0) {
         double *sc = scal + (size_t)c * UVMEM_NSCAL;
         const double chi2 = 0.5 * x2[0];
