@@ -1182,9 +1182,13 @@ int uvmem_cg_run(uvmem_ctx *c, void *I, int iters, double *hist, int use_graph) 
         hipStream_t cap = c->cap_stream;
         // graph launches go to the context's stream, so a replay still runs
         // after the work queued there before it
+        // with one image the gradient pass's last workgroup writes the
+        // history row itself (one launch less per replay)
+        c->hist_in_grad = c->nimg == 1;
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) e = launch_cg_step(c, I, nullptr, cap);
-        if (e == hipSuccess) e = launch_copy_scal(c, nullptr, c->d_iter_ctr, cap);
+        if (e == hipSuccess && !c->hist_in_grad) e = launch_copy_scal(c, nullptr, c->d_iter_ctr, cap);
+        c->hist_in_grad = false;
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;

@@ -227,6 +227,8 @@ struct uvmem_ctx {
     hipStream_t cap_stream = nullptr;           // capture stream of the CG graph (made at finalize)
     long long *d_hist_ptr = nullptr;            // device copy of the cg_run history pointer
     long long *d_iter_ctr = nullptr;
+    bool hist_in_grad = false;                  // set while a one-image CG step is captured: the
+                                                // gradient pass's last workgroup writes the history
     // test hook (UVMEM_TEST_FAIL_ALLOC): index of the finalize allocation
     // that fails, -1 for none; allocations counted so far
     int fail_alloc_at = -1, n_alloc = 0;

@@ -350,6 +350,10 @@ struct GradTail {
     double *scal;
     double *chan;
     double *user;
+    // graph replays of a one-image CG step: the history buffer's address and
+    // the replay counter (the scalars go to row *hist_ctr); null otherwise
+    const long long *hist_ptr;
+    long long *hist_ctr;
 };
 
 template <typename R, int RP, typename PT>
@@ -505,6 +509,14 @@ __global__ __launch_bounds__(NTHR) void k_grad(const PT *__restrict__ gpart, con
         if (sc[UVMEM_S_ALPHA] != 0.0) sc[UVMEM_S_ITER] += 1.0;
         if (tail.user) {
             for (int x = 0; x < UVMEM_NSCAL; ++x) tail.user[(size_t)c * UVMEM_NSCAL + x] = sc[x];
+        }
+        if (tail.hist_ptr) {
+            double *hb = reinterpret_cast<double *>(tail.hist_ptr[0]);
+            const long long t = tail.hist_ctr[0];
+            if (hb) {
+                for (int x = 0; x < UVMEM_NSCAL; ++x) hb[t * UVMEM_NSCAL + x] = sc[x];
+            }
+            tail.hist_ctr[0] = t + 1;
         }
     }
 }
@@ -1064,7 +1076,9 @@ void grad_launch_t(const uvmem_ctx *c, const void *I, void *out, double *ppart, 
     const PT *gp = static_cast<const PT *>(c->d_gpart);
     // gradients (modes 1, 2) follow the region-restricted adjoint and its slots
     const int *slots = (mode == 1 || mode == 2) && c->has_region ? c->d_slot_base_m : c->d_slot_base;
-    const GradTail tail{ctr(c, CTR_GRAD), c->d_vispart, c->d_ivis_base, pp(c, 0), c->d_scal, c->d_chan, user};
+    const bool hist = mode == 2 && c->hist_in_grad;
+    const GradTail tail{ctr(c, CTR_GRAD), c->d_vispart, c->d_ivis_base, pp(c, 0), c->d_scal, c->d_chan, user,
+                        hist ? c->d_hist_ptr : nullptr, hist ? c->d_iter_ctr : nullptr};
     if (c->pix_blk >= 4 * NTHR)
         hipLaunchKernelGGL((k_grad<R, 4, PT>), dim3(pix_grid(c)), dim3(NTHR), 0, st, gp, slots,
                            c->d_ichan_base, CP<R>(c->d_beam), CP<R>(I), P<R>(out), P<R>(c->d_gt), ppart,

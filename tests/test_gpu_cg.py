@@ -82,6 +82,31 @@ def test_graph_replay_equals_eager():
     assert torch.equal(Ia, Ib)
 
 
+def test_graph_replay_equals_eager_several_images():
+    """Cube mode with three channels (one empty): each graph replay writes
+    the same history rows, bit for bit, as the eager steps (with one image
+    the gradient pass writes the history row itself; with several a
+    separate copy follows the step)."""
+    _cuda()
+    flush("graph replay vs eager, three-channel cube fp32")
+    prob = Problem.random(64, [1500, 0, 777], seed=41, lam=0.05)
+    a = prob.context("fp32")
+    b = prob.context("fp32")
+    Ia, Ib = a.image(), b.image()
+    a.cg_init(Ia)
+    b.cg_init(Ib)
+    hb = b.cg_run(Ib, 4, graph=True)
+    torch.cuda.synchronize()
+    for t in range(4):
+        sa = a.cg_step(Ia)
+        assert torch.equal(sa, hb[t]), f"replay {t} scalars"
+    assert torch.equal(Ia, Ib)
+    hb2 = b.cg_run(Ib, 2, graph=True)   # a second run restarts the history rows
+    for t in range(2):
+        sa = a.cg_step(Ia)
+        assert torch.equal(sa, hb2[t]), f"second run, replay {t} scalars"
+
+
 def test_checkpoint_resume_bitwise():
     _cuda()
     flush("checkpoint/resume c1 fp32")
