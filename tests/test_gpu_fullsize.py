@@ -276,29 +276,39 @@ def test_zero_weights_channel():
     assert rel(grad.cpu().numpy(), expect) < 1e-6
 
 
-@pytest.mark.parametrize("n", [2, 2048])
-def test_extreme_image_sizes(n):
-    """Smallest legal image (2 x 2, padded to one tile) and a large 2048^2
-    image with few visibilities: forward and adjoint against the oracle."""
+@pytest.mark.parametrize("n,prec", [(2, "fp32"), (2048, "fp32"), (8192, "fp64"), (8192, "fp32"),
+                                    (8192, "bf16x3"), (8192, "fp16x3")])
+def test_extreme_image_sizes(n, prec):
+    """Smallest legal image (2 x 2, padded to one tile), a 2048^2 image and
+    the largest the library accepts (8192^2, 67 M pixels) with few
+    visibilities: forward and adjoint against the oracle."""
     _cuda()
-    nv = 300 if n > 2 else 40
+    nv = 40 if n == 2 else 300 if n <= 2048 else 160
+    flush(f"extreme image size n={n} {prec} nvis={nv}")
     prob = Problem.random(n, [nv], seed=n, fwhm_px=max(2, n // 2))
-    ctx = prob.context("fp32")
-    img = synth.random_image(n, n)[0].astype(np.float32)
-    V = ctx.forward(torch.tensor(img[None], device="cuda")).cpu().numpy()
+    ctx = prob.context(prec)
+    img = synth.random_image(n, n)[0]
+    I = torch.tensor(img[None], dtype=ctx.dtype, device="cuda")
+    V = ctx.forward(I).cpu().numpy()
+    img64 = I.cpu().numpy()[0].astype(np.float64)
     if n <= 64:
-        ref = prob.oracle_forward(0, img.astype(np.float64))
-        assert rel(V, ref) < TOL["fp32"]
+        ref = prob.oracle_forward(0, img64)
+        assert rel(V, ref) < TOL[prec]
     else:
-        idx = np.arange(0, nv, 7)
+        idx = np.arange(0, nv, 7 if n <= 2048 else 16)
         ch = prob.chans[0]
-        ref = oracle.forward_sel(n, prob.cell, idx, ch["u"], ch["v"], prob.beam(0), img.astype(np.float64))
-        assert rel(V[idx], ref) < TOL["fp32"]
+        ref = oracle.forward_sel(n, prob.cell, idx, ch["u"], ch["v"], prob.beam(0), img64)
+        e = rel(V[idx], ref)
+        flush(f"  forward rel err {e:.2e} over {idx.size} visibilities")
+        assert e < TOL[prec]
     coef = np.random.default_rng(n).standard_normal(nv) + 0j
     G = ctx.adjoint(torch.tensor(coef, dtype=torch.complex128, device="cuda")).cpu().numpy()[0]
     pix = np.arange(0, n * n, max(1, (n * n) // 97))
     ref = prob.oracle_adjoint(0, coef, pix=pix)
-    assert rel(G.ravel()[pix], ref) < TOL["fp32"]
+    e = rel(G.ravel()[pix], ref)
+    flush(f"  adjoint rel err {e:.2e} over {pix.size} pixels")
+    assert e < TOL[prec]
+    ctx.close()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
