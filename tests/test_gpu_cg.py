@@ -82,6 +82,31 @@ def test_graph_replay_equals_eager():
     assert torch.equal(Ia, Ib)
 
 
+def test_graph_replay_without_history_buffer():
+    """cg_run in graph mode with no history buffer (NULL): the replays still
+    advance the image exactly as eager steps do, and a later run with a
+    buffer starts its rows at 0."""
+    _cuda()
+    flush("graph replay without a history buffer, c1 fp32")
+    ds = synth.make_config(1)
+    prob = Problem.from_dataset(ds)
+    a = prob.context("fp32")
+    b = prob.context("fp32")
+    Ia, Ib = a.image(), b.image()
+    a.cg_init(Ia)
+    b.cg_init(Ib)
+    b._call("uvmem_cg_run", b._img(Ib).data_ptr(), 3, None, 1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        a.cg_step(Ia)
+    assert torch.equal(Ia, Ib)
+    hb = b.cg_run(Ib, 2, graph=True)
+    for t in range(2):
+        sa = a.cg_step(Ia)
+        assert torch.equal(sa, hb[t]), t
+    assert torch.equal(Ia, Ib)
+
+
 def test_graph_replay_equals_eager_several_images():
     """Cube mode with three channels (one empty): each graph replay writes
     the same history rows, bit for bit, as the eager steps (with one image
