@@ -55,6 +55,35 @@ def test_cg_trajectory_c1(prec):
     assert abs(phis[0] - ref_phis[0]) < CG_TOL[prec]["first"] * abs(ref_phis[0])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_trajectory_without_entropy(prec):
+    """lambda = 0 (no entropy term: positivity-constrained least squares,
+    phi'' from the chi^2 part alone, so the line search's entropy sums are
+    zero): the c1 trajectory against the oracle's CG, same bars as with the
+    entropy."""
+    _cuda()
+    ds = synth.make_config(1)
+    iters = 12
+    flush(f"cg trajectory c1 lambda=0 {prec} {iters} iterations")
+    prob = Problem.from_dataset(ds)
+    prob.lam = 0.0
+    I_ref, traj = _oracle_cg(prob, 0, iters, None)
+    ctx = prob.context(prec)
+    I = ctx.image()
+    ctx.cg_init(I, init_to_floor=True)
+    hist = ctx.cg_run(I, iters, graph=True).cpu().numpy()
+    phis = hist[:, 0, 0]
+    ref_phis = np.array([t["phi"] for t in traj])
+    n = min(len(traj), iters)
+    e_phi = np.max(np.abs(phis[:n] - ref_phis[:n]) / np.abs(ref_phis[:n]))
+    e_img = rel(I.cpu().numpy()[0], I_ref)
+    flush(f"  {len(traj)} oracle steps; max rel phi {e_phi:.2e}, final image {e_img:.2e}")
+    assert len(traj) == iters
+    assert np.all(np.diff(phis) <= 1e-12 * np.abs(phis[:-1]))
+    assert float(I.min()) >= ds.prior_m * (1 - 1e-7)
+    assert e_phi < CG_TOL[prec]["phi"] and e_img < CG_TOL[prec]["img"]
+
+
 def test_graph_replay_equals_eager():
     """Each graph replay, with eager work and synchronisation in between,
     gives the same bits as the eager step."""
