@@ -583,7 +583,8 @@ def main():
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (no multi-GPU path); --gpus {args.gpus} is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
